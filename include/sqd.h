@@ -1,0 +1,241 @@
+/*
+ * libsqd -- MI355X (gfx950) hot path of sample-based quantum diagonalization.
+ *
+ * The library evaluates sigma = H c over the product space S = S_alpha x S_beta
+ * of sampled alpha and beta occupation strings (Sec. I: configurations as
+ * bit-strings; Sec. IV: the alpha x beta index space and the three task types
+ * of the Slater-Condon rules), runs a Davidson eigensolver for the lowest root
+ * entirely on the GPU (Sec. III names moving the whole Davidson iteration to
+ * the device as the alternative to offloading only the product; Sec. VI lists
+ * its steps), and forms reduced density matrices for energy gradients.
+ *
+ * Hamiltonian (real orbitals, chemists' notation; the paper names the
+ * second-quantized Hamiltonian and the Slater-Condon rules, Sec. I-II):
+ *   H = ecore + sum_pq h_pq E_pq + 1/2 sum_pqrs (pq|rs) sum_st a+_ps a+_rt a_st a_qs
+ * Determinants: |Ia Ib> = prod_{p in Ia, asc} a+_pa prod_{q in Ib, asc} a+_qb |0>
+ * (all alpha creators left of all beta creators).
+ *
+ * Conventions shared by every entry point:
+ *  - a string is a uint64 with bit p set when orbital p is occupied
+ *    (norb <= 64, Sec. V-A / the bit_length discussion of Sec. IV-A);
+ *  - string lists are strictly ascending; the vector index of determinant
+ *    (ia, ib) is d = ia * nb + ib (alpha-major, the ia-outer / ib-inner loop
+ *    order of Sec. IV-A);
+ *  - pointers named *_dev are device pointers on the context's device,
+ *    owned by the caller; pointers named *_host are host pointers;
+ *  - work is enqueued on the context's stream; calls return after enqueueing
+ *    unless stated otherwise;
+ *  - every call returns an int status: 0 = SQD_OK, > 0 = warning, < 0 = error.
+ *    No exception crosses the ABI.  sqd_last_error() gives the message of the
+ *    last failing call on a context.
+ *  - a context is not thread-safe; distinct contexts may be used concurrently.
+ */
+#ifndef SQD_H
+#define SQD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define SQD_OK 0
+#define SQD_NOT_CONVERGED 1     /* warning: outputs hold the best Ritz pair   */
+#define SQD_E_INVALID_ARG (-1)  /* null pointer, bad size or option           */
+#define SQD_E_UNSORTED (-2)     /* string list not strictly ascending          */
+#define SQD_E_POPCOUNT (-3)     /* a string has the wrong electron count       */
+#define SQD_E_NORB (-4)         /* norb outside [1, 64] or a bit >= norb       */
+#define SQD_E_ASYMMETRIC (-5)   /* integrals lack the required symmetry        */
+#define SQD_E_OOM (-6)          /* device allocation failed                    */
+#define SQD_E_HIP (-7)          /* HIP runtime error                           */
+#define SQD_E_STATE (-8)        /* call order violated (e.g. no Hamiltonian)   */
+#define SQD_E_LIMIT (-9)        /* size beyond a documented library limit      */
+
+/* ---- sigma term selection (Sec. IV: the three task types) -------------- */
+#define SQD_TERM_DIAG 1u  /* H_II c_I                                        */
+#define SQD_TERM_AA 2u    /* pairs differing only in the alpha string          */
+#define SQD_TERM_BB 4u    /* pairs differing only in the beta string           */
+#define SQD_TERM_AB 8u    /* one alpha and one beta excitation                 */
+#define SQD_TERM_ALL 15u
+
+/* arithmetic of the off-diagonal sigma terms */
+#define SQD_FP64 0
+#define SQD_FP32 1        /* FP32 storage and accumulation; the diagonal term
+                             and the output stay FP64                          */
+
+/* alpha-beta algorithm */
+#define SQD_AB_AUTO 0
+#define SQD_AB_DIRECT 1   /* LDS-staged gather over alpha x beta singles       */
+#define SQD_AB_KH 2       /* Knowles-Handy: D build, MFMA GEMM with (pq|rs), gather */
+
+/* Davidson precision modes */
+#define SQD_DAV_FP64 0
+#define SQD_DAV_MIXED 1   /* FP32 sigma until ||r|| < switch_tol, then FP64 refinement */
+
+#define SQD_MMAX 32       /* largest Davidson subspace                         */
+#define SQD_HIST 512      /* residual history kept in the report               */
+
+/* table kinds for sqd_get_tables */
+#define SQD_SINGLES 0
+#define SQD_DOUBLES 1
+
+/* tuning keys for sqd_set_tuning */
+#define SQD_TUNE_SS_ROWS 0     /* rows staged per same-spin workgroup: 1,2,4,8 (0 = auto) */
+#define SQD_TUNE_AB_CHUNK 1    /* alpha sources staged per alpha-beta pass: 1,2,4,8 (0 = auto) */
+#define SQD_TUNE_AB_WAVES 2    /* waves per alpha-beta workgroup: 4, 8 or 16 (0 = auto) */
+#define SQD_TUNE_SS_WAVES 3    /* waves per same-spin workgroup: 4, 8 or 16 (0 = auto) */
+#define SQD_TUNE_AB_PATH 4     /* default alpha-beta path for SQD_AB_AUTO */
+#define SQD_TUNE_KH_TILE 5     /* beta targets per KH tile: 32 or 64 (0 = auto) */
+#define SQD_TUNE_COUNT 6
+
+typedef struct sqd_ctx sqd_ctx;      /* opaque, library-owned */
+typedef struct sqd_space sqd_space;  /* opaque, library-owned */
+
+typedef struct {
+    int norb, nalpha, nbeta;
+    int64_t na, nb, dim;
+    int64_t nnz_single[2];   /* [0] alpha, [1] beta: in-set single excitations  */
+    int64_t nnz_double[2];   /* in-set double excitations                       */
+    int64_t conn_per_sigma;  /* connected (I,J) pairs visited by one full sigma,
+                                the diagonal included                           */
+    int64_t conn_terms[4];   /* the same split as DIAG, AA, BB, AB              */
+    int64_t device_bytes;    /* device memory held by the space                 */
+} sqd_space_info_t;
+
+typedef struct {
+    double tol;                  /* stop when ||H x - theta x||_2 <= tol, ||x|| = 1 */
+    int max_iter;                /* iterations (sigma products) cap              */
+    int m_max;                   /* subspace size before collapse, 2..SQD_MMAX   */
+    int mode;                    /* SQD_DAV_FP64 or SQD_DAV_MIXED                */
+    double switch_tol;           /* mixed: leave FP32 sigma when ||r|| < switch_tol */
+    int ab_path;                 /* SQD_AB_*                                      */
+    const double* guess_noise_dev; /* optional (dim): start = e_argmin(H_II) + noise */
+    const double* guess_dev;       /* optional (dim): explicit start vector; overrides */
+    int check_every;             /* host polls the device convergence flag every k
+                                    iterations (>= 1); iterations past convergence
+                                    are skipped on the device                    */
+} sqd_davidson_opts;
+
+typedef struct {
+    int iterations;              /* Davidson iterations (one sigma each)          */
+    int iterations_fp32;         /* of which with FP32 sigma                      */
+    int switch_iter;             /* iteration at which FP64 refinement began (-1) */
+    int converged;               /* 1 if ||r|| <= tol                             */
+    int status;                  /* device end state: 1 converged, 2 stalled, 3 cap */
+    int nhist;
+    double energy;               /* lowest Ritz value (includes ecore)            */
+    double residual;             /* final ||r||_2                                 */
+    double seconds;              /* wall time of the solve, diagonal included     */
+    double residual_history[SQD_HIST];
+    double energy_history[SQD_HIST];
+} sqd_report;
+
+/* ---- context ----------------------------------------------------------- */
+
+/* Create a context on HIP device `device`; all work is enqueued on
+ * `hip_stream` (a hipStream_t, or NULL for the default stream).  The stream
+ * must outlive the context. */
+int sqd_create(int device, void* hip_stream, sqd_ctx** out);
+void sqd_destroy(sqd_ctx* ctx);
+/* Message of the last failing call on ctx (never NULL; empty if none). */
+const char* sqd_last_error(const sqd_ctx* ctx);
+/* Library version string. */
+const char* sqd_version(void);
+/* Block the host until all work enqueued by ctx has finished. */
+int sqd_synchronize(sqd_ctx* ctx);
+/* Set a tuning parameter (SQD_TUNE_*); value 0 restores the automatic choice. */
+int sqd_set_tuning(sqd_ctx* ctx, int key, int value);
+int sqd_get_tuning(const sqd_ctx* ctx, int key, int* value);
+
+/* ---- Hamiltonian (Sec. II: integrals provided in an input file; Sec. V-A:
+ * integrals held as raw arrays indexed by orbital pair) ------------------ */
+
+/* Copy the integrals (host pointers) to the device.
+ *   h   : norb*norb, row-major, h[p*norb+q] = h_pq
+ *   eri : norb^4, (pq|rs) at ((p*norb+q)*norb+r)*norb+s
+ * Checks h = h^T and (pq|rs) = (qp|rs) = (pq|sr) = (rs|pq) to
+ * 1e-12 * max|value| (else SQD_E_ASYMMETRIC).  Spaces built on ctx pick up
+ * new integrals at their next use. */
+int sqd_set_hamiltonian(sqd_ctx* ctx, int norb, const double* h_host,
+                        const double* eri_host, double ecore);
+
+/* ---- space: strings and excitation tables (Sec. IV-A configuration cache,
+ * Sec. V-A flattened excitation lists) ---------------------------------- */
+
+/* Validate the strings (strictly ascending, popcount == nalpha / nbeta, no bit
+ * >= norb), upload them and build on the device the per-string single and
+ * double excitation tables with fermionic signs.  astr_host / bstr_host are
+ * host arrays of na / nb strings.  Requires sqd_set_hamiltonian first (for
+ * norb).  Limits: na, nb <= 524287; na*nb < 2^40.  The space is owned by the
+ * library; free it with sqd_space_free before destroying ctx. */
+int sqd_build_space(sqd_ctx* ctx, int nalpha, int nbeta,
+                    const uint64_t* astr_host, int64_t na,
+                    const uint64_t* bstr_host, int64_t nb, sqd_space** out);
+void sqd_space_free(sqd_space* space);
+int sqd_space_info(const sqd_space* space, sqd_space_info_t* out);
+
+/* Copy one table to the host in canonical order: rows by source string,
+ * entries by target index ascending.  spin 0 = alpha, 1 = beta; kind
+ * SQD_SINGLES or SQD_DOUBLES.  offsets_host has n+1 int64 slots (CSR),
+ * entries_host has nnz uint64 slots packed as
+ *   singles: target | i << 32 | a << 38 | negative << 63
+ *   doubles: target | i << 32 | j << 38 | a << 44 | b << 50 | negative << 63
+ * where i (< j) are annihilated in the source, a (< b) created, and the sign is
+ * <target| a+_a a_i |source> or <target| a+_a a+_b a_j a_i |source>.
+ * Synchronous. */
+int sqd_get_tables(const sqd_space* space, int spin, int kind,
+                   int64_t* offsets_host, uint64_t* entries_host);
+
+/* ---- products ---------------------------------------------------------- */
+
+/* diag_dev[d] = H_dd for every determinant (dim doubles). */
+int sqd_diag(sqd_ctx* ctx, const sqd_space* space, double* diag_dev);
+
+/* sigma_dev = (selected terms of H) c_dev, both dim doubles, distinct buffers.
+ * precision SQD_FP64 or SQD_FP32 (off-diagonal terms in FP32 with FP32
+ * accumulation; the diagonal term and the result in FP64).  terms_mask is a
+ * non-zero OR of SQD_TERM_*.  ab_path selects the alpha-beta algorithm. */
+int sqd_sigma(sqd_ctx* ctx, const sqd_space* space, const double* c_dev,
+              double* sigma_dev, int precision, unsigned terms_mask, int ab_path);
+
+/* ---- eigensolver (Sec. I, Sec. VI: Davidson for the lowest eigenpair) --- */
+
+/* Fill opts with the defaults: tol 1e-8, max_iter 200, m_max 24, FP64,
+ * switch_tol 1e-4, AUTO path, no guess, check_every 4. */
+void sqd_davidson_default_opts(sqd_davidson_opts* opts);
+
+/* Lowest eigenpair of H restricted to S.  energy_host receives the energy
+ * (ecore included); vec_dev (dim doubles, caller-owned) the normalised
+ * eigenvector with its largest-magnitude entry positive.  rep (optional)
+ * receives the report.  Synchronous.  Returns SQD_NOT_CONVERGED (warning) if
+ * the tolerance was not reached; the outputs then hold the last Ritz pair. */
+int sqd_davidson(sqd_ctx* ctx, const sqd_space* space, const sqd_davidson_opts* opts,
+                 double* energy_host, double* vec_dev, sqd_report* rep);
+
+/* Many independent spaces built on the same context (same integrals) solved
+ * together: one persistent launch per sigma term over a work queue of
+ * (space, tile) units ordered longest-first, and the Davidson iteration of all
+ * spaces captured once in a hipGraph and replayed.  energies_host[nspace],
+ * vecs_dev[nspace] (each that space's dim), reps[nspace] optional.
+ * Synchronous. */
+int sqd_davidson_batched(sqd_ctx* ctx, int nspace, const sqd_space* const* spaces,
+                         const sqd_davidson_opts* opts, double* energies_host,
+                         double* const* vecs_dev, sqd_report* reps);
+
+/* ---- reduced density matrices (Hellmann-Feynman gradients) ------------- */
+
+/* For a normalised c_dev (dim doubles):
+ *   rdm1_dev[p*n+q]           = sum_s <c| a+_ps a_qs |c>
+ *   rdm2_dev[((p*n+q)*n+r)*n+s] = sum_st <c| a+_ps a+_rt a_st a_qs |c>
+ * so that E = ecore + sum h.rdm1 + 1/2 sum (pq|rs) rdm2, dE/dh_pq = rdm1_pq and
+ * dE/d(pq|rs) = rdm2_pqrs / 2 (per element).  rdm1_dev has norb^2 doubles,
+ * rdm2_dev norb^4 (NULL skips it).  The alpha-beta part of rdm2 is a
+ * D_alpha^T D_beta product over all determinants on FP64 MFMA. */
+int sqd_rdm(sqd_ctx* ctx, const sqd_space* space, const double* c_dev,
+            double* rdm1_dev, double* rdm2_dev);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SQD_H */

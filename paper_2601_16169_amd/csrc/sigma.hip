@@ -1,0 +1,509 @@
+// sigma = H c on the product space (Sec. II matrix-free product; Sec. IV the
+// three task types of the Slater-Condon rules: alpha-alpha, beta-beta and one
+// alpha plus one beta excitation).
+//
+// Terms and kernels (all owner-computes, no atomics, deterministic):
+//   DIAG  H_II c_I, fused into the beta-beta kernel's epilogue (FP64 always).
+//   BB    same-spin kernel on C (rows = alpha strings, columns = beta strings):
+//         sigma[ia, jb] += sum over beta singles/doubles (jb <- kb) of
+//         H^bb(jb, kb; Ia) c[ia, kb].  A workgroup stages R rows of C in LDS
+//         (layout [column][row], plus a zero slot for padding) and the
+//         cross-spin term W_a[pq] = sum_{k in Ia} (pq|kk) of those rows; each
+//         lane owns one target column of a 64-row slice of the sliced table
+//         and walks its entries (coalesced 64-wide table reads).
+//   AA    the same kernel on C^T (one tiled transpose each way), i.e. the
+//         beta-beta machinery applied with the spins swapped.
+//   AB    sigma[ia', jb'] += sum_{alpha singles ia' <- ia (pair ai, s_a)}
+//         sum_{beta singles jb' <- jb (pair bj, s_b)} s_a s_b (ai|bj) c[ia, jb]:
+//         a workgroup per target alpha row stages KC source rows of C and the
+//         KC rows s_a (ai|..) of the (pq|rs) matrix in LDS (interleaved so one
+//         lane reads all KC values of a column with wide loads), lanes own
+//         beta targets and accumulate in registers across all alpha sources.
+#include "sqd_internal.h"
+
+namespace {
+
+inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+template <typename T> struct vec2;
+template <> struct vec2<double> { using type = double2; };
+template <> struct vec2<float> { using type = float2; };
+
+// ---------------------------------------------------------------- diagonal
+// ua[ia*norb + q] = sum_{p in Ia} (pp|qq)
+__global__ void k_ua(const uint64_t* __restrict__ astr, int64_t na, int norb, const double* __restrict__ jdiag,
+                     double* __restrict__ ua) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= na * norb) return;
+    const int64_t ia = k / norb;
+    const int q = (int)(k % norb);
+    double acc = 0.0;
+    for (uint64_t x = astr[ia]; x; x &= x - 1) acc += jdiag[(__ffsll((unsigned long long)x) - 1) * norb + q];
+    ua[k] = acc;
+}
+
+// H_II = ecore + E_a(Ia) + E_b(Ib) + sum_{p in Ia, q in Ib} (pp|qq)
+__global__ void k_diag(const double* __restrict__ ea, const double* __restrict__ eb, const double* __restrict__ ua,
+                       const uint64_t* __restrict__ bstr, int64_t na, int64_t nb, int norb, double ecore,
+                       double* __restrict__ diag) {
+    const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= na * nb) return;
+    const int64_t ia = d / nb, ib = d % nb;
+    const double* u = ua + ia * norb;
+    double acc = ecore + ea[ia] + eb[ib];
+    for (uint64_t x = bstr[ib]; x; x &= x - 1) acc += u[__ffsll((unsigned long long)x) - 1];
+    diag[d] = acc;
+}
+
+// ---------------------------------------------------------------- transposes
+// out[c][r] (=|+=) in[r][c], in is rows x cols; 64x64 tiles through LDS.
+template <typename TI, typename TO, bool ADD>
+__global__ void __launch_bounds__(256) k_transpose(const TI* __restrict__ in, TO* __restrict__ out, int64_t rows,
+                                                   int64_t cols, const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    __shared__ TI tile[64][65];
+    const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int k = ty; k < 64; k += 4) {
+        const int64_t r = r0 + k, c = c0 + tx;
+        if (r < rows && c < cols) tile[k][tx] = in[r * cols + c];
+    }
+    __syncthreads();
+    for (int k = ty; k < 64; k += 4) {
+        const int64_t c = c0 + k, r = r0 + tx;
+        if (r < rows && c < cols) {
+            TO v = (TO)tile[tx][k];
+            if (ADD) v += out[c * rows + r];
+            out[c * rows + r] = v;
+        }
+    }
+}
+
+template <typename TI, typename TO>
+__global__ void k_convert(const TI* __restrict__ in, TO* __restrict__ out, int64_t n, const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) out[k] = (TO)in[k];
+}
+
+template <typename T>
+__global__ void k_fill(T* __restrict__ out, int64_t n, T v, const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) out[k] = v;
+}
+
+// sigma = (diag ? diag*c : 0) + (accumulate ? sigma : 0) + (double)s32
+__global__ void k_combine(const double* __restrict__ diag, const double* __restrict__ c,
+                          const float* __restrict__ s32, double* __restrict__ sigma, int64_t n,
+                          const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    double v = s32 ? (double)s32[k] : 0.0;
+    if (diag) v += diag[k] * c[k];
+    sigma[k] = v;
+}
+
+__global__ void k_diag_apply(const double* __restrict__ diag, const double* __restrict__ c, double* __restrict__ s,
+                             int64_t n, int accumulate, const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    double v = diag[k] * c[k];
+    if (accumulate) v += s[k];
+    s[k] = v;
+}
+
+// ---------------------------------------------------------------- same-spin
+// X: nrows x ncols (row = string of the other spin, column = string of the
+// excited spin).  Y (=|+=) sum over the column spin's singles and doubles.
+// LDS: xs[(ncols+1)*R] as [col][r]; ws[norb2*R] as [pq][r].
+template <typename T, int R>
+__global__ void __launch_bounds__(1024)
+k_same_spin(const T* __restrict__ X, T* __restrict__ Y, int64_t nrows, int64_t ncols,
+            const int* __restrict__ perm, int nslices, const int* __restrict__ sl_s_off,
+            const int* __restrict__ sl_d_off, const uint32_t* __restrict__ s_pk, const T* __restrict__ s_val,
+            const int* __restrict__ d_nbr, const T* __restrict__ d_val, const uint64_t* __restrict__ row_str,
+            const T* __restrict__ jk, int norb, const double* __restrict__ diag, int accumulate,
+            const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    T* xs = reinterpret_cast<T*>(lds_raw);
+    const int norb2 = norb * norb;
+    T* ws = xs + (ncols + 1) * R;
+    const int64_t row0 = (int64_t)blockIdx.x * R;
+    const int nthr = blockDim.x;
+    const int tid = threadIdx.x;
+    // stage R rows of X, transposed to [col][r]
+    for (int64_t idx = tid; idx < (int64_t)R * ncols; idx += nthr) {
+        const int r = (int)(idx / ncols);
+        const int64_t col = idx - (int64_t)r * ncols;
+        const int64_t row = row0 + r;
+        xs[col * R + r] = (row < nrows) ? X[row * ncols + col] : (T)0;
+    }
+    if (tid < R) xs[ncols * R + tid] = (T)0;
+    // cross-spin term of the staged rows: ws[pq][r] = sum_{k in row string} (pq|kk)
+    for (int idx = tid; idx < R * norb2; idx += nthr) {
+        const int r = idx / norb2, pq = idx - r * norb2;
+        const int64_t row = row0 + r;
+        T acc = (T)0;
+        if (row < nrows)
+            for (uint64_t x = row_str[row]; x; x &= x - 1)
+                acc += jk[(__ffsll((unsigned long long)x) - 1) * norb2 + pq];
+        ws[pq * R + r] = acc;
+    }
+    __syncthreads();
+    const int wave = tid >> 6, lane = tid & 63, nw = nthr >> 6;
+    for (int sl = wave; sl < nslices; sl += nw) {
+        T acc[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = (T)0;
+        const int s0 = sl_s_off[sl], s1 = sl_s_off[sl + 1];
+        for (int k = s0; k < s1; ++k) {
+            const int64_t pos = (int64_t)k * 64 + lane;
+            const uint32_t e = s_pk[pos];
+            const T v = s_val[pos];
+            const int nbr = (int)(e & SQD_NBR_MASK);
+            const int pair = (int)((e >> SQD_PAIR_SHIFT) & SQD_PAIR_MASK);
+            const T* xr = xs + (int64_t)nbr * R;
+            const T* wr = ws + pair * R;
+            const bool neg = (e >> 31) != 0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const T w = wr[r];
+                acc[r] += (v + (neg ? -w : w)) * xr[r];
+            }
+        }
+        const int d0 = sl_d_off[sl], d1 = sl_d_off[sl + 1];
+        for (int k = d0; k < d1; ++k) {
+            const int64_t pos = (int64_t)k * 64 + lane;
+            const int nbr = d_nbr[pos];
+            const T v = d_val[pos];
+            const T* xr = xs + (int64_t)nbr * R;
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r] += v * xr[r];
+        }
+        const int t = perm[sl * 64 + lane];
+        if (t < ncols) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int64_t row = row0 + r;
+                if (row < nrows) {
+                    const int64_t o = row * ncols + t;
+                    T val = acc[r];
+                    if (diag) val += (T)(diag[o] * (double)xs[(int64_t)t * R + r]);
+                    if (accumulate) val += Y[o];
+                    Y[o] = val;
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- alpha-beta
+// One workgroup per target alpha row ia' (blockIdx.x) and group of beta slices
+// (blockIdx.y).  LDS: cs[(nb+1)*KC] as [col][k]; vs[norb2*KC] as [pq][k].
+template <typename T, int KC, int MAXJ>
+__global__ void __launch_bounds__(1024)
+k_ab_direct(const T* __restrict__ C, T* __restrict__ S, int64_t na, int64_t nb, const int* __restrict__ a_off,
+            const uint32_t* __restrict__ a_pk, const int* __restrict__ bperm, int nbslices,
+            const int* __restrict__ bsl_off, const uint32_t* __restrict__ bs_pk, const T* __restrict__ V, int norb,
+            const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    T* cs = reinterpret_cast<T*>(lds_raw);
+    const int norb2 = norb * norb;
+    T* vs = cs + (nb + 1) * KC;
+    const int64_t ia = blockIdx.x;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int wave = tid >> 6, lane = tid & 63, nw = nthr >> 6;
+    const int slice_base = blockIdx.y * nw * MAXJ;
+    const int a0 = a_off[ia], a1 = a_off[ia + 1];
+    T acc[MAXJ];
+#pragma unroll
+    for (int j = 0; j < MAXJ; ++j) acc[j] = (T)0;
+    for (int k0 = a0; k0 < a1; k0 += KC) {
+        __syncthreads();
+        for (int64_t idx = tid; idx < (int64_t)KC * nb; idx += nthr) {
+            const int k = (int)(idx / nb);
+            const int64_t col = idx - (int64_t)k * nb;
+            T v = (T)0;
+            if (k0 + k < a1) {
+                const int64_t src = a_pk[k0 + k] & SQD_NBR_MASK;
+                v = C[src * nb + col];
+            }
+            cs[col * KC + k] = v;
+        }
+        if (tid < KC) cs[nb * KC + tid] = (T)0;
+        for (int idx = tid; idx < KC * norb2; idx += nthr) {
+            const int k = idx / norb2, pq = idx - k * norb2;
+            T v = (T)0;
+            if (k0 + k < a1) {
+                const uint32_t e = a_pk[k0 + k];
+                const int pair = (int)((e >> SQD_PAIR_SHIFT) & SQD_PAIR_MASK);
+                v = V[(int64_t)pair * norb2 + pq];
+                if (e >> 31) v = -v;
+            }
+            vs[pq * KC + k] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < MAXJ; ++j) {
+            const int sl = slice_base + j * nw + wave;
+            if (sl < nbslices) {
+                const int c0 = bsl_off[sl], c1 = bsl_off[sl + 1];
+                T a = acc[j];
+                for (int col = c0; col < c1; ++col) {
+                    const uint32_t e = bs_pk[(int64_t)col * 64 + lane];
+                    const int nbr = (int)(e & SQD_NBR_MASK);
+                    const int pair = (int)((e >> SQD_PAIR_SHIFT) & SQD_PAIR_MASK);
+                    const T* cr = cs + (int64_t)nbr * KC;
+                    const T* vr = vs + pair * KC;
+                    T t = (T)0;
+#pragma unroll
+                    for (int k = 0; k < KC; ++k) t += vr[k] * cr[k];
+                    a += (e >> 31) ? -t : t;
+                }
+                acc[j] = a;
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < MAXJ; ++j) {
+        const int sl = slice_base + j * nw + wave;
+        if (sl < nbslices) {
+            const int tb = bperm[sl * 64 + lane];
+            if (tb < nb) {
+                const int64_t o = ia * nb + tb;
+                S[o] += acc[j];
+            }
+        }
+    }
+}
+
+constexpr int kAbMaxJ = 8;
+
+// Raise a kernel's dynamic-LDS limit once per kernel (largest size seen).
+template <typename F>
+void set_lds(F f, int bytes) {
+    static std::vector<std::pair<const void*, int>> seen;
+    const void* key = reinterpret_cast<const void*>(f);
+    for (auto& kv : seen)
+        if (kv.first == key) {
+            if (kv.second >= bytes) return;
+            kv.second = bytes;
+            hipFuncSetAttribute(key, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+            return;
+        }
+    seen.emplace_back(key, bytes);
+    hipFuncSetAttribute(key, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+int pick_rows(sqd_ctx* ctx, int64_t nrows, int64_t ncols, int norb, size_t es) {
+    const int forced = ctx->tune[SQD_TUNE_SS_ROWS];
+    const int cands[4] = {8, 4, 2, 1};
+    for (int R : cands) {
+        if (forced && R != forced) continue;
+        const size_t lds = ((size_t)(ncols + 1) * R + (size_t)norb * norb * R) * es;
+        if (lds > (size_t)ctx->max_lds) continue;
+        if (!forced && R > 1 && (nrows + R - 1) / R < ctx->num_cu) continue;
+        return R;
+    }
+    return 0;
+}
+
+int pick_chunk(sqd_ctx* ctx, int64_t nb, int norb, size_t es) {
+    const int forced = ctx->tune[SQD_TUNE_AB_CHUNK];
+    const int cands[4] = {8, 4, 2, 1};
+    for (int K : cands) {
+        if (forced && K != forced) continue;
+        const size_t lds = ((size_t)(nb + 1) + (size_t)norb * norb) * K * es;
+        if (lds <= (size_t)ctx->max_lds) return K;
+    }
+    return 0;
+}
+
+template <typename T>
+int launch_same_spin(sqd_ctx* ctx, const T* X, T* Y, int64_t nrows, int64_t ncols, const spin_tables& col,
+                     const spin_tables& row, const T* jk, int norb, const double* diag, int accumulate,
+                     const int* skip) {
+    const size_t es = sizeof(T);
+    const int R = pick_rows(ctx, nrows, ncols, norb, es);
+    if (R == 0) return sqd_fail(ctx, SQD_E_LIMIT, "same-spin row does not fit in LDS (too many strings)");
+    int nw = ctx->tune[SQD_TUNE_SS_WAVES] ? ctx->tune[SQD_TUNE_SS_WAVES] : 8;
+    const size_t lds = ((size_t)(ncols + 1) * R + (size_t)norb * norb * R) * es;
+    const dim3 grid(nblk(nrows, R)), block(64 * nw);
+    const T* sv = nullptr; const T* dv = nullptr;
+    if constexpr (sizeof(T) == 8) { sv = (const T*)col.sell_s_v64; dv = (const T*)col.sell_d_v64; }
+    else { sv = (const T*)col.sell_s_v32; dv = (const T*)col.sell_d_v32; }
+#define SQD_SS_LAUNCH(RR)                                                                                    \
+    case RR:                                                                                                 \
+        set_lds(k_same_spin<T, RR>, (int)lds);                                                               \
+        hipLaunchKernelGGL((k_same_spin<T, RR>), grid, block, lds, ctx->stream, X, Y, nrows, ncols,         \
+                           col.perm_ss, col.nslices, col.sl_s_off, col.sl_d_off, col.sell_s_pk, sv,        \
+                           col.sell_d_nbr, dv, row.str, jk, norb, diag, accumulate, skip);                  \
+        break;
+    switch (R) {
+        SQD_SS_LAUNCH(1)
+        SQD_SS_LAUNCH(2)
+        SQD_SS_LAUNCH(4)
+        SQD_SS_LAUNCH(8)
+    }
+#undef SQD_SS_LAUNCH
+    SQD_HIP(ctx, hipGetLastError());
+    return SQD_OK;
+}
+
+template <typename T>
+int launch_ab_direct(sqd_ctx* ctx, const sqd_space* sp, const T* C, T* S, const T* V, const int* skip) {
+    const spin_tables& A = sp->sp[0];
+    const spin_tables& B = sp->sp[1];
+    const size_t es = sizeof(T);
+    const int KC = pick_chunk(ctx, B.n, sp->norb, es);
+    if (KC == 0) return sqd_fail(ctx, SQD_E_LIMIT, "alpha-beta source row does not fit in LDS");
+    int nw = ctx->tune[SQD_TUNE_AB_WAVES] ? ctx->tune[SQD_TUNE_AB_WAVES] : 8;
+    // fewer waves when there are few slices
+    while (nw > 4 && (int64_t)nw * 2 > B.nslices && ctx->tune[SQD_TUNE_AB_WAVES] == 0) nw >>= 1;
+    const int groups = (B.nslices + nw * kAbMaxJ - 1) / (nw * kAbMaxJ);
+    const size_t lds = ((size_t)(B.n + 1) + (size_t)sp->norb * sp->norb) * KC * es;
+    const dim3 grid((unsigned)A.n, (unsigned)groups), block(64 * nw);
+#define SQD_AB_LAUNCH(KK)                                                                                    \
+    case KK:                                                                                                 \
+        set_lds(k_ab_direct<T, KK, kAbMaxJ>, (int)lds);                                                      \
+        hipLaunchKernelGGL((k_ab_direct<T, KK, kAbMaxJ>), grid, block, lds, ctx->stream, C, S, A.n, B.n,   \
+                           A.s_off, A.s_pk, B.perm_ab, B.nslices, B.sl_ab_off, B.sell_ab_pk, V, sp->norb,  \
+                           skip);                                                                            \
+        break;
+    switch (KC) {
+        SQD_AB_LAUNCH(1)
+        SQD_AB_LAUNCH(2)
+        SQD_AB_LAUNCH(4)
+        SQD_AB_LAUNCH(8)
+    }
+#undef SQD_AB_LAUNCH
+    SQD_HIP(ctx, hipGetLastError());
+    return SQD_OK;
+}
+
+}  // namespace
+
+int sqd_ensure_diag(sqd_ctx* ctx, sqd_space* sp) {
+    int rc = sqd_build_values(ctx, sp);
+    if (rc) return rc;
+    if (sp->diag_version == ctx->ham_version) return SQD_OK;
+    const spin_tables& A = sp->sp[0];
+    const spin_tables& B = sp->sp[1];
+    if (!sp->diag) {
+        if ((rc = sqd_alloc(ctx, (void**)&sp->diag, sizeof(double) * (sp->dim + 1), &sp->bytes))) return rc;
+        if ((rc = sqd_alloc(ctx, (void**)&sp->ua, sizeof(double) * (A.n * sp->norb + 1), &sp->bytes))) return rc;
+    }
+    hipLaunchKernelGGL(k_ua, dim3(nblk(A.n * sp->norb, 256)), dim3(256), 0, ctx->stream, A.str, A.n, sp->norb,
+                       ctx->jdiag, sp->ua);
+    hipLaunchKernelGGL(k_diag, dim3(nblk(sp->dim, 256)), dim3(256), 0, ctx->stream, A.e_same, B.e_same, sp->ua,
+                       B.str, A.n, B.n, sp->norb, ctx->ecore, sp->diag);
+    SQD_HIP(ctx, hipGetLastError());
+    sp->diag_version = ctx->ham_version;
+    return SQD_OK;
+}
+
+int sqd_sigma_auto_path(sqd_ctx* ctx, const sqd_space* sp, int precision) {
+    (void)sp; (void)precision;
+    if (ctx->tune[SQD_TUNE_AB_PATH]) return ctx->tune[SQD_TUNE_AB_PATH];
+    return SQD_AB_DIRECT;
+}
+
+// Context scratch (grown on demand): FP64 path 2*dim doubles, FP32 path 4*dim floats.
+static int space_scratch_get(sqd_ctx* ctx, sqd_space* sp, size_t bytes, void** out) {
+    (void)sp;
+    void* p = sqd_ctx_scratch(ctx, bytes, nullptr);
+    if (!p) return sqd_fail(ctx, SQD_E_OOM, "scratch allocation failed (" + std::to_string(bytes) + " bytes)");
+    *out = p;
+    return SQD_OK;
+}
+
+int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma, int precision, unsigned mask,
+                   int ab_path, const float* c32_in, const int* skip) {
+    int rc = sqd_ensure_diag(ctx, sp);
+    if (rc) return rc;
+    const spin_tables& A = sp->sp[0];
+    const spin_tables& B = sp->sp[1];
+    const int64_t na = A.n, nb = B.n, dim = sp->dim;
+    const int norb = sp->norb;
+    if (ab_path == SQD_AB_AUTO) ab_path = sqd_sigma_auto_path(ctx, sp, precision);
+    const double* diag = (mask & SQD_TERM_DIAG) ? sp->diag : nullptr;
+    const unsigned g = nblk(dim, 256);
+    const dim3 tgrid(nblk(nb, 64), nblk(na, 64)), tgridT(nblk(na, 64), nblk(nb, 64));
+    if (precision == SQD_FP64) {
+        void* scr = nullptr;
+        if ((rc = space_scratch_get(ctx, sp, sizeof(double) * 2 * (dim + 64), &scr))) return rc;
+        double* Ct = (double*)scr;
+        double* Yt = Ct + dim + 64;
+        bool written = false;
+        if (mask & SQD_TERM_AA) {
+            hipLaunchKernelGGL((k_transpose<double, double, false>), tgrid, dim3(256), 0, ctx->stream, c, Ct, na, nb,
+                               skip);
+            if ((rc = launch_same_spin<double>(ctx, Ct, Yt, nb, na, A, B, ctx->jk64, norb, nullptr, 0, skip))) return rc;
+            hipLaunchKernelGGL((k_transpose<double, double, false>), tgridT, dim3(256), 0, ctx->stream, Yt, sigma, nb,
+                               na, skip);
+            written = true;
+        }
+        if (mask & SQD_TERM_BB) {
+            if ((rc = launch_same_spin<double>(ctx, c, sigma, na, nb, B, A, ctx->jk64, norb, diag, written ? 1 : 0,
+                                               skip)))
+                return rc;
+            written = true;
+        } else if (diag) {
+            hipLaunchKernelGGL(k_diag_apply, dim3(g), dim3(256), 0, ctx->stream, diag, c, sigma, dim, written ? 1 : 0,
+                               skip);
+            written = true;
+        }
+        if (!written) hipLaunchKernelGGL(k_fill<double>, dim3(g), dim3(256), 0, ctx->stream, sigma, dim, 0.0, skip);
+        if (mask & SQD_TERM_AB) {
+            if (ab_path == SQD_AB_KH) {
+                if ((rc = sqd_sigma_ab_kh(ctx, sp, c, sigma, 0, skip))) return rc;
+            } else if ((rc = launch_ab_direct<double>(ctx, sp, c, sigma, ctx->eri, skip))) {
+                return rc;
+            }
+        }
+        SQD_HIP(ctx, hipGetLastError());
+        return SQD_OK;
+    }
+    // FP32 off-diagonal terms
+    void* scr = nullptr;
+    if ((rc = space_scratch_get(ctx, sp, sizeof(float) * 4 * (dim + 64), &scr))) return rc;
+    float* C32 = (float*)scr;
+    float* Ct32 = C32 + dim + 64;
+    float* Yt32 = Ct32 + dim + 64;
+    float* S32 = Yt32 + dim + 64;
+    const float* Cin = c32_in;
+    if (!Cin) {
+        hipLaunchKernelGGL((k_convert<double, float>), dim3(g), dim3(256), 0, ctx->stream, c, C32, dim, skip);
+        Cin = C32;
+    }
+    bool written = false;
+    if (mask & SQD_TERM_AA) {
+        hipLaunchKernelGGL((k_transpose<float, float, false>), tgrid, dim3(256), 0, ctx->stream, Cin, Ct32, na, nb, skip);
+        if ((rc = launch_same_spin<float>(ctx, Ct32, Yt32, nb, na, A, B, ctx->jk32, norb, nullptr, 0, skip))) return rc;
+        hipLaunchKernelGGL((k_transpose<float, float, false>), tgridT, dim3(256), 0, ctx->stream, Yt32, S32, nb, na,
+                           skip);
+        written = true;
+    }
+    if (mask & SQD_TERM_BB) {
+        if ((rc = launch_same_spin<float>(ctx, Cin, S32, na, nb, B, A, ctx->jk32, norb, nullptr, written ? 1 : 0,
+                                          skip)))
+            return rc;
+        written = true;
+    }
+    if (!written) hipLaunchKernelGGL(k_fill<float>, dim3(g), dim3(256), 0, ctx->stream, S32, dim, 0.0f, skip);
+    if (mask & SQD_TERM_AB) {
+        if (ab_path == SQD_AB_KH) {
+            if ((rc = sqd_sigma_ab_kh(ctx, sp, Cin, S32, 1, skip))) return rc;
+        } else if ((rc = launch_ab_direct<float>(ctx, sp, Cin, S32, ctx->eri32, skip))) {
+            return rc;
+        }
+    }
+    hipLaunchKernelGGL(k_combine, dim3(g), dim3(256), 0, ctx->stream, diag, c, S32, sigma, dim, skip);
+    SQD_HIP(ctx, hipGetLastError());
+    return SQD_OK;
+}

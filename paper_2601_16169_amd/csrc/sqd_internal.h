@@ -1,0 +1,139 @@
+// Internal declarations of libsqd (gfx950).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+#include <vector>
+
+#include "../../include/sqd.h"
+
+#define SQD_MAXN 524287          // strings per spin (19-bit neighbour field)
+#define SQD_NBR_MASK 0x7FFFFu
+#define SQD_PAIR_SHIFT 19
+#define SQD_PAIR_MASK 0xFFFu
+#define SQD_WAVE 64
+
+struct sqd_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    int tune[SQD_TUNE_COUNT] = {0, 0, 0, 0, 0, 0};
+    int max_lds = 65536;          // bytes of LDS a workgroup may allocate
+    int num_cu = 256;
+    // Hamiltonian
+    int norb = 0;
+    double ecore = 0.0;
+    int ham_version = 0;
+    double* h = nullptr;          // norb^2
+    double* eri = nullptr;        // norb^4 (also the norb^2 x norb^2 matrix V)
+    float* eri32 = nullptr;
+    double* jk64 = nullptr;       // Jk[k*norb2 + pq] = (pq|kk)
+    float* jk32 = nullptr;
+    double* jdiag = nullptr;      // J[p*norb+q] = (pp|qq)
+    std::vector<double> h_host, eri_host;
+    // scratch shared by products on this context
+    void* scratch = nullptr;
+    size_t scratch_bytes = 0;
+};
+
+// Per-spin tables of one string set (Sec. V-A flattened lists).
+struct spin_tables {
+    int64_t n = 0;                // strings
+    int nel = 0;
+    uint64_t* str = nullptr;      // ascending strings
+    // canonical CSR (rows = source strings, entries sorted by target)
+    int* s_off = nullptr;         // n+1
+    uint64_t* s_ent = nullptr;    // packed canonical singles
+    int* d_off = nullptr;
+    uint64_t* d_ent = nullptr;
+    int64_t nnz_s = 0, nnz_d = 0;
+    // gather form of the singles: nbr | pair << 19 | negative << 31
+    uint32_t* s_pk = nullptr;
+    int* d_nbr = nullptr;
+    // integral-dependent values (rebuilt when the Hamiltonian changes)
+    double* s_val64 = nullptr; float* s_val32 = nullptr;
+    double* d_val64 = nullptr; float* d_val32 = nullptr;
+    double* e_same = nullptr;     // same-spin diagonal energy per string
+    // sliced (SELL-64) copies for the same-spin kernel, rows sorted by length
+    int nslices = 0;
+    int* perm_ss = nullptr;       // nslices*64, padded with n
+    int* sl_s_off = nullptr;      // nslices+1 (units of 64 entries)
+    int* sl_d_off = nullptr;
+    uint32_t* sell_s_pk = nullptr;
+    double* sell_s_v64 = nullptr; float* sell_s_v32 = nullptr;
+    int* sell_d_nbr = nullptr;
+    double* sell_d_v64 = nullptr; float* sell_d_v32 = nullptr;
+    // sliced singles for the alpha-beta kernel (rows sorted by singles count)
+    int* perm_ab = nullptr;
+    int* sl_ab_off = nullptr;
+    uint32_t* sell_ab_pk = nullptr;
+    int* sell_csr_s = nullptr;    // CSR index of each sliced slot (-1 = padding)
+    int* sell_csr_d = nullptr;
+    int64_t sell_ss_entries = 0, sell_ab_entries = 0;
+    int max_singles = 0, max_doubles = 0;
+    bool alias = false;           // arrays owned by the other spin
+};
+
+struct sqd_space {
+    sqd_ctx* ctx = nullptr;
+    int norb = 0;
+    int nalpha = 0, nbeta = 0;
+    spin_tables sp[2];            // 0 alpha, 1 beta
+    int values_version = -1;      // ham_version the values were built for
+    int64_t dim = 0;
+    int64_t bytes = 0;
+    // diagonal cache (FP64), per Hamiltonian version
+    double* diag = nullptr;
+    int diag_version = -1;
+    double* ua = nullptr;         // na x norb: sum_{p in Ia} (pp|qq)
+};
+
+// ---- helpers (api.hip) ----
+int sqd_fail(sqd_ctx* ctx, int code, const std::string& msg);
+int sqd_hip_fail(sqd_ctx* ctx, hipError_t e, const char* what);
+int sqd_alloc(sqd_ctx* ctx, void** p, size_t bytes, int64_t* counter);
+void* sqd_ctx_scratch(sqd_ctx* ctx, size_t bytes, int* rc);
+
+#define SQD_HIP(ctx, call)                                              \
+    do {                                                                \
+        hipError_t _e = (call);                                         \
+        if (_e != hipSuccess) return sqd_hip_fail((ctx), _e, #call);    \
+    } while (0)
+
+// ---- tables.hip ----
+int sqd_build_spin_tables(sqd_ctx* ctx, sqd_space* sp, int spin, const uint64_t* host_str,
+                          int64_t n, int nel);
+int sqd_build_values(sqd_ctx* ctx, sqd_space* sp);   // integral-dependent parts
+void sqd_free_spin_tables(spin_tables* t);
+
+// ---- sigma.hip ----
+int sqd_ensure_diag(sqd_ctx* ctx, sqd_space* sp);
+int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma,
+                   int precision, unsigned mask, int ab_path, const float* c32_in,
+                   const int* skip_flag);
+int sqd_sigma_auto_path(sqd_ctx* ctx, const sqd_space* sp, int precision);
+
+// ---- kh.hip ----
+int sqd_sigma_ab_kh(sqd_ctx* ctx, sqd_space* sp, const void* c, void* sigma, int fp32,
+                    const int* skip_flag);
+
+// ---- davidson.hip ----
+int sqd_davidson_impl(sqd_ctx* ctx, sqd_space* sp, const sqd_davidson_opts* o,
+                      double* energy, double* vec, sqd_report* rep);
+
+// ---- rdm.hip ----
+int sqd_rdm_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* rdm1, double* rdm2);
+
+// ---- batched.hip ----
+int sqd_davidson_batched_impl(sqd_ctx* ctx, int nspace, sqd_space* const* spaces,
+                              const sqd_davidson_opts* o, double* energies,
+                              double* const* vecs, sqd_report* reps);
+
+// ---- device helpers shared by kernels ----
+__device__ __forceinline__ int dev_popc(uint64_t x) { return __popcll(x); }
+
+// sign of applying a_k (or a+_k) to string s: (-1)^(occupied orbitals below k)
+__device__ __forceinline__ int dev_parity_below(uint64_t s, int k) {
+    return __popcll(s & ((k == 0) ? 0ull : ((~0ull) >> (64 - k)))) & 1;
+}
