@@ -1,0 +1,143 @@
+"""GPU Davidson (FP64 and FP32-sigma + FP64 refinement) against the oracle:
+dense eigh where the space is small, the stored oracle Davidson result for the
+4.0e6-determinant workload, and residual checks with the oracle sigma.
+
+Bars: FP64 energy <= 1e-8 Ha, vector 1 - |<x, x_ref>| <= 1e-12 (when the
+reference vector is available); mixed energy <= 1e-6 Ha.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2601_16169_amd import inputs as I
+from oracle import core, davidson
+from tests.gpu_util import banner, need_gpu
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    need_gpu()
+    from paper_2601_16169_amd import sqd
+    c = sqd.Context(0)
+    yield c
+    c.close()
+
+
+def _space(ctx, p):
+    ctx.set_hamiltonian(p.ints.h, p.ints.eri, p.ints.ecore)
+    return ctx.build_space(p.nalpha, p.nbeta, p.astr, p.bstr)
+
+
+def _noise(torch, dim):
+    return torch.tensor(I.guess_noise(dim), device="cuda:0")
+
+
+CASES = [
+    ("cfg1", I.cfg1, 1e-10),
+    ("ragged_8_3_4", lambda: I.small_problem(8, 3, 4, 37, 53, 3), 1e-10),
+    ("sab_neq_10_4_3", lambda: I.small_problem(10, 4, 3, 70, 97, 4), 1e-9),
+    ("tiny_dim_6", lambda: I.small_problem(4, 1, 1, 2, 3, 8), 1e-10),
+]
+
+
+@pytest.mark.parametrize("name,make,tol", CASES)
+def test_fp64_matches_dense(ctx, name, make, tol):
+    torch = need_gpu()
+    banner(f"davidson fp64 {name}")
+    p = make()
+    sp = _space(ctx, p)
+    E_ref, x_ref, _ = davidson.dense_lowest(core.Space.from_problem(p).dense())
+    E, x, rep = sp.davidson(tol=tol, noise=_noise(torch, sp.dim))
+    assert rep["converged"], rep["status"]
+    assert abs(E - E_ref) <= 1e-8, (E, E_ref)
+    xv = x.cpu().numpy()
+    assert abs(np.linalg.norm(xv) - 1) <= 1e-12
+    assert 1 - abs(xv @ x_ref) <= 1e-12
+    sp.close()
+
+
+@pytest.mark.parametrize("m_max", [2, 4, 7])
+def test_collapse_paths(ctx, m_max):
+    torch = need_gpu()
+    p = I.small_problem(8, 3, 4, 37, 53, 3)
+    sp = _space(ctx, p)
+    E_ref = np.linalg.eigvalsh(core.Space.from_problem(p).dense())[0]
+    E, x, rep = sp.davidson(tol=1e-9, m_max=m_max, max_iter=400, noise=_noise(torch, sp.dim))
+    assert rep["converged"] and abs(E - E_ref) <= 1e-8
+    sp.close()
+
+
+def test_explicit_guess_and_phase(ctx):
+    torch = need_gpu()
+    p = I.cfg1()
+    sp = _space(ctx, p)
+    osp = core.Space.from_problem(p)
+    E_ref, x_ref, _ = davidson.dense_lowest(osp.dense())
+    g = torch.tensor(I.random_vector(sp.dim, 3), device="cuda:0")
+    E, x, rep = sp.davidson(tol=1e-10, guess=g)
+    xv = x.cpu().numpy()
+    assert abs(E - E_ref) <= 1e-8
+    k = int(np.argmax(np.abs(xv)))
+    assert xv[k] > 0 and np.allclose(xv, x_ref, atol=1e-9)
+    sp.close()
+
+
+@pytest.mark.parametrize("name,make,tol", CASES[:3])
+def test_mixed_matches_dense(ctx, name, make, tol):
+    torch = need_gpu()
+    from paper_2601_16169_amd import sqd
+    banner(f"davidson mixed {name}")
+    p = make()
+    sp = _space(ctx, p)
+    E_ref = np.linalg.eigvalsh(core.Space.from_problem(p).dense())[0]
+    E, x, rep = sp.davidson(tol=tol, mode=sqd.DAV_MIXED, switch_tol=1e-4, noise=_noise(torch, sp.dim))
+    assert rep["converged"]
+    assert rep["switch_iter"] >= 1
+    assert abs(E - E_ref) <= 1e-6
+    sp.close()
+
+
+def test_max_iter_cap_reports_not_converged(ctx):
+    torch = need_gpu()
+    p = I.cfg1()
+    sp = _space(ctx, p)
+    E, x, rep = sp.davidson(tol=1e-14, max_iter=3, noise=_noise(torch, sp.dim))
+    assert not rep["converged"] and rep["status_code"] == 1 and rep["iterations"] == 3
+    sp.close()
+
+
+def _golden(name):
+    path = os.path.join(GOLDEN, f"{name}_oracle.json")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    return json.load(open(path))
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_cfg2_against_stored_oracle(ctx, mode):
+    """4.0e6 determinants: the energy against the oracle's Davidson (stored by
+    tests/golden/make_golden.py), the vector on its 256 largest entries, and
+    the residual of the GPU vector under the oracle sigma on sampled rows."""
+    torch = need_gpu()
+    from paper_2601_16169_amd import sqd
+    gold = _golden("cfg2")
+    banner(f"davidson cfg2 mode={mode}")
+    p = I.cfg2()
+    sp = _space(ctx, p)
+    E, x, rep = sp.davidson(tol=1e-8, mode=mode, noise=_noise(torch, sp.dim))
+    assert rep["converged"]
+    tolE = 1e-8 if mode == 0 else 1e-6
+    assert abs(E - gold["energy"]) <= tolE, (E, gold["energy"])
+    xv = x.cpu().numpy()
+    idx = np.array(gold["top_index"])
+    ref = np.array(gold["top_value"])
+    assert np.abs(xv[idx] - ref).max() <= (1e-7 if mode == 0 else 1e-5)
+    rows = np.unique(np.concatenate([idx[:64], np.random.default_rng(3).choice(sp.dim, 512, replace=False)]))
+    hx = core.Space.from_problem(p).sigma_rows(xv, rows)
+    assert np.abs(hx - E * xv[rows]).max() <= 1e-7
+    sp.close()
