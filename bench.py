@@ -1,0 +1,225 @@
+#!/usr/bin/env python3
+"""Benchmark of the SQD hot path on one MI355X.
+
+A step is one full sigma = H c (diagonal, alpha-alpha, beta-beta and
+alpha-beta terms, FP64) over the 4.0e6-determinant workload (norb 16, 8+8
+electrons, 2000 HF-biased strings per spin, seeded synthetic integrals).
+``value`` is determinants per second per sigma (Gdet/s) with all inputs
+resident in HBM.  The same run also reports:
+
+  * FP32-sigma throughput (off-diagonal terms in FP32, diagonal in FP64);
+  * Davidson time-to-converge for the lowest root, FP64 vs FP32-sigma + FP64
+    refinement, both from the same start vector and to the same residual
+    tolerance, with the energy difference to the stored oracle value;
+  * the roofline of the dominant kernel, timed live with HIP events on the
+    stream it runs on;
+  * the CPU oracle timed on a bounded sample of rows on this host.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg2]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X published peaks
+PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_TFLOPS = 157.3
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cfg2")
+    ap.add_argument("--no-davidson", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--profile-only", action="store_true",
+                    help="only the timed sigma loop (for profilers)")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU only; --gpus must be 1 "
+                          "(multi-GPU sharding is a design in DESIGN.md, not built)"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2601_16169_amd import inputs as I
+    from paper_2601_16169_amd import sqd
+
+    assert torch.cuda.is_available(), "bench needs a HIP device"
+    dev = "cuda:0"
+    prob = I.WORKLOADS[a.workload]()
+    log(f"workload {prob.name}: dim {prob.dim}")
+    stream = torch.cuda.current_stream(0)
+    ctx = sqd.Context(0, stream)
+    ctx.set_hamiltonian(prob.ints.h, prob.ints.eri, prob.ints.ecore)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sp = ctx.build_space(prob.nalpha, prob.nbeta, prob.astr, prob.bstr)
+    torch.cuda.synchronize()
+    t_tables = time.perf_counter() - t0
+    info = sp.info()
+    log(f"tables built in {t_tables:.3f} s: {info}")
+    c = torch.tensor(I.random_vector(sp.dim, 21), device=dev)
+    out = torch.empty_like(c)
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / steps
+
+    # ---- headline: FP64 sigma, all terms
+    t64 = timed(lambda: sp.sigma(c, out, precision=sqd.FP64), a.steps, a.warmup)
+    log(f"sigma fp64 {t64 * 1e3:.3f} ms")
+    if a.profile_only:
+        t32 = timed(lambda: sp.sigma(c, out, precision=sqd.FP32), a.steps, a.warmup)
+        log(f"sigma fp32 {t32 * 1e3:.3f} ms")
+        return
+    t32 = timed(lambda: sp.sigma(c, out, precision=sqd.FP32), a.steps, a.warmup)
+    log(f"sigma fp32 {t32 * 1e3:.3f} ms")
+
+    # ---- per-term times (HIP events on the context's stream)
+    def event_time(fn, reps):
+        fn()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(reps):
+            fn()
+        ev1.record(stream)
+        ev1.synchronize()
+        return ev0.elapsed_time(ev1) / 1e3 / reps
+
+    terms = {}
+    for name, mask in (("diag", sqd.TERM_DIAG), ("aa", sqd.TERM_AA), ("bb", sqd.TERM_BB), ("ab", sqd.TERM_AB)):
+        terms[name] = {
+            "fp64_ms": 1e3 * event_time(lambda: sp.sigma(c, out, precision=sqd.FP64, terms=mask), a.steps),
+            "fp32_ms": 1e3 * event_time(lambda: sp.sigma(c, out, precision=sqd.FP32, terms=mask), a.steps),
+        }
+    log(f"terms {terms}")
+
+    # dominant kernel: the alpha-beta term (FP64), one kernel per call after a
+    # trivial zero fill of sigma; algorithmic work = 2 flops per (alpha single,
+    # beta single) pair = 2 * nnz_single_alpha * nnz_single_beta.
+    n_ab = info["conn_terms"][3]
+    t_ab = terms["ab"]["fp64_ms"] / 1e3
+    flops_ab = 2.0 * n_ab
+    achieved = flops_ab / t_ab / 1e12
+    roofline = {"kernel": "k_ab_direct<double>", "bound": "alu", "achieved": achieved,
+                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                "traffic": None, "algorithmic_flops_per_launch": flops_ab,
+                "launch_ms": t_ab * 1e3}
+
+    conn = info["conn_per_sigma"]
+    result = {
+        "metric": "sigma (H.c) Gdet/s + Davidson time-to-converge, mixed vs FP64, one GPU",
+        "value": sp.dim / t64 / 1e9,
+        "unit": "Gdet/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": t64 * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded integrals and HF-biased strings; the paper's molecules are not available)",
+        "config": {"workload": prob.name, "norb": prob.norb, "nalpha": prob.nalpha, "nbeta": prob.nbeta,
+                   "strings_per_spin": [int(sp.na), int(sp.nb)], "dim": int(sp.dim),
+                   "connections_per_sigma": int(conn)},
+        "sigma_fp32": {"value": sp.dim / t32 / 1e9, "unit": "Gdet/s", "ms": t32 * 1e3},
+        "gconn_per_s": {"fp64": conn / t64 / 1e9, "fp32": conn / t32 / 1e9},
+        "terms_ms": terms,
+        "tables_s": t_tables,
+        "roofline": roofline,
+    }
+
+    # ---- Davidson, FP64 vs mixed
+    if not a.no_davidson:
+        noise = torch.tensor(I.guess_noise(sp.dim), device=dev)
+        gold_path = os.path.join(ROOT, "tests", "golden", f"{a.workload}_oracle.json")
+        gold = json.load(open(gold_path)) if os.path.exists(gold_path) else None
+        dav = {}
+        sp.davidson(tol=1e-8, noise=noise, max_iter=5)  # warm-up of every kernel
+        for mode, name in ((sqd.DAV_FP64, "fp64"), (sqd.DAV_MIXED, "mixed")):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            E, x, rep = sp.davidson(tol=1e-8, mode=mode, switch_tol=1e-4, noise=noise)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t
+            d = {"seconds": el, "energy": E, "iterations": rep["iterations"],
+                 "iterations_fp32": rep["iterations_fp32"], "switch_iter": rep["switch_iter"],
+                 "converged": rep["converged"], "residual": rep["residual"]}
+            if gold:
+                d["abs_err_vs_oracle_Ha"] = abs(E - gold["energy"])
+            dav[name] = (d, x.clone())
+            log(f"davidson {name}: {d}")
+        d64, x64 = dav["fp64"]
+        dmx, xmx = dav["mixed"]
+        dmx["abs_err_vs_fp64_Ha"] = abs(dmx["energy"] - d64["energy"])
+        dmx["vector_err_vs_fp64"] = float(1.0 - abs(torch.dot(x64, xmx)))
+        result["davidson"] = {"tol": 1e-8, "fp64": d64, "mixed": dmx,
+                              "speedup_mixed_vs_fp64": d64["seconds"] / dmx["seconds"],
+                              "oracle_energy": gold["energy"] if gold else None}
+
+    # ---- CPU oracle on a bounded sample of rows
+    if not a.no_cpu_baseline:
+        from oracle import core
+        osp = core.Space.from_problem(prob)
+        cnp = c.cpu().numpy()
+        rng = np.random.default_rng(0)
+        rows = rng.choice(sp.dim, size=min(4096, sp.dim), replace=False)
+        t = time.perf_counter()
+        osp.sigma_rows(cnp, rows)
+        t_small = time.perf_counter() - t
+        nrows = int(min(sp.dim, max(4096, len(rows) * a.cpu_seconds / max(t_small, 1e-3))))
+        rows = rng.choice(sp.dim, size=nrows, replace=False)
+        t = time.perf_counter()
+        ref = osp.sigma_rows(cnp, rows)
+        t_cpu = time.perf_counter() - t
+        got = out  # last product was a term-only call: recompute the full one
+        sp.sigma(c, out, precision=sqd.FP64)
+        err = float(np.abs(out.cpu().numpy()[rows] - ref).max() / np.abs(ref).max())
+        result["cpu_baseline"] = {"value": nrows / t_cpu / 1e9, "unit": "Gdet/s", "cores": core.num_threads(),
+                                  "kind": "oracle",
+                                  "sample": f"{nrows} random rows of sigma (of {sp.dim}), {t_cpu:.1f} s",
+                                  "cpu_model": _cpu_model(), "gpu_vs_cpu": (sp.dim / t64) / (nrows / t_cpu),
+                                  "max_rel_err_gpu_vs_oracle_rows": err}
+        log(f"cpu baseline {result['cpu_baseline']}")
+
+    print(json.dumps(result))
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+if __name__ == "__main__":
+    main()

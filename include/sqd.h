@@ -87,7 +87,10 @@ extern "C" {
 #define SQD_TUNE_SS_WAVES 3    /* waves per same-spin workgroup: 4, 8 or 16 (0 = auto) */
 #define SQD_TUNE_AB_PATH 4     /* default alpha-beta path for SQD_AB_AUTO */
 #define SQD_TUNE_KH_TILE 5     /* beta targets per KH tile: 32 or 64 (0 = auto) */
-#define SQD_TUNE_COUNT 6
+#define SQD_TUNE_AB_VARIANT 6  /* direct alpha-beta kernel: 1 grouped by alpha pair (with an
+                                  intermediate of nnz_singles_alpha x nb values and a gather),
+                                  2 staged per target row (no intermediate); 0 = auto */
+#define SQD_TUNE_COUNT 7
 
 typedef struct sqd_ctx sqd_ctx;      /* opaque, library-owned */
 typedef struct sqd_space sqd_space;  /* opaque, library-owned */

@@ -129,7 +129,8 @@ int sqd_set_tuning(sqd_ctx* ctx, int key, int value) {
     if (!ctx) return SQD_E_INVALID_ARG;
     if (key < 0 || key >= SQD_TUNE_COUNT) return sqd_fail(ctx, SQD_E_INVALID_ARG, "unknown tuning key");
     static const int allowed[SQD_TUNE_COUNT][5] = {
-        {0, 1, 2, 4, 8}, {0, 1, 2, 4, 8}, {0, 4, 8, 16, -1}, {0, 4, 8, 16, -1}, {0, 1, 2, -1, -1}, {0, 32, 64, -1, -1}};
+        {0, 1, 2, 4, 8}, {0, 1, 2, 4, 8}, {0, 4, 8, 16, -1}, {0, 4, 8, 16, -1}, {0, 1, 2, -1, -1}, {0, 32, 64, -1, -1},
+        {0, 1, 2, -1, -1}};
     bool ok = false;
     for (int v : allowed[key]) ok |= (v == value);
     if (!ok) return sqd_fail(ctx, SQD_E_INVALID_ARG, "tuning value not allowed for key " + std::to_string(key));
@@ -261,6 +262,8 @@ void sqd_space_free(sqd_space* sp) {
     sqd_free_spin_tables(&sp->sp[0]);
     if (sp->diag) (void)hipFree(sp->diag);
     if (sp->ua) (void)hipFree(sp->ua);
+    if (sp->ab_grp) (void)hipFree(sp->ab_grp);
+    if (sp->ab_chunk_pair) (void)hipFree(sp->ab_chunk_pair);
     delete sp;
 }
 

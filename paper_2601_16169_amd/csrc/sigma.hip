@@ -136,11 +136,12 @@ k_same_spin(const T* __restrict__ X, T* __restrict__ Y, int64_t nrows, int64_t n
     const int nthr = blockDim.x;
     const int tid = threadIdx.x;
     // stage R rows of X, transposed to [col][r]
-    for (int64_t idx = tid; idx < (int64_t)R * ncols; idx += nthr) {
-        const int r = (int)(idx / ncols);
-        const int64_t col = idx - (int64_t)r * ncols;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
         const int64_t row = row0 + r;
-        xs[col * R + r] = (row < nrows) ? X[row * ncols + col] : (T)0;
+        const bool ok = row < nrows;
+        const T* xr = X + row * ncols;
+        for (int col = tid; col < (int)ncols; col += nthr) xs[col * R + r] = ok ? xr[col] : (T)0;
     }
     if (tid < R) xs[ncols * R + tid] = (T)0;
     // cross-spin term of the staged rows: ws[pq][r] = sum_{k in row string} (pq|kk)
@@ -225,15 +226,11 @@ k_ab_direct(const T* __restrict__ C, T* __restrict__ S, int64_t na, int64_t nb, 
     for (int j = 0; j < MAXJ; ++j) acc[j] = (T)0;
     for (int k0 = a0; k0 < a1; k0 += KC) {
         __syncthreads();
-        for (int64_t idx = tid; idx < (int64_t)KC * nb; idx += nthr) {
-            const int k = (int)(idx / nb);
-            const int64_t col = idx - (int64_t)k * nb;
-            T v = (T)0;
-            if (k0 + k < a1) {
-                const int64_t src = a_pk[k0 + k] & SQD_NBR_MASK;
-                v = C[src * nb + col];
-            }
-            cs[col * KC + k] = v;
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+            const bool ok = k0 + k < a1;
+            const T* cr = C + (ok ? (int64_t)(a_pk[k0 + k] & SQD_NBR_MASK) * nb : 0);
+            for (int col = tid; col < (int)nb; col += nthr) cs[col * KC + k] = ok ? cr[col] : (T)0;
         }
         if (tid < KC) cs[nb * KC + tid] = (T)0;
         for (int idx = tid; idx < KC * norb2; idx += nthr) {
@@ -279,6 +276,90 @@ k_ab_direct(const T* __restrict__ C, T* __restrict__ S, int64_t na, int64_t nb, 
                 S[o] += acc[j];
             }
         }
+    }
+}
+
+
+// ---------------------------------------------------------------- alpha-beta, grouped by alpha pair
+// The alpha single entries e (CSR position in the target row's list; source
+// row src(e), pair ai(e), sign s(e)) are grouped by pair ai and cut into chunks
+// of G entries that share ai.  One workgroup per chunk stages the G source rows
+// of C in LDS ([col][r]) and the row (ai|..) of the (pq|rs) matrix, then walks
+// the sliced beta singles table once for all G rows:
+//   Y[e][jb'] = s(e) * sum_{beta singles jb' <- jb (pair bj, s_b)} s_b (ai|bj) C[src(e)][jb]
+// A coalesced gather then adds sigma[ia'][jb'] += sum_{e in row ia'} Y[e][jb'].
+template <typename T, int G>
+__global__ void __launch_bounds__(1024)
+k_ab_grouped(const T* __restrict__ C, T* __restrict__ Y, int64_t nb, const int* __restrict__ grp,
+             const int* __restrict__ chunk_pair, const uint32_t* __restrict__ a_pk, const int* __restrict__ bperm,
+             int nbslices, const int* __restrict__ bsl_off, const uint32_t* __restrict__ bs_pk,
+             const T* __restrict__ V, int norb, const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    T* xs = reinterpret_cast<T*>(lds_raw);
+    const int norb2 = norb * norb;
+    T* vrow = xs + (nb + 1) * G;
+    const int chunk = blockIdx.x;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int pair = chunk_pair[chunk];
+    int e[G];
+    T sgn[G];
+#pragma unroll
+    for (int r = 0; r < G; ++r) {
+        e[r] = grp[chunk * G + r];
+        sgn[r] = (e[r] >= 0 && (a_pk[e[r]] >> 31)) ? (T)-1 : (T)1;
+    }
+#pragma unroll
+    for (int r = 0; r < G; ++r) {
+        const bool ok = e[r] >= 0;
+        const T* cr = C + (ok ? (int64_t)(a_pk[e[r]] & SQD_NBR_MASK) * nb : 0);
+        for (int col = tid; col < (int)nb; col += nthr) xs[col * G + r] = ok ? cr[col] : (T)0;
+    }
+    if (tid < G) xs[nb * G + tid] = (T)0;
+    for (int q = tid; q < norb2; q += nthr) vrow[q] = V[(int64_t)pair * norb2 + q];
+    __syncthreads();
+    const int wave = tid >> 6, lane = tid & 63, nw = nthr >> 6;
+    for (int sl = wave; sl < nbslices; sl += nw) {
+        T acc[G];
+#pragma unroll
+        for (int r = 0; r < G; ++r) acc[r] = (T)0;
+        const int c0 = bsl_off[sl], c1 = bsl_off[sl + 1];
+        for (int col = c0; col < c1; ++col) {
+            const uint32_t b = bs_pk[(int64_t)col * 64 + lane];
+            const int nbr = (int)(b & SQD_NBR_MASK);
+            const int pb = (int)((b >> SQD_PAIR_SHIFT) & SQD_PAIR_MASK);
+            T v = vrow[pb];
+            if (b >> 31) v = -v;
+            const T* xr = xs + (int64_t)nbr * G;
+#pragma unroll
+            for (int r = 0; r < G; ++r) acc[r] += v * xr[r];
+        }
+        const int tb = bperm[sl * 64 + lane];
+        if (tb < nb) {
+#pragma unroll
+            for (int r = 0; r < G; ++r)
+                if (e[r] >= 0) Y[(int64_t)e[r] * nb + tb] = sgn[r] * acc[r];
+        }
+    }
+}
+
+// sigma[ia][jb] += sum_{e = a_off[ia]}^{a_off[ia+1]-1} Y[e][jb]
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_ab_gather(const T* __restrict__ Y, T* __restrict__ S, int64_t na, int64_t nb, const int* __restrict__ a_off,
+            const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    const int64_t jb = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (jb >= nb) return;
+    for (int64_t ia = blockIdx.y; ia < na; ia += gridDim.y) {
+        const int e0 = a_off[ia], e1 = a_off[ia + 1];
+        T acc = (T)0;
+        int e = e0;
+        for (; e + 3 < e1; e += 4)
+            acc += (Y[(int64_t)e * nb + jb] + Y[(int64_t)(e + 1) * nb + jb]) +
+                   (Y[(int64_t)(e + 2) * nb + jb] + Y[(int64_t)(e + 3) * nb + jb]);
+        for (; e < e1; ++e) acc += Y[(int64_t)e * nb + jb];
+        S[ia * nb + jb] += acc;
     }
 }
 
@@ -386,6 +467,91 @@ int launch_ab_direct(sqd_ctx* ctx, const sqd_space* sp, const T* C, T* S, const 
     return SQD_OK;
 }
 
+
+// Entries per chunk of the grouped alpha-beta kernel: the most source rows of
+// C (FP64) that fit in LDS next to one row of (pq|rs).
+int ab_group_size(sqd_ctx* ctx, const sqd_space* sp) {
+    const size_t nb = (size_t)sp->sp[1].n, n2 = (size_t)sp->norb * sp->norb;
+    for (int G : {8, 4, 2, 1})
+        if ((nb + 1) * G * sizeof(double) + n2 * sizeof(double) <= (size_t)ctx->max_lds) return G;
+    return 0;
+}
+
+// Group the alpha singles (CSR positions) by orbital pair, padded to chunks of G.
+int ensure_ab_groups(sqd_ctx* ctx, sqd_space* sp, int G) {
+    if (sp->ab_G == G && sp->ab_grp) return SQD_OK;
+    const spin_tables& A = sp->sp[0];
+    std::vector<uint32_t> pk(A.nnz_s);
+    if (A.nnz_s > 0)
+        SQD_HIP(ctx, hipMemcpy(pk.data(), A.s_pk, sizeof(uint32_t) * A.nnz_s, hipMemcpyDeviceToHost));
+    const int npair = sp->norb * sp->norb;
+    std::vector<std::vector<int>> by(npair);
+    for (int64_t e = 0; e < A.nnz_s; ++e) by[(pk[e] >> SQD_PAIR_SHIFT) & SQD_PAIR_MASK].push_back((int)e);
+    std::vector<int> grp, cp;
+    for (int p = 0; p < npair; ++p) {
+        const auto& v = by[p];
+        for (size_t k = 0; k < v.size(); k += G) {
+            for (int r = 0; r < G; ++r) grp.push_back(k + r < v.size() ? v[k + r] : -1);
+            cp.push_back(p);
+        }
+    }
+    if (sp->ab_grp) { (void)hipFree(sp->ab_grp); sp->ab_grp = nullptr; }
+    if (sp->ab_chunk_pair) { (void)hipFree(sp->ab_chunk_pair); sp->ab_chunk_pair = nullptr; }
+    int rc;
+    if ((rc = sqd_alloc(ctx, (void**)&sp->ab_grp, sizeof(int) * (grp.size() + 1), &sp->bytes))) return rc;
+    if ((rc = sqd_alloc(ctx, (void**)&sp->ab_chunk_pair, sizeof(int) * (cp.size() + 1), &sp->bytes))) return rc;
+    if (!grp.empty()) {
+        SQD_HIP(ctx, hipMemcpy(sp->ab_grp, grp.data(), sizeof(int) * grp.size(), hipMemcpyHostToDevice));
+        SQD_HIP(ctx, hipMemcpy(sp->ab_chunk_pair, cp.data(), sizeof(int) * cp.size(), hipMemcpyHostToDevice));
+    }
+    sp->ab_G = G;
+    sp->ab_nchunks = (int)cp.size();
+    return SQD_OK;
+}
+
+// Y bytes of the grouped alpha-beta path (0 if it is not to be used).
+size_t ab_grouped_bytes(sqd_ctx* ctx, const sqd_space* sp, size_t es) {
+    const int variant = ctx->tune[SQD_TUNE_AB_VARIANT];
+    if (variant == 2) return 0;
+    if (ab_group_size(ctx, sp) == 0) return 0;
+    const size_t bytes = (size_t)sp->sp[0].nnz_s * (size_t)sp->sp[1].n * es;
+    const size_t cap = (size_t)64 << 30;   // keep the intermediate below 64 GiB
+    if (variant == 0 && bytes > cap) return 0;
+    return bytes + 256;
+}
+
+template <typename T>
+int launch_ab_grouped(sqd_ctx* ctx, sqd_space* sp, const T* C, T* S, T* Y, const T* V, const int* skip) {
+    const spin_tables& A = sp->sp[0];
+    const spin_tables& B = sp->sp[1];
+    const int G = ab_group_size(ctx, sp);
+    int rc = ensure_ab_groups(ctx, sp, G);
+    if (rc) return rc;
+    if (sp->ab_nchunks > 0) {
+        const int nw = ctx->tune[SQD_TUNE_AB_WAVES] ? ctx->tune[SQD_TUNE_AB_WAVES] : 8;
+        const size_t lds = ((size_t)(B.n + 1) * G + (size_t)sp->norb * sp->norb) * sizeof(T);
+#define SQD_ABG_LAUNCH(GG)                                                                                   \
+    case GG:                                                                                                 \
+        set_lds(k_ab_grouped<T, GG>, (int)lds);                                                              \
+        hipLaunchKernelGGL((k_ab_grouped<T, GG>), dim3(sp->ab_nchunks), dim3(64 * nw), lds, ctx->stream, C, Y, \
+                           B.n, sp->ab_grp, sp->ab_chunk_pair, A.s_pk, B.perm_ab, B.nslices, B.sl_ab_off,     \
+                           B.sell_ab_pk, V, sp->norb, skip);                                                 \
+        break;
+        switch (G) {
+            SQD_ABG_LAUNCH(1)
+            SQD_ABG_LAUNCH(2)
+            SQD_ABG_LAUNCH(4)
+            SQD_ABG_LAUNCH(8)
+        }
+#undef SQD_ABG_LAUNCH
+    }
+    const unsigned gy = (unsigned)(A.n < 65535 ? A.n : 65535);
+    hipLaunchKernelGGL((k_ab_gather<T>), dim3(nblk(B.n, 256), gy), dim3(256), 0, ctx->stream, Y, S, A.n, B.n,
+                       A.s_off, skip);
+    SQD_HIP(ctx, hipGetLastError());
+    return SQD_OK;
+}
+
 }  // namespace
 
 int sqd_ensure_diag(sqd_ctx* ctx, sqd_space* sp) {
@@ -436,9 +602,11 @@ int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma, 
     const dim3 tgrid(nblk(nb, 64), nblk(na, 64)), tgridT(nblk(na, 64), nblk(nb, 64));
     if (precision == SQD_FP64) {
         void* scr = nullptr;
-        if ((rc = space_scratch_get(ctx, sp, sizeof(double) * 2 * (dim + 64), &scr))) return rc;
+        const size_t ybytes = (mask & SQD_TERM_AB) && ab_path != SQD_AB_KH ? ab_grouped_bytes(ctx, sp, 8) : 0;
+        if ((rc = space_scratch_get(ctx, sp, sizeof(double) * 2 * (dim + 64) + ybytes, &scr))) return rc;
         double* Ct = (double*)scr;
         double* Yt = Ct + dim + 64;
+        double* Yab = Yt + dim + 64;
         bool written = false;
         if (mask & SQD_TERM_AA) {
             hipLaunchKernelGGL((k_transpose<double, double, false>), tgrid, dim3(256), 0, ctx->stream, c, Ct, na, nb,
@@ -462,6 +630,8 @@ int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma, 
         if (mask & SQD_TERM_AB) {
             if (ab_path == SQD_AB_KH) {
                 if ((rc = sqd_sigma_ab_kh(ctx, sp, c, sigma, 0, skip))) return rc;
+            } else if (ybytes) {
+                if ((rc = launch_ab_grouped<double>(ctx, sp, c, sigma, Yab, ctx->eri, skip))) return rc;
             } else if ((rc = launch_ab_direct<double>(ctx, sp, c, sigma, ctx->eri, skip))) {
                 return rc;
             }
@@ -471,11 +641,13 @@ int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma, 
     }
     // FP32 off-diagonal terms
     void* scr = nullptr;
-    if ((rc = space_scratch_get(ctx, sp, sizeof(float) * 4 * (dim + 64), &scr))) return rc;
+    const size_t ybytes = (mask & SQD_TERM_AB) && ab_path != SQD_AB_KH ? ab_grouped_bytes(ctx, sp, 4) : 0;
+    if ((rc = space_scratch_get(ctx, sp, sizeof(float) * 4 * (dim + 64) + ybytes, &scr))) return rc;
     float* C32 = (float*)scr;
     float* Ct32 = C32 + dim + 64;
     float* Yt32 = Ct32 + dim + 64;
     float* S32 = Yt32 + dim + 64;
+    float* Yab = S32 + dim + 64;
     const float* Cin = c32_in;
     if (!Cin) {
         hipLaunchKernelGGL((k_convert<double, float>), dim3(g), dim3(256), 0, ctx->stream, c, C32, dim, skip);
@@ -499,6 +671,8 @@ int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma, 
     if (mask & SQD_TERM_AB) {
         if (ab_path == SQD_AB_KH) {
             if ((rc = sqd_sigma_ab_kh(ctx, sp, Cin, S32, 1, skip))) return rc;
+        } else if (ybytes) {
+            if ((rc = launch_ab_grouped<float>(ctx, sp, Cin, S32, Yab, ctx->eri32, skip))) return rc;
         } else if ((rc = launch_ab_direct<float>(ctx, sp, Cin, S32, ctx->eri32, skip))) {
             return rc;
         }

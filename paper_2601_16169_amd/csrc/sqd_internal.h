@@ -18,7 +18,7 @@ struct sqd_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     std::string err;
-    int tune[SQD_TUNE_COUNT] = {0, 0, 0, 0, 0, 0};
+    int tune[SQD_TUNE_COUNT] = {0, 0, 0, 0, 0, 0, 0};
     int max_lds = 65536;          // bytes of LDS a workgroup may allocate
     int num_cu = 256;
     // Hamiltonian
@@ -87,6 +87,11 @@ struct sqd_space {
     double* diag = nullptr;
     int diag_version = -1;
     double* ua = nullptr;         // na x norb: sum_{p in Ia} (pp|qq)
+    // alpha singles grouped by orbital pair for the grouped alpha-beta kernel
+    int ab_G = 0;                 // entries per chunk (0 = not built)
+    int ab_nchunks = 0;
+    int* ab_grp = nullptr;        // ab_nchunks * ab_G CSR positions (-1 = padding)
+    int* ab_chunk_pair = nullptr; // pair index of each chunk
 };
 
 // ---- helpers (api.hip) ----
