@@ -33,6 +33,8 @@ if ROOT not in sys.path:
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
+COPY_BYTES = 1 << 28
+PROFILES = os.path.join(ROOT, "profiles")
 
 
 def log(msg):
@@ -93,8 +95,13 @@ def main():
     t64 = timed(lambda: sp.sigma(c, out, precision=sqd.FP64), a.steps, a.warmup)
     log(f"sigma fp64 {t64 * 1e3:.3f} ms")
     if a.profile_only:
-        t32 = timed(lambda: sp.sigma(c, out, precision=sqd.FP32), a.steps, a.warmup)
-        log(f"sigma fp32 {t32 * 1e3:.3f} ms")
+        # plain copy of known size, for scaling the HBM byte counters
+        src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {COPY_BYTES} bytes read + written per copy")
         return
     t32 = timed(lambda: sp.sigma(c, out, precision=sqd.FP32), a.steps, a.warmup)
     log(f"sigma fp32 {t32 * 1e3:.3f} ms")
@@ -119,18 +126,16 @@ def main():
         }
     log(f"terms {terms}")
 
-    # dominant kernel: the alpha-beta term (FP64), one kernel per call after a
-    # trivial zero fill of sigma; algorithmic work = 2 flops per (alpha single,
-    # beta single) pair = 2 * nnz_single_alpha * nnz_single_beta.
-    n_ab = info["conn_terms"][3]
-    t_ab = terms["ab"]["fp64_ms"] / 1e3
-    flops_ab = 2.0 * n_ab
-    achieved = flops_ab / t_ab / 1e12
-    roofline = {"kernel": "k_ab_direct<double>", "bound": "alu", "achieved": achieved,
-                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
-                "traffic": None, "algorithmic_flops_per_launch": flops_ab,
-                "launch_ms": t_ab * 1e3}
-
+    # ---- per-kernel times: HIP events recorded by the library on its stream
+    ctx.profile(True)
+    for _ in range(a.steps):
+        sp.sigma(c, out, precision=sqd.FP64)
+    kern = ctx.profile_report()
+    ctx.profile(False)
+    kernels = {k: {"calls_per_step": n / a.steps, "ms_per_step": ms / a.steps, "ms_per_launch": ms / n}
+               for k, (n, ms) in kern.items()}
+    log(f"kernels {kernels}")
+    roofline = _roofline(kernels, info, sp, prob)
     conn = info["conn_per_sigma"]
     result = {
         "metric": "sigma (H.c) Gdet/s + Davidson time-to-converge, mixed vs FP64, one GPU",
@@ -151,6 +156,7 @@ def main():
         "sigma_fp32": {"value": sp.dim / t32 / 1e9, "unit": "Gdet/s", "ms": t32 * 1e3},
         "gconn_per_s": {"fp64": conn / t64 / 1e9, "fp32": conn / t32 / 1e9},
         "terms_ms": terms,
+        "kernels": kernels,
         "tables_s": t_tables,
         "roofline": roofline,
     }
@@ -209,6 +215,66 @@ def main():
         log(f"cpu baseline {result['cpu_baseline']}")
 
     print(json.dumps(result))
+
+
+def _algorithmic(name, info, sp):
+    """(bound, work per launch, unit) of one kernel, from the table counts.
+
+    Pair-gather kernels: one multiply-add (2 flops) per Hamiltonian connection
+    they evaluate.  alpha-beta: every (alpha single, beta single) pair.
+    same-spin (called once per spin, the beta call also applying the
+    diagonal): the singles and doubles of that spin times the strings of the
+    other.  Gather, transpose: bytes read + written once.
+    """
+    es = 8 if "double" in name else 4
+    t = info["conn_terms"]  # diag, aa, bb, ab connections per sigma
+    if name.startswith(("k_ab_grouped", "k_ab_direct", "k_ab_kh")):
+        return "alu", 2.0 * t[3], "flop"
+    if name.startswith("k_same_spin"):
+        return "alu", 2.0 * (t[1] + t[2]) / 2, "flop"
+    if name.startswith("k_ab_gather"):
+        return "hbm", float(es) * (info["nnz_single"][0] * sp.nb + 2 * sp.dim), "byte"
+    if name.startswith("k_transpose"):
+        return "hbm", 2.0 * es * sp.dim, "byte"
+    return None, None, None
+
+
+def _traffic(name):
+    """HBM bytes per launch from the committed --pmc summary of this kernel,
+    or None when none is there or the kernel source changed since."""
+    import hashlib
+    base = name.split("<")[0]
+    path = os.path.join(PROFILES, f"traffic_{base}_cfg2.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    src = vals.get("source")
+    if not src or "bytes_per_launch" not in vals:
+        return None
+    h = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()[:16]
+    if h != vals.get("source_sha256"):
+        return None
+    return float(vals["bytes_per_launch"])
+
+
+def _roofline(kernels, info, sp, prob):
+    """Roofline of the kernel with the largest share of the step."""
+    name = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
+    bound, work, unit = _algorithmic(name, info, sp)
+    t = kernels[name]["ms_per_launch"] / 1e3
+    if bound == "hbm":
+        ach, peak, u = work / t / 1e9, PEAK_HBM_GBS, "GB/s"
+    else:
+        peak = PEAK_FP64_TFLOPS if "double" in name else PEAK_FP32_TFLOPS
+        ach, u = work / t / 1e12, "TFLOP/s"
+    return {"kernel": name, "bound": bound, "achieved": ach, "peak": peak, "unit": u, "frac": ach / peak,
+            "traffic": _traffic(name), "algorithmic_per_launch": work, "algorithmic_unit": unit,
+            "launch_ms": t * 1e3, "share_of_step": kernels[name]["ms_per_step"] / sum(
+                v["ms_per_step"] for v in kernels.values())}
 
 
 def _cpu_model():

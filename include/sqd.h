@@ -150,6 +150,13 @@ int sqd_synchronize(sqd_ctx* ctx);
 /* Set a tuning parameter (SQD_TUNE_*); value 0 restores the automatic choice. */
 int sqd_set_tuning(sqd_ctx* ctx, int key, int value);
 int sqd_get_tuning(const sqd_ctx* ctx, int key, int* value);
+/* Per-kernel timers: while enabled, the single-space calls record HIP events
+ * on the context's stream around each kernel they launch (the batched solver,
+ * which replays captured graphs, records none). */
+int sqd_profile(sqd_ctx* ctx, int enable);
+/* Synchronise, write one line per kernel name, "name calls total_ms\n", into
+ * buf (NUL-terminated, truncated to len), and clear the records. */
+int sqd_profile_report(sqd_ctx* ctx, char* buf, int len);
 
 /* ---- Hamiltonian (Sec. II: integrals provided in an input file; Sec. V-A:
  * integrals held as raw arrays indexed by orbital pair) ------------------ */

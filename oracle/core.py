@@ -41,6 +41,9 @@ def lib():
         L.oracle_h_elem.argtypes = [ctypes.c_int, P, i64, P, i64, P, P, d, i64, i64, i64, i64]
         L.oracle_h_elem.restype = d
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_csr_count.argtypes = [ctypes.c_int, P, i64, P, i64, P]
+        L.oracle_csr_fill.argtypes = [ctypes.c_int, P, i64, P, i64, P, P, d, P, P, P]
+        L.oracle_csr_matvec.argtypes = [i64, P, P, P, P, P]
         _lib = L
     return _lib
 
@@ -137,6 +140,39 @@ class Space:
 
     def energy_from_rdm(self, g1, g2) -> float:
         return self.ecore + float(np.sum(self.h * g1)) + 0.5 * float(np.sum(self.eri * g2))
+
+
+class MemoisedH:
+    """H of a Space evaluated once (by the same definition-based elements) and
+    kept as CSR, for repeated products on spaces too large for the matrix-free
+    oracle to revisit hundreds of times."""
+
+    def __init__(self, space: "Space"):
+        dim = space.dim
+        self.dim = dim
+        self.rowptr = np.zeros(dim + 1, dtype=np.int64)
+        rc = lib().oracle_csr_count(space.norb, _p(space.astr), space.na, _p(space.bstr), space.nb,
+                                    _p(self.rowptr))
+        if rc:
+            raise RuntimeError("oracle_csr_count failed")
+        nnz = int(self.rowptr[-1])
+        self.cols = np.empty(nnz, dtype=np.int32)
+        self.vals = np.empty(nnz, dtype=np.float64)
+        rc = lib().oracle_csr_fill(space.norb, _p(space.astr), space.na, _p(space.bstr), space.nb,
+                                   _p(space.h), _p(space.eri), ctypes.c_double(space.ecore),
+                                   _p(self.rowptr), _p(self.cols), _p(self.vals))
+        if rc:
+            raise RuntimeError(f"oracle_csr_fill failed ({rc})")
+
+    @property
+    def nnz(self):
+        return int(self.rowptr[-1])
+
+    def matvec(self, x: np.ndarray) -> np.ndarray:
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.empty(self.dim)
+        lib().oracle_csr_matvec(self.dim, _p(self.rowptr), _p(self.cols), _p(self.vals), _p(x), _p(y))
+        return y
 
 
 def num_threads() -> int:

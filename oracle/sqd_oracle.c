@@ -435,3 +435,70 @@ double oracle_h_elem(int norb, const uint64_t* astr, int64_t na, const uint64_t*
     pb.h = h; pb.eri = eri; pb.ecore = ecore;
     return h_elem(&pb, ia, ib, ja, jb);
 }
+
+/* ----------------------------------------------------------- memoised H
+ * The same elements, evaluated once into CSR (rows I, every visited J, the
+ * diagonal first), so that a Davidson run on a large space pays the
+ * definition-based evaluation only once.  Pass 1 counts (rowptr), pass 2 fills. */
+
+typedef struct { const prob_t* pb; int64_t n; } cctx_t;
+static void count_visit(void* vctx, int64_t ja, int64_t jb, unsigned cls) {
+    (void)ja; (void)jb; (void)cls;
+    ((cctx_t*)vctx)->n += 1;
+}
+
+int oracle_csr_count(int norb, const uint64_t* astr, int64_t na, const uint64_t* bstr, int64_t nb,
+                     int64_t* rowptr) {
+    if (norb < 1 || norb > 64) return -1;
+    prob_t pb;
+    prob_init(&pb, norb, astr, na, bstr, nb, NULL, NULL, 0.0);
+    int64_t dim = na * nb;
+    #pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t r = 0; r < dim; ++r) {
+        cctx_t c = {&pb, 0};
+        for_each_neighbour(&pb, r / nb, r % nb, count_visit, &c);
+        rowptr[r + 1] = c.n;
+    }
+    rowptr[0] = 0;
+    for (int64_t r = 0; r < dim; ++r) rowptr[r + 1] += rowptr[r];
+    prob_free(&pb);
+    return 0;
+}
+
+typedef struct { const prob_t* pb; int64_t ia, ib, pos; int32_t* cols; double* vals; } fctx_t;
+static void fill_visit(void* vctx, int64_t ja, int64_t jb, unsigned cls) {
+    (void)cls;
+    fctx_t* f = (fctx_t*)vctx;
+    f->cols[f->pos] = (int32_t)(ja * f->pb->nb + jb);
+    f->vals[f->pos] = h_elem(f->pb, f->ia, f->ib, ja, jb);
+    f->pos += 1;
+}
+
+int oracle_csr_fill(int norb, const uint64_t* astr, int64_t na, const uint64_t* bstr, int64_t nb,
+                    const double* h, const double* eri, double ecore,
+                    const int64_t* rowptr, int32_t* cols, double* vals) {
+    if (norb < 1 || norb > 64) return -1;
+    if (na * nb >= 2147483647LL) return -2;
+    prob_t pb;
+    prob_init(&pb, norb, astr, na, bstr, nb, h, eri, ecore);
+    int64_t dim = na * nb;
+    #pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t r = 0; r < dim; ++r) {
+        fctx_t f = {&pb, r / nb, r % nb, rowptr[r], cols, vals};
+        for_each_neighbour(&pb, f.ia, f.ib, fill_visit, &f);
+    }
+    prob_free(&pb);
+    return 0;
+}
+
+/* y = H x with the memoised rows */
+int oracle_csr_matvec(int64_t dim, const int64_t* rowptr, const int32_t* cols, const double* vals,
+                      const double* x, double* y) {
+    #pragma omp parallel for schedule(dynamic, 1024)
+    for (int64_t r = 0; r < dim; ++r) {
+        double acc = 0.0;
+        for (int64_t k = rowptr[r]; k < rowptr[r + 1]; ++k) acc += vals[k] * x[cols[k]];
+        y[r] = acc;
+    }
+    return 0;
+}

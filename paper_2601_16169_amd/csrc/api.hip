@@ -114,6 +114,11 @@ void sqd_destroy(sqd_ctx* ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     free_ham(ctx);
     if (ctx->scratch) (void)hipFree(ctx->scratch);
+    for (auto& r : ctx->prof) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (hipEvent_t e : ctx->prof_pool) (void)hipEventDestroy(e);
     delete ctx;
 }
 
@@ -135,6 +140,40 @@ int sqd_set_tuning(sqd_ctx* ctx, int key, int value) {
     for (int v : allowed[key]) ok |= (v == value);
     if (!ok) return sqd_fail(ctx, SQD_E_INVALID_ARG, "tuning value not allowed for key " + std::to_string(key));
     ctx->tune[key] = value;
+    return SQD_OK;
+}
+
+int sqd_profile(sqd_ctx* ctx, int enable) {
+    if (!ctx) return SQD_E_INVALID_ARG;
+    ctx->profiling = enable != 0;
+    return SQD_OK;
+}
+
+int sqd_profile_report(sqd_ctx* ctx, char* buf, int len) {
+    if (!ctx || !buf || len < 1) return SQD_E_INVALID_ARG;
+    SQD_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    std::vector<std::pair<std::string, std::pair<int, double>>> agg;
+    for (auto& r : ctx->prof) {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, r.a, r.b);
+        bool found = false;
+        for (auto& kv : agg)
+            if (kv.first == r.name) {
+                kv.second.first += 1;
+                kv.second.second += ms;
+                found = true;
+                break;
+            }
+        if (!found) agg.push_back({r.name, {1, (double)ms}});
+        ctx->prof_pool.push_back(r.a);
+        ctx->prof_pool.push_back(r.b);
+    }
+    ctx->prof.clear();
+    std::string out;
+    for (auto& kv : agg)
+        out += kv.first + " " + std::to_string(kv.second.first) + " " + std::to_string(kv.second.second) + "\n";
+    std::strncpy(buf, out.c_str(), (size_t)len - 1);
+    buf[len - 1] = 0;
     return SQD_OK;
 }
 
@@ -264,6 +303,7 @@ void sqd_space_free(sqd_space* sp) {
     if (sp->ua) (void)hipFree(sp->ua);
     if (sp->ab_grp) (void)hipFree(sp->ab_grp);
     if (sp->ab_chunk_pair) (void)hipFree(sp->ab_chunk_pair);
+    if (sp->ab_rev) (void)hipFree(sp->ab_rev);
     delete sp;
 }
 

@@ -1,0 +1,654 @@
+// Device bodies of the Davidson kernels, shared by the single-space launches
+// and the batched launches (davidson.hip).  Grid bodies take their block index
+// and block count within their space (bid, nblk); finishing bodies run in one
+// block per space.
+#pragma once
+
+#include <cmath>
+
+#include "sqd_internal.h"
+
+namespace dav {
+
+
+constexpr int MM = SQD_MMAX;
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+constexpr int kMaxBlocks = 1024;
+constexpr int kPstride = MM + 4;   // partial sums per block
+
+enum { DONE_RUNNING = 0, DONE_CONVERGED = 1, DONE_STALLED = 2, DONE_CAP = 3, DONE_SWITCH = 4 };
+
+struct dav_state {
+    int m;
+    int done;
+    int iter;
+    int collapse;         // number of vectors kept by a pending collapse (0 = none)
+    int phase;            // 0: FP32 sigma (mixed mode), 1: FP64 sigma
+    int phase_start;      // iteration at which the current phase began
+    int kmin;
+    int nhist;
+    int reortho;          // second Gram-Schmidt projection needed
+    int pad_;
+    int counter[8];       // last-block tickets, one per kernel kind
+    double theta;
+    double rnorm;
+    double tt0;           // |t|^2 before orthogonalisation
+    double tinv;          // 1 / |v| of the new basis vector
+    double G[MM * MM];
+    double y[MM];
+    double y_prev[MM];    // previous Ritz vector in the current basis
+    double h[MM];
+    double qc[2][MM];     // collapse coefficients (columns kept)
+    double Gc[4];         // projected matrix after a collapse
+    double hc[2];         // Gram-Schmidt coefficients after a collapse
+    double hist_r[SQD_HIST];
+    double hist_e[SQD_HIST];
+};
+
+struct dav_params {
+    double tol;
+    double switch_tol;
+    int max_iter;
+    int m_max;
+    int mixed;
+};
+
+// Block-wide sums of acc[0..NV) (wave shuffles, then one LDS slot per wave);
+// written to partial row `row`.  All NV entries are reduced so that every
+// register index is static.
+template <int NV>
+__device__ void block_to_partial(const double (&acc)[NV], double* __restrict__ partial, int64_t row) {
+    __shared__ double wred[kWaves][NV];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        double v = acc[j];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if (lane == 0) wred[w][j] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        double s = 0.0;
+        for (int q = 0; q < kWaves; ++q) s += wred[q][threadIdx.x];
+        partial[(size_t)row * kPstride + threadIdx.x] = s;
+    }
+}
+
+// One block of kThreads: out[j] = sum over rows b < nrows of partial[b][j],
+// j < NV (thread t takes rows t, t + kThreads, ...; then a fixed tree), so the
+// result is deterministic.  The partials come from an earlier launch.
+template <int NV>
+__device__ void reduce_rows(const double* __restrict__ partial, int nrows, double* out) {
+    double acc[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) acc[j] = 0.0;
+    for (int b = threadIdx.x; b < nrows; b += kThreads) {
+        const double* row = partial + (size_t)b * kPstride;
+#pragma unroll
+        for (int j = 0; j < NV; ++j) acc[j] += row[j];
+    }
+    __shared__ double wred[kWaves][NV];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        double v = acc[j];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if (lane == 0) wred[w][j] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        double s = 0.0;
+        for (int q = 0; q < kWaves; ++q) s += wred[q][threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------- kernels
+
+// per-block (min value, first index) of the diagonal
+__device__ __forceinline__ void d_argmin(const double* __restrict__ d, int64_t n,
+                                                     double* __restrict__ partial, int64_t bid, int64_t nblk) {
+    __shared__ double sv[kThreads];
+    __shared__ long long si[kThreads];
+    double best = INFINITY;
+    long long bi = -1;
+    for (int64_t i = (int64_t)bid * kThreads + threadIdx.x; i < n; i += (int64_t)nblk * kThreads) {
+        const double v = d[i];
+        if (v < best) { best = v; bi = i; }   // ascending i: first minimum kept
+    }
+    sv[threadIdx.x] = best;
+    si[threadIdx.x] = bi;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            const double v = sv[threadIdx.x + s];
+            const long long j = si[threadIdx.x + s];
+            if (j >= 0 && (si[threadIdx.x] < 0 || v < sv[threadIdx.x] || (v == sv[threadIdx.x] && j < si[threadIdx.x]))) {
+                sv[threadIdx.x] = v;
+                si[threadIdx.x] = j;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[(size_t)bid * kPstride + 0] = sv[0];
+        partial[(size_t)bid * kPstride + 1] = (double)si[0];
+    }
+}
+
+// largest |x| (MODE 1, lowest index on ties) or smallest value (MODE 0) over
+// the per-block partials -> st->kmin; MODE 1 also sums column 2 -> st->tinv = 1/sqrt.
+template <int MODE>
+__device__ __forceinline__ void f_pick_fin(const double* __restrict__ partial, int nrows, dav_state* st) {
+    __shared__ double sv[kThreads], sn[kThreads];
+    __shared__ long long si[kThreads];
+    double b = MODE ? -1.0 : INFINITY, ss = 0.0;
+    long long k = -1;
+    for (int q = threadIdx.x; q < nrows; q += kThreads) {
+        const double v = partial[(size_t)q * kPstride];
+        const long long j = (long long)partial[(size_t)q * kPstride + 1];
+        if (MODE) ss += partial[(size_t)q * kPstride + 2];
+        const bool better = MODE ? (v > b) : (v < b);
+        if (j >= 0 && (k < 0 || better || (v == b && j < k))) { b = v; k = j; }
+    }
+    sv[threadIdx.x] = b; si[threadIdx.x] = k; sn[threadIdx.x] = ss;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            const double v = sv[threadIdx.x + s];
+            const long long j = si[threadIdx.x + s];
+            const bool better = MODE ? (v > sv[threadIdx.x]) : (v < sv[threadIdx.x]);
+            if (j >= 0 && (si[threadIdx.x] < 0 || better || (v == sv[threadIdx.x] && j < si[threadIdx.x]))) {
+                sv[threadIdx.x] = v;
+                si[threadIdx.x] = j;
+            }
+            sn[threadIdx.x] += sn[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        st->kmin = (int)(si[0] < 0 ? 0 : si[0]);
+        if (MODE) st->tinv = 1.0 / sqrt(sn[0]);
+    }
+}
+
+// V[0] = start vector (explicit guess, or e_kmin + noise), and |V[0]|^2 partials.
+__device__ __forceinline__ void d_start(const double* __restrict__ guess, const double* __restrict__ noise,
+                                                    int64_t n, const dav_state* st, double* __restrict__ V0,
+                                                    double* __restrict__ partial, int64_t bid, int64_t nblk) {
+    double acc[1] = {0.0};
+    const int64_t kmin = st->kmin;
+    for (int64_t i = (int64_t)bid * kThreads + threadIdx.x; i < n; i += (int64_t)nblk * kThreads) {
+        double v;
+        if (guess) v = guess[i];
+        else v = (i == kmin ? 1.0 : 0.0) + (noise ? noise[i] : 0.0);
+        V0[i] = v;
+        acc[0] += v * v;
+    }
+    block_to_partial<1>(acc, partial, bid);
+}
+
+__device__ __forceinline__ void f_norm_fin(const double* __restrict__ partial, int nrows, dav_state* st) {
+    __shared__ double out[1];
+    reduce_rows<1>(partial, nrows, out);
+    if (threadIdx.x == 0) st->tinv = 1.0 / sqrt(out[0]);
+}
+
+// V0 *= tinv; copies into the product input (and its FP32 copy)
+__device__ __forceinline__ void d_scale_copy(double* __restrict__ V0, int64_t n, const dav_state* st,
+                                                         double* __restrict__ cin, float* __restrict__ c32, int64_t bid, int64_t nblk) {
+    const double sc = st->tinv;
+    for (int64_t i = (int64_t)bid * kThreads + threadIdx.x; i < n; i += (int64_t)nblk * kThreads) {
+        const double v = V0[i] * sc;
+        V0[i] = v;
+        cin[i] = v;
+        if (c32) c32[i] = (float)v;
+    }
+}
+
+// Residual, preconditioned correction and the first Gram-Schmidt projection:
+// partial columns 0..MT-1: V^T t; MT: |r|^2; MT+1: |t|^2.
+template <int MT>
+__device__ __forceinline__ void d_residual(const double* __restrict__ V, const double* __restrict__ AV, const double* __restrict__ diag, int64_t n,
+           const dav_state* st, double* __restrict__ T, double* __restrict__ partial, int64_t bid, int64_t nblk) {
+    if (st->done) return;
+    const int m = st->m;
+    const double theta = st->theta;
+    double acc[MT + 2];
+#pragma unroll
+    for (int k = 0; k < MT + 2; ++k) acc[k] = 0.0;
+    for (int64_t i = (int64_t)bid * kThreads + threadIdx.x; i < n; i += (int64_t)nblk * kThreads) {
+        double x = 0.0, ax = 0.0;
+#pragma unroll
+        for (int k = 0; k < MT; ++k)
+            if (k < m) {
+                const double yk = st->y[k];
+                x += yk * V[(int64_t)k * n + i];
+                ax += yk * AV[(int64_t)k * n + i];
+            }
+        const double r = ax - theta * x;
+        double den = theta - diag[i];
+        if (fabs(den) < 1e-8) den = (den < 0.0) ? -1e-8 : 1e-8;
+        const double tv = r / den;
+        T[i] = tv;
+        acc[MT] += r * r;
+        acc[MT + 1] += tv * tv;
+#pragma unroll
+        for (int k = 0; k < MT; ++k)
+            if (k < m) acc[k] += V[(int64_t)k * n + i] * tv;
+    }
+    block_to_partial<MT + 2>(acc, partial, bid);
+}
+
+// Convergence / cap / phase-switch decisions and the collapse plan.
+template <int MT>
+__device__ __forceinline__ void f_res_fin(const double* __restrict__ partial, int nrows, dav_state* st, dav_params prm) {
+    if (st->done) return;
+    __shared__ double out[MT + 2];
+    reduce_rows<MT + 2>(partial, nrows, out);
+    if (threadIdx.x != 0) return;
+    const int m = st->m;
+    const double theta = st->theta;
+    const double rn = sqrt(out[MT]);
+    st->rnorm = rn;
+    st->tt0 = out[MT + 1];
+    for (int j = 0; j < m; ++j) st->h[j] = out[j];
+    const int it = st->iter;
+    if (it < SQD_HIST) {
+        st->hist_r[it] = rn;
+        st->hist_e[it] = theta;
+        st->nhist = it + 1;
+    }
+    st->iter = it + 1;
+    int done = DONE_RUNNING;
+    if (st->phase == 0) {
+        // FP32 phase: hand over to FP64 refinement below switch_tol, on
+        // reaching tol, or when the residual stops falling
+        const int inphase = st->iter - st->phase_start;
+        const bool stall = inphase >= 6 && it >= 5 && it - 5 < SQD_HIST && rn > 0.7 * st->hist_r[it - 5];
+        if (rn < prm.switch_tol || rn <= prm.tol || stall) done = DONE_SWITCH;
+    } else if (rn <= prm.tol) {
+        done = DONE_CONVERGED;
+    }
+    if (done == DONE_RUNNING && st->iter >= prm.max_iter) done = DONE_CAP;
+    st->done = done;
+    st->collapse = 0;
+    if (done == DONE_RUNNING && m >= prm.m_max) {
+        // keep the Ritz vector and the previous Ritz vector, orthonormalised in
+        // the small space: q1 = y, q2 ~ y_prev - (y . y_prev) y
+        double* q1 = st->qc[0];
+        double* q2 = st->qc[1];
+        double dp = 0.0;
+        for (int k = 0; k < m; ++k) dp += st->y[k] * st->y_prev[k];
+        double nq = 0.0;
+        for (int k = 0; k < MM; ++k) {
+            q1[k] = (k < m) ? st->y[k] : 0.0;
+            q2[k] = (k < m) ? st->y_prev[k] - dp * st->y[k] : 0.0;
+            nq += q2[k] * q2[k];
+        }
+        int keep = 1;
+        if (nq > 1e-20 && prm.m_max >= 3) {
+            double d2 = 0.0;
+            for (int k = 0; k < m; ++k) d2 += q1[k] * q2[k];
+            nq = 0.0;
+            for (int k = 0; k < m; ++k) {
+                q2[k] -= d2 * q1[k];
+                nq += q2[k] * q2[k];
+            }
+            const double inv = 1.0 / sqrt(nq);
+            for (int k = 0; k < m; ++k) q2[k] *= inv;
+            keep = 2;
+        }
+        for (int a = 0; a < keep; ++a) {
+            double ha = 0.0;
+            for (int k = 0; k < m; ++k) ha += st->qc[a][k] * out[k];
+            st->hc[a] = ha;
+            for (int b = 0; b < keep; ++b) {
+                double g = 0.0;
+                for (int k = 0; k < m; ++k) {
+                    double gk = 0.0;
+                    for (int l = 0; l < m; ++l) gk += st->G[k * MM + l] * st->qc[b][l];
+                    g += st->qc[a][k] * gk;
+                }
+                st->Gc[a * 2 + b] = g;
+            }
+        }
+        if (keep == 2) {
+            const double g = 0.5 * (st->Gc[1] + st->Gc[2]);
+            st->Gc[1] = g;
+            st->Gc[2] = g;
+        }
+        st->collapse = keep;
+    }
+}
+
+// In-place collapse: V[a] = V qc[a], AV[a] = AV qc[a] for the kept columns a.
+// force = 1 (switch to FP64 refinement): keep x = V y only, AV not kept.
+template <int MT>
+__device__ __forceinline__ void d_collapse(double* __restrict__ V, double* __restrict__ AV, int64_t n, const dav_state* st, int force,
+           double* __restrict__ cin, int64_t bid, int64_t nblk) {
+    int keep;
+    if (force) {
+        keep = 1;
+    } else {
+        if (st->done || !st->collapse) return;
+        keep = st->collapse;
+    }
+    const int m = st->m;
+    const double* q1 = force ? st->y : st->qc[0];
+    const double* q2 = st->qc[1];
+    for (int64_t i = (int64_t)bid * kThreads + threadIdx.x; i < n; i += (int64_t)nblk * kThreads) {
+        double x1 = 0.0, x2 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < MT; ++k)
+            if (k < m) {
+                const double v = V[(int64_t)k * n + i];
+                x1 += q1[k] * v;
+                x2 += q2[k] * v;
+                if (!force) {
+                    const double av = AV[(int64_t)k * n + i];
+                    a1 += q1[k] * av;
+                    a2 += q2[k] * av;
+                }
+            }
+        V[i] = x1;
+        if (keep == 2) V[n + i] = x2;
+        if (!force) {
+            AV[i] = a1;
+            if (keep == 2) AV[n + i] = a2;
+        }
+        if (cin) cin[i] = x1;
+    }
+}
+
+// State after a collapse (force: m = 0, the next dots pass rebuilds G[0][0]).
+__device__ __forceinline__ void f_collapse_fin(dav_state* st, int force) {
+    if (threadIdx.x != 0) return;
+    if (force) {
+        st->m = 0;
+        st->collapse = 0;
+        return;
+    }
+    if (st->done || !st->collapse) return;
+    const int keep = st->collapse;
+    st->m = keep;
+    for (int k = 0; k < MM * MM; ++k) st->G[k] = 0.0;
+    st->G[0] = st->Gc[0];
+    if (keep == 2) {
+        st->G[1] = st->Gc[1];
+        st->G[MM] = st->Gc[2];
+        st->G[MM + 1] = st->Gc[3];
+    }
+    for (int k = 0; k < MM; ++k) {
+        st->h[k] = (k < keep) ? st->hc[k] : 0.0;
+        st->y[k] = (k == 0) ? 1.0 : 0.0;
+        st->y_prev[k] = st->y[k];
+    }
+    st->collapse = 0;
+}
+
+// t1 = t - V h; partial columns 0..MT-1: V^T t1; MT: |t1|^2.
+template <int MT>
+__device__ __forceinline__ void d_orth1(const double* __restrict__ V, int64_t n, const dav_state* st, double* __restrict__ T,
+        double* __restrict__ partial, int64_t bid, int64_t nblk) {
+    if (st->done) return;
+    const int m = st->m;
+    double acc[MT + 1];
+#pragma unroll
+    for (int k = 0; k < MT + 1; ++k) acc[k] = 0.0;
+    for (int64_t i = (int64_t)bid * kThreads + threadIdx.x; i < n; i += (int64_t)nblk * kThreads) {
+        double t = T[i];
+#pragma unroll
+        for (int k = 0; k < MT; ++k)
+            if (k < m) t -= st->h[k] * V[(int64_t)k * n + i];
+        T[i] = t;
+        acc[MT] += t * t;
+#pragma unroll
+        for (int k = 0; k < MT; ++k)
+            if (k < m) acc[k] += V[(int64_t)k * n + i] * t;
+    }
+    block_to_partial<MT + 1>(acc, partial, bid);
+}
+
+template <int MT>
+__device__ __forceinline__ void f_orth1_fin(const double* __restrict__ partial, int nrows, dav_state* st) {
+    if (st->done) return;
+    __shared__ double out[MT + 1];
+    reduce_rows<MT + 1>(partial, nrows, out);
+    if (threadIdx.x != 0) return;
+    const int m = st->m;
+    double hh = 0.0;
+    for (int j = 0; j < m; ++j) {
+        st->h[j] = out[j];
+        hh += out[j] * out[j];
+    }
+    const double t1 = out[MT];
+    const double nrm2 = t1 - hh;
+    // a second projection only when the first left a visible overlap
+    st->reortho = (hh > 1e-26 * t1) ? 1 : 0;
+    if (!(nrm2 > 1e-28 * st->tt0) || !(nrm2 > 0.0)) {
+        st->done = (st->rnorm <= 0.0) ? DONE_CONVERGED : DONE_STALLED;
+    } else {
+        st->tinv = 1.0 / sqrt(st->reortho ? nrm2 : t1);
+    }
+}
+
+template <int MT>
+__device__ __forceinline__ void d_orth2(double* __restrict__ V, int64_t n, const dav_state* st, const double* __restrict__ T, double* __restrict__ cin,
+        float* __restrict__ c32, int64_t bid, int64_t nblk) {
+    if (st->done) return;
+    const int m = st->m;
+    const double sc = st->tinv;
+    const bool re = st->reortho != 0;
+    double* vm = V + (int64_t)m * n;
+    const bool lo = (st->phase == 0) && c32;
+    for (int64_t i = (int64_t)bid * kThreads + threadIdx.x; i < n; i += (int64_t)nblk * kThreads) {
+        double t = T[i];
+        if (re) {
+#pragma unroll
+            for (int k = 0; k < MT; ++k)
+                if (k < m) t -= st->h[k] * V[(int64_t)k * n + i];
+        }
+        t *= sc;
+        vm[i] = t;
+        cin[i] = t;
+        if (lo) c32[i] = (float)t;
+    }
+}
+
+// AV[m] = S; partial columns 0..m: V[k] . S.
+template <int MT>
+__device__ __forceinline__ void d_dots(const double* __restrict__ V, double* __restrict__ AV, const double* __restrict__ S, int64_t n,
+       const dav_state* st, double* __restrict__ partial, int64_t bid, int64_t nblk) {
+    if (st->done) return;
+    const int m = st->m;
+    double acc[MT + 1];
+#pragma unroll
+    for (int k = 0; k <= MT; ++k) acc[k] = 0.0;
+    double* avm = AV + (int64_t)m * n;
+    for (int64_t i = (int64_t)bid * kThreads + threadIdx.x; i < n; i += (int64_t)nblk * kThreads) {
+        const double s = S[i];
+        avm[i] = s;
+#pragma unroll
+        for (int k = 0; k <= MT; ++k)
+            if (k <= m) acc[k] += V[(int64_t)k * n + i] * s;
+    }
+    block_to_partial<MT + 1>(acc, partial, bid);
+}
+
+// G[:, m] from the partials, m += 1, then the lowest eigenpair of G by
+// parallel cyclic Jacobi (round-robin pairs): theta, y (y_prev keeps the old y).
+template <int MT>
+__device__ __forceinline__ void f_dots_fin(const double* __restrict__ partial, int nrows, dav_state* st) {
+    if (st->done) return;
+    __shared__ double out[MT + 1];
+    reduce_rows<MT + 1>(partial, nrows, out);
+    __shared__ double A[MM * MM];
+    __shared__ double Q[MM * MM];
+    __shared__ double rc[MM / 2], rs[MM / 2];
+    __shared__ int rp[MM / 2], rq[MM / 2];
+    __shared__ double red[2 * kWaves];
+    const int t = threadIdx.x;
+    const int m0 = st->m;
+    const int m = m0 + 1;
+    for (int j = t; j <= m0; j += kThreads) {
+        st->G[j * MM + m0] = out[j];
+        st->G[m0 * MM + j] = out[j];
+    }
+    for (int k = t; k < MM; k += kThreads) st->y_prev[k] = st->y[k];
+    __syncthreads();
+    for (int k = t; k < MM * MM; k += kThreads) {
+        A[k] = st->G[k];
+        Q[k] = ((k / MM) == (k % MM)) ? 1.0 : 0.0;
+    }
+    if (t == 0) st->m = m;
+    __syncthreads();
+    if (m > 1) {
+        const int n2 = (m + 1) & ~1;
+        const int npair = n2 / 2;
+        const int lane = t & 63, w = t >> 6;
+        for (int sweep = 0; sweep < 50; ++sweep) {
+            double off = 0.0, tot = 0.0;
+            for (int k = t; k < m * m; k += kThreads) {
+                const int i = k / m, j = k % m;
+                const double v = A[i * MM + j];
+                tot += v * v;
+                if (i != j) off += v * v;
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+                off += __shfl_xor(off, o);
+                tot += __shfl_xor(tot, o);
+            }
+            if (lane == 0) { red[w] = off; red[kWaves + w] = tot; }
+            __syncthreads();
+            off = 0.0; tot = 0.0;
+            for (int q = 0; q < kWaves; ++q) { off += red[q]; tot += red[kWaves + q]; }
+            __syncthreads();
+            if (off <= 1e-28 * tot || off == 0.0) break;
+            for (int step = 0; step < n2 - 1; ++step) {
+                if (t < npair) {
+                    const int pa = t, pb = n2 - 1 - t;
+                    int p = pa == 0 ? 0 : ((pa - 1 + step) % (n2 - 1)) + 1;
+                    int q = pb == 0 ? 0 : ((pb - 1 + step) % (n2 - 1)) + 1;
+                    if (p > q) { const int x = p; p = q; q = x; }
+                    double c = 1.0, s = 0.0;
+                    if (q < m) {
+                        const double apq = A[p * MM + q];
+                        if (apq != 0.0) {
+                            const double tau = (A[q * MM + q] - A[p * MM + p]) / (2.0 * apq);
+                            const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                            c = 1.0 / sqrt(1.0 + tt * tt);
+                            s = tt * c;
+                        }
+                    }
+                    rc[t] = c; rs[t] = s; rp[t] = p; rq[t] = q;
+                }
+                __syncthreads();
+                for (int k = t; k < npair * m; k += kThreads) {   // rows: A <- J^T A
+                    const int pr = k / m, j = k % m;
+                    const int p = rp[pr], q = rq[pr];
+                    if (q >= m) continue;
+                    const double c = rc[pr], s = rs[pr];
+                    const double ap = A[p * MM + j], aq = A[q * MM + j];
+                    A[p * MM + j] = c * ap - s * aq;
+                    A[q * MM + j] = s * ap + c * aq;
+                }
+                __syncthreads();
+                for (int k = t; k < npair * m; k += kThreads) {   // columns: A <- A J, Q <- Q J
+                    const int pr = k / m, i = k % m;
+                    const int p = rp[pr], q = rq[pr];
+                    if (q >= m) continue;
+                    const double c = rc[pr], s = rs[pr];
+                    const double ap = A[i * MM + p], aq = A[i * MM + q];
+                    A[i * MM + p] = c * ap - s * aq;
+                    A[i * MM + q] = s * ap + c * aq;
+                    const double qp = Q[i * MM + p], qq = Q[i * MM + q];
+                    Q[i * MM + p] = c * qp - s * qq;
+                    Q[i * MM + q] = s * qp + c * qq;
+                }
+                __syncthreads();
+            }
+        }
+    }
+    if (t == 0) {
+        int kmin = 0;
+        for (int k = 1; k < m; ++k)
+            if (A[k * MM + k] < A[kmin * MM + kmin]) kmin = k;
+        st->theta = A[kmin * MM + kmin];
+        double nrm = 0.0;
+        for (int k = 0; k < m; ++k) nrm += Q[k * MM + kmin] * Q[k * MM + kmin];
+        nrm = 1.0 / sqrt(nrm);
+        // sign: keep continuity with the previous Ritz vector
+        double dp = 0.0;
+        for (int k = 0; k < m; ++k) dp += Q[k * MM + kmin] * st->y_prev[k];
+        if (dp < 0.0) nrm = -nrm;
+        for (int k = 0; k < MM; ++k) st->y[k] = (k < m) ? Q[k * MM + kmin] * nrm : 0.0;
+    }
+}
+
+// Final vector x = V y; per-block largest |x| (lowest index on ties) and |x|^2.
+template <int MT>
+__device__ __forceinline__ void d_final(const double* __restrict__ V, int64_t n, const dav_state* st, double* __restrict__ out,
+        double* __restrict__ partial, int64_t bid, int64_t nblk) {
+    const int m = st->m;
+    __shared__ double sv[kThreads], sn[kThreads];
+    __shared__ long long si[kThreads];
+    double best = -1.0, nrm = 0.0;
+    long long bi = -1;
+    for (int64_t i = (int64_t)bid * kThreads + threadIdx.x; i < n; i += (int64_t)nblk * kThreads) {
+        double x = 0.0;
+#pragma unroll
+        for (int k = 0; k < MT; ++k)
+            if (k < m) x += st->y[k] * V[(int64_t)k * n + i];
+        out[i] = x;
+        nrm += x * x;
+        const double a = fabs(x);
+        if (a > best) { best = a; bi = i; }
+    }
+    sv[threadIdx.x] = best; si[threadIdx.x] = bi; sn[threadIdx.x] = nrm;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            const double v = sv[threadIdx.x + s];
+            const long long j = si[threadIdx.x + s];
+            if (j >= 0 && (si[threadIdx.x] < 0 || v > sv[threadIdx.x] || (v == sv[threadIdx.x] && j < si[threadIdx.x]))) {
+                sv[threadIdx.x] = v;
+                si[threadIdx.x] = j;
+            }
+            sn[threadIdx.x] += sn[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[(size_t)bid * kPstride + 0] = sv[0];
+        partial[(size_t)bid * kPstride + 1] = (double)si[0];
+        partial[(size_t)bid * kPstride + 2] = sn[0];
+    }
+}
+
+// sign of the largest entry, read before any rescaling
+__device__ __forceinline__ void f_final_sign(const double* __restrict__ out, dav_state* st) {
+    if (threadIdx.x == 0) {
+        const int64_t k = st->kmin;
+        if (out[k] < 0.0) st->tinv = -st->tinv;
+    }
+}
+
+__device__ __forceinline__ void d_final_scale(double* __restrict__ out, int64_t n, const dav_state* st, int64_t bid, int64_t nblk) {
+    const double sc = st->tinv;
+    for (int64_t i = (int64_t)bid * kThreads + threadIdx.x; i < n; i += (int64_t)nblk * kThreads)
+        out[i] *= sc;
+}
+
+__device__ __forceinline__ void f_set_phase(dav_state* st, int phase, int done) {
+    if (threadIdx.x == 0) {
+        st->phase = phase;
+        st->phase_start = st->iter;
+        st->done = done;
+    }
+}
+
+
+}  // namespace dav

@@ -19,7 +19,7 @@
 //         KC rows s_a (ai|..) of the (pq|rs) matrix in LDS (interleaved so one
 //         lane reads all KC values of a column with wide loads), lanes own
 //         beta targets and accumulate in registers across all alpha sources.
-#include "sqd_internal.h"
+#include "sigma_body.h"
 
 namespace {
 
@@ -62,21 +62,7 @@ __global__ void __launch_bounds__(256) k_transpose(const TI* __restrict__ in, TO
                                                    int64_t cols, const int* __restrict__ skip) {
     if (skip && *skip) return;
     __shared__ TI tile[64][65];
-    const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    for (int k = ty; k < 64; k += 4) {
-        const int64_t r = r0 + k, c = c0 + tx;
-        if (r < rows && c < cols) tile[k][tx] = in[r * cols + c];
-    }
-    __syncthreads();
-    for (int k = ty; k < 64; k += 4) {
-        const int64_t c = c0 + k, r = r0 + tx;
-        if (r < rows && c < cols) {
-            TO v = (TO)tile[tx][k];
-            if (ADD) v += out[c * rows + r];
-            out[c * rows + r] = v;
-        }
-    }
+    transpose_tile<TI, TO, ADD>(in, out, rows, cols, blockIdx.y, blockIdx.x, tile);
 }
 
 template <typename TI, typename TO>
@@ -115,91 +101,17 @@ __global__ void k_diag_apply(const double* __restrict__ diag, const double* __re
     s[k] = v;
 }
 
+
 // ---------------------------------------------------------------- same-spin
 // X: nrows x ncols (row = string of the other spin, column = string of the
 // excited spin).  Y (=|+=) sum over the column spin's singles and doubles.
 // LDS: xs[(ncols+1)*R] as [col][r]; ws[norb2*R] as [pq][r].
 template <typename T, int R>
 __global__ void __launch_bounds__(1024)
-k_same_spin(const T* __restrict__ X, T* __restrict__ Y, int64_t nrows, int64_t ncols,
-            const int* __restrict__ perm, int nslices, const int* __restrict__ sl_s_off,
-            const int* __restrict__ sl_d_off, const uint32_t* __restrict__ s_pk, const T* __restrict__ s_val,
-            const int* __restrict__ d_nbr, const T* __restrict__ d_val, const uint64_t* __restrict__ row_str,
-            const T* __restrict__ jk, int norb, const double* __restrict__ diag, int accumulate,
-            const int* __restrict__ skip) {
+k_same_spin(ss_args<T> a, const T* __restrict__ jk, int norb, const int* __restrict__ skip) {
     if (skip && *skip) return;
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    T* xs = reinterpret_cast<T*>(lds_raw);
-    const int norb2 = norb * norb;
-    T* ws = xs + (ncols + 1) * R;
-    const int64_t row0 = (int64_t)blockIdx.x * R;
-    const int nthr = blockDim.x;
-    const int tid = threadIdx.x;
-    // stage R rows of X, transposed to [col][r]
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int64_t row = row0 + r;
-        const bool ok = row < nrows;
-        const T* xr = X + row * ncols;
-        for (int col = tid; col < (int)ncols; col += nthr) xs[col * R + r] = ok ? xr[col] : (T)0;
-    }
-    if (tid < R) xs[ncols * R + tid] = (T)0;
-    // cross-spin term of the staged rows: ws[pq][r] = sum_{k in row string} (pq|kk)
-    for (int idx = tid; idx < R * norb2; idx += nthr) {
-        const int r = idx / norb2, pq = idx - r * norb2;
-        const int64_t row = row0 + r;
-        T acc = (T)0;
-        if (row < nrows)
-            for (uint64_t x = row_str[row]; x; x &= x - 1)
-                acc += jk[(__ffsll((unsigned long long)x) - 1) * norb2 + pq];
-        ws[pq * R + r] = acc;
-    }
-    __syncthreads();
-    const int wave = tid >> 6, lane = tid & 63, nw = nthr >> 6;
-    for (int sl = wave; sl < nslices; sl += nw) {
-        T acc[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) acc[r] = (T)0;
-        const int s0 = sl_s_off[sl], s1 = sl_s_off[sl + 1];
-        for (int k = s0; k < s1; ++k) {
-            const int64_t pos = (int64_t)k * 64 + lane;
-            const uint32_t e = s_pk[pos];
-            const T v = s_val[pos];
-            const int nbr = (int)(e & SQD_NBR_MASK);
-            const int pair = (int)((e >> SQD_PAIR_SHIFT) & SQD_PAIR_MASK);
-            const T* xr = xs + (int64_t)nbr * R;
-            const T* wr = ws + pair * R;
-            const bool neg = (e >> 31) != 0;
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const T w = wr[r];
-                acc[r] += (v + (neg ? -w : w)) * xr[r];
-            }
-        }
-        const int d0 = sl_d_off[sl], d1 = sl_d_off[sl + 1];
-        for (int k = d0; k < d1; ++k) {
-            const int64_t pos = (int64_t)k * 64 + lane;
-            const int nbr = d_nbr[pos];
-            const T v = d_val[pos];
-            const T* xr = xs + (int64_t)nbr * R;
-#pragma unroll
-            for (int r = 0; r < R; ++r) acc[r] += v * xr[r];
-        }
-        const int t = perm[sl * 64 + lane];
-        if (t < ncols) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int64_t row = row0 + r;
-                if (row < nrows) {
-                    const int64_t o = row * ncols + t;
-                    T val = acc[r];
-                    if (diag) val += (T)(diag[o] * (double)xs[(int64_t)t * R + r]);
-                    if (accumulate) val += Y[o];
-                    Y[o] = val;
-                }
-            }
-        }
-    }
+    ss_block<T, R>(a, jk, norb, blockIdx.x, lds_raw);
 }
 
 // ---------------------------------------------------------------- alpha-beta
@@ -226,13 +138,13 @@ k_ab_direct(const T* __restrict__ C, T* __restrict__ S, int64_t na, int64_t nb, 
     for (int j = 0; j < MAXJ; ++j) acc[j] = (T)0;
     for (int k0 = a0; k0 < a1; k0 += KC) {
         __syncthreads();
+        {
+            const T* rows[KC];
 #pragma unroll
-        for (int k = 0; k < KC; ++k) {
-            const bool ok = k0 + k < a1;
-            const T* cr = C + (ok ? (int64_t)(a_pk[k0 + k] & SQD_NBR_MASK) * nb : 0);
-            for (int col = tid; col < (int)nb; col += nthr) cs[col * KC + k] = ok ? cr[col] : (T)0;
+            for (int k = 0; k < KC; ++k)
+                rows[k] = (k0 + k < a1) ? C + (int64_t)(a_pk[k0 + k] & SQD_NBR_MASK) * nb : nullptr;
+            stage_rows<T, KC>(cs, rows, (int)nb);
         }
-        if (tid < KC) cs[nb * KC + tid] = (T)0;
         for (int idx = tid; idx < KC * norb2; idx += nthr) {
             const int k = idx / norb2, pq = idx - k * norb2;
             T v = (T)0;
@@ -281,66 +193,14 @@ k_ab_direct(const T* __restrict__ C, T* __restrict__ S, int64_t na, int64_t nb, 
 
 
 // ---------------------------------------------------------------- alpha-beta, grouped by alpha pair
-// The alpha single entries e (CSR position in the target row's list; source
-// row src(e), pair ai(e), sign s(e)) are grouped by pair ai and cut into chunks
-// of G entries that share ai.  One workgroup per chunk stages the G source rows
-// of C in LDS ([col][r]) and the row (ai|..) of the (pq|rs) matrix, then walks
-// the sliced beta singles table once for all G rows:
-//   Y[e][jb'] = s(e) * sum_{beta singles jb' <- jb (pair bj, s_b)} s_b (ai|bj) C[src(e)][jb]
-// A coalesced gather then adds sigma[ia'][jb'] += sum_{e in row ia'} Y[e][jb'].
+// (body and layout: abg_block); a coalesced gather then adds
+// sigma[ia'][jb'] += sum_{e in row ia'} Y[e][jb'].
 template <typename T, int G>
 __global__ void __launch_bounds__(1024)
-k_ab_grouped(const T* __restrict__ C, T* __restrict__ Y, int64_t nb, const int* __restrict__ grp,
-             const int* __restrict__ chunk_pair, const uint32_t* __restrict__ a_pk, const int* __restrict__ bperm,
-             int nbslices, const int* __restrict__ bsl_off, const uint32_t* __restrict__ bs_pk,
-             const T* __restrict__ V, int norb, const int* __restrict__ skip) {
+k_ab_grouped(abg_args<T> a, const T* __restrict__ V, int norb, const int* __restrict__ skip) {
     if (skip && *skip) return;
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    T* xs = reinterpret_cast<T*>(lds_raw);
-    const int norb2 = norb * norb;
-    T* vrow = xs + (nb + 1) * G;
-    const int chunk = blockIdx.x;
-    const int tid = threadIdx.x, nthr = blockDim.x;
-    const int pair = chunk_pair[chunk];
-    int e[G];
-    T sgn[G];
-#pragma unroll
-    for (int r = 0; r < G; ++r) {
-        e[r] = grp[chunk * G + r];
-        sgn[r] = (e[r] >= 0 && (a_pk[e[r]] >> 31)) ? (T)-1 : (T)1;
-    }
-#pragma unroll
-    for (int r = 0; r < G; ++r) {
-        const bool ok = e[r] >= 0;
-        const T* cr = C + (ok ? (int64_t)(a_pk[e[r]] & SQD_NBR_MASK) * nb : 0);
-        for (int col = tid; col < (int)nb; col += nthr) xs[col * G + r] = ok ? cr[col] : (T)0;
-    }
-    if (tid < G) xs[nb * G + tid] = (T)0;
-    for (int q = tid; q < norb2; q += nthr) vrow[q] = V[(int64_t)pair * norb2 + q];
-    __syncthreads();
-    const int wave = tid >> 6, lane = tid & 63, nw = nthr >> 6;
-    for (int sl = wave; sl < nbslices; sl += nw) {
-        T acc[G];
-#pragma unroll
-        for (int r = 0; r < G; ++r) acc[r] = (T)0;
-        const int c0 = bsl_off[sl], c1 = bsl_off[sl + 1];
-        for (int col = c0; col < c1; ++col) {
-            const uint32_t b = bs_pk[(int64_t)col * 64 + lane];
-            const int nbr = (int)(b & SQD_NBR_MASK);
-            const int pb = (int)((b >> SQD_PAIR_SHIFT) & SQD_PAIR_MASK);
-            T v = vrow[pb];
-            if (b >> 31) v = -v;
-            const T* xr = xs + (int64_t)nbr * G;
-#pragma unroll
-            for (int r = 0; r < G; ++r) acc[r] += v * xr[r];
-        }
-        const int tb = bperm[sl * 64 + lane];
-        if (tb < nb) {
-#pragma unroll
-            for (int r = 0; r < G; ++r)
-                if (e[r] >= 0) Y[(int64_t)e[r] * nb + tb] = sgn[r] * acc[r];
-        }
-    }
+    abg_block<T, G>(a, V, norb, blockIdx.x, lds_raw);
 }
 
 // sigma[ia][jb] += sum_{e = a_off[ia]}^{a_off[ia+1]-1} Y[e][jb]
@@ -349,18 +209,7 @@ __global__ void __launch_bounds__(256)
 k_ab_gather(const T* __restrict__ Y, T* __restrict__ S, int64_t na, int64_t nb, const int* __restrict__ a_off,
             const int* __restrict__ skip) {
     if (skip && *skip) return;
-    const int64_t jb = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (jb >= nb) return;
-    for (int64_t ia = blockIdx.y; ia < na; ia += gridDim.y) {
-        const int e0 = a_off[ia], e1 = a_off[ia + 1];
-        T acc = (T)0;
-        int e = e0;
-        for (; e + 3 < e1; e += 4)
-            acc += (Y[(int64_t)e * nb + jb] + Y[(int64_t)(e + 1) * nb + jb]) +
-                   (Y[(int64_t)(e + 2) * nb + jb] + Y[(int64_t)(e + 3) * nb + jb]);
-        for (; e < e1; ++e) acc += Y[(int64_t)e * nb + jb];
-        S[ia * nb + jb] += acc;
-    }
+    for (int64_t ia = blockIdx.y; ia < na; ia += gridDim.y) gather_block<T>(Y, S, nb, a_off, ia, blockIdx.x);
 }
 
 constexpr int kAbMaxJ = 8;
@@ -374,11 +223,11 @@ void set_lds(F f, int bytes) {
         if (kv.first == key) {
             if (kv.second >= bytes) return;
             kv.second = bytes;
-            hipFuncSetAttribute(key, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+            (void)hipFuncSetAttribute(key, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
             return;
         }
     seen.emplace_back(key, bytes);
-    hipFuncSetAttribute(key, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    (void)hipFuncSetAttribute(key, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 int pick_rows(sqd_ctx* ctx, int64_t nrows, int64_t ncols, int norb, size_t es) {
@@ -418,12 +267,13 @@ int launch_same_spin(sqd_ctx* ctx, const T* X, T* Y, int64_t nrows, int64_t ncol
     const T* sv = nullptr; const T* dv = nullptr;
     if constexpr (sizeof(T) == 8) { sv = (const T*)col.sell_s_v64; dv = (const T*)col.sell_d_v64; }
     else { sv = (const T*)col.sell_s_v32; dv = (const T*)col.sell_d_v32; }
+    ss_args<T> args{X, Y, nrows, ncols, col.perm_ss, col.nslices, col.sl_s_off, col.sl_d_off, col.sell_s_pk, sv,
+                    col.sell_d_nbr, dv, row.str, diag, accumulate};
+    prof_scope ps(ctx, sizeof(T) == 8 ? "k_same_spin<double>" : "k_same_spin<float>");
 #define SQD_SS_LAUNCH(RR)                                                                                    \
     case RR:                                                                                                 \
         set_lds(k_same_spin<T, RR>, (int)lds);                                                               \
-        hipLaunchKernelGGL((k_same_spin<T, RR>), grid, block, lds, ctx->stream, X, Y, nrows, ncols,         \
-                           col.perm_ss, col.nslices, col.sl_s_off, col.sl_d_off, col.sell_s_pk, sv,        \
-                           col.sell_d_nbr, dv, row.str, jk, norb, diag, accumulate, skip);                  \
+        hipLaunchKernelGGL((k_same_spin<T, RR>), grid, block, lds, ctx->stream, args, jk, norb, skip);       \
         break;
     switch (R) {
         SQD_SS_LAUNCH(1)
@@ -449,6 +299,7 @@ int launch_ab_direct(sqd_ctx* ctx, const sqd_space* sp, const T* C, T* S, const 
     const int groups = (B.nslices + nw * kAbMaxJ - 1) / (nw * kAbMaxJ);
     const size_t lds = ((size_t)(B.n + 1) + (size_t)sp->norb * sp->norb) * KC * es;
     const dim3 grid((unsigned)A.n, (unsigned)groups), block(64 * nw);
+    prof_scope ps(ctx, sizeof(T) == 8 ? "k_ab_direct<double>" : "k_ab_direct<float>");
 #define SQD_AB_LAUNCH(KK)                                                                                    \
     case KK:                                                                                                 \
         set_lds(k_ab_direct<T, KK, kAbMaxJ>, (int)lds);                                                      \
@@ -478,7 +329,7 @@ int ab_group_size(sqd_ctx* ctx, const sqd_space* sp) {
 }
 
 // Group the alpha singles (CSR positions) by orbital pair, padded to chunks of G.
-int ensure_ab_groups(sqd_ctx* ctx, sqd_space* sp, int G) {
+int ensure_ab_groups_impl(sqd_ctx* ctx, sqd_space* sp, int G) {
     if (sp->ab_G == G && sp->ab_grp) return SQD_OK;
     const spin_tables& A = sp->sp[0];
     std::vector<uint32_t> pk(A.nnz_s);
@@ -525,17 +376,19 @@ int launch_ab_grouped(sqd_ctx* ctx, sqd_space* sp, const T* C, T* S, T* Y, const
     const spin_tables& A = sp->sp[0];
     const spin_tables& B = sp->sp[1];
     const int G = ab_group_size(ctx, sp);
-    int rc = ensure_ab_groups(ctx, sp, G);
+    int rc = ensure_ab_groups_impl(ctx, sp, G);
     if (rc) return rc;
     if (sp->ab_nchunks > 0) {
-        const int nw = ctx->tune[SQD_TUNE_AB_WAVES] ? ctx->tune[SQD_TUNE_AB_WAVES] : 8;
+        const int nw = ctx->tune[SQD_TUNE_AB_WAVES] ? ctx->tune[SQD_TUNE_AB_WAVES] : 16;
         const size_t lds = ((size_t)(B.n + 1) * G + (size_t)sp->norb * sp->norb) * sizeof(T);
+        abg_args<T> args{C, Y, B.n, sp->ab_grp, sp->ab_chunk_pair, A.s_pk, B.perm_ab, B.nslices, B.sl_ab_off,
+                         B.sell_ab_pk};
+        prof_scope ps(ctx, sizeof(T) == 8 ? "k_ab_grouped<double>" : "k_ab_grouped<float>");
 #define SQD_ABG_LAUNCH(GG)                                                                                   \
     case GG:                                                                                                 \
         set_lds(k_ab_grouped<T, GG>, (int)lds);                                                              \
-        hipLaunchKernelGGL((k_ab_grouped<T, GG>), dim3(sp->ab_nchunks), dim3(64 * nw), lds, ctx->stream, C, Y, \
-                           B.n, sp->ab_grp, sp->ab_chunk_pair, A.s_pk, B.perm_ab, B.nslices, B.sl_ab_off,     \
-                           B.sell_ab_pk, V, sp->norb, skip);                                                 \
+        hipLaunchKernelGGL((k_ab_grouped<T, GG>), dim3(sp->ab_nchunks), dim3(64 * nw), lds, ctx->stream, args, \
+                           V, sp->norb, skip);                                                               \
         break;
         switch (G) {
             SQD_ABG_LAUNCH(1)
@@ -546,6 +399,7 @@ int launch_ab_grouped(sqd_ctx* ctx, sqd_space* sp, const T* C, T* S, T* Y, const
 #undef SQD_ABG_LAUNCH
     }
     const unsigned gy = (unsigned)(A.n < 65535 ? A.n : 65535);
+    prof_scope ps(ctx, sizeof(T) == 8 ? "k_ab_gather<double>" : "k_ab_gather<float>");
     hipLaunchKernelGGL((k_ab_gather<T>), dim3(nblk(B.n, 256), gy), dim3(256), 0, ctx->stream, Y, S, A.n, B.n,
                        A.s_off, skip);
     SQD_HIP(ctx, hipGetLastError());
@@ -553,6 +407,8 @@ int launch_ab_grouped(sqd_ctx* ctx, sqd_space* sp, const T* C, T* S, T* Y, const
 }
 
 }  // namespace
+
+int sqd_ensure_ab_groups(sqd_ctx* ctx, sqd_space* sp, int G) { return ensure_ab_groups_impl(ctx, sp, G); }
 
 int sqd_ensure_diag(sqd_ctx* ctx, sqd_space* sp) {
     int rc = sqd_build_values(ctx, sp);
@@ -602,18 +458,25 @@ int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma, 
     const dim3 tgrid(nblk(nb, 64), nblk(na, 64)), tgridT(nblk(na, 64), nblk(nb, 64));
     if (precision == SQD_FP64) {
         void* scr = nullptr;
-        const size_t ybytes = (mask & SQD_TERM_AB) && ab_path != SQD_AB_KH ? ab_grouped_bytes(ctx, sp, 8) : 0;
+        const size_t ybytes = !(mask & SQD_TERM_AB) ? 0
+                              : (ab_path == SQD_AB_KH ? sqd_kh_bytes(sp, 8) : ab_grouped_bytes(ctx, sp, 8));
         if ((rc = space_scratch_get(ctx, sp, sizeof(double) * 2 * (dim + 64) + ybytes, &scr))) return rc;
         double* Ct = (double*)scr;
         double* Yt = Ct + dim + 64;
         double* Yab = Yt + dim + 64;
         bool written = false;
         if (mask & SQD_TERM_AA) {
-            hipLaunchKernelGGL((k_transpose<double, double, false>), tgrid, dim3(256), 0, ctx->stream, c, Ct, na, nb,
-                               skip);
+            {
+                prof_scope pt(ctx, "k_transpose<double>");
+                hipLaunchKernelGGL((k_transpose<double, double, false>), tgrid, dim3(256), 0, ctx->stream, c, Ct, na,
+                                   nb, skip);
+            }
             if ((rc = launch_same_spin<double>(ctx, Ct, Yt, nb, na, A, B, ctx->jk64, norb, nullptr, 0, skip))) return rc;
-            hipLaunchKernelGGL((k_transpose<double, double, false>), tgridT, dim3(256), 0, ctx->stream, Yt, sigma, nb,
-                               na, skip);
+            {
+                prof_scope pt(ctx, "k_transpose<double>");
+                hipLaunchKernelGGL((k_transpose<double, double, false>), tgridT, dim3(256), 0, ctx->stream, Yt, sigma,
+                                   nb, na, skip);
+            }
             written = true;
         }
         if (mask & SQD_TERM_BB) {
@@ -629,7 +492,7 @@ int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma, 
         if (!written) hipLaunchKernelGGL(k_fill<double>, dim3(g), dim3(256), 0, ctx->stream, sigma, dim, 0.0, skip);
         if (mask & SQD_TERM_AB) {
             if (ab_path == SQD_AB_KH) {
-                if ((rc = sqd_sigma_ab_kh(ctx, sp, c, sigma, 0, skip))) return rc;
+                if ((rc = sqd_sigma_ab_kh(ctx, sp, c, sigma, Yab, 0, skip))) return rc;
             } else if (ybytes) {
                 if ((rc = launch_ab_grouped<double>(ctx, sp, c, sigma, Yab, ctx->eri, skip))) return rc;
             } else if ((rc = launch_ab_direct<double>(ctx, sp, c, sigma, ctx->eri, skip))) {
@@ -641,7 +504,8 @@ int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma, 
     }
     // FP32 off-diagonal terms
     void* scr = nullptr;
-    const size_t ybytes = (mask & SQD_TERM_AB) && ab_path != SQD_AB_KH ? ab_grouped_bytes(ctx, sp, 4) : 0;
+    const size_t ybytes = !(mask & SQD_TERM_AB) ? 0
+                          : (ab_path == SQD_AB_KH ? sqd_kh_bytes(sp, 4) : ab_grouped_bytes(ctx, sp, 4));
     if ((rc = space_scratch_get(ctx, sp, sizeof(float) * 4 * (dim + 64) + ybytes, &scr))) return rc;
     float* C32 = (float*)scr;
     float* Ct32 = C32 + dim + 64;
@@ -655,10 +519,17 @@ int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma, 
     }
     bool written = false;
     if (mask & SQD_TERM_AA) {
-        hipLaunchKernelGGL((k_transpose<float, float, false>), tgrid, dim3(256), 0, ctx->stream, Cin, Ct32, na, nb, skip);
+        {
+            prof_scope pt(ctx, "k_transpose<float>");
+            hipLaunchKernelGGL((k_transpose<float, float, false>), tgrid, dim3(256), 0, ctx->stream, Cin, Ct32, na, nb,
+                               skip);
+        }
         if ((rc = launch_same_spin<float>(ctx, Ct32, Yt32, nb, na, A, B, ctx->jk32, norb, nullptr, 0, skip))) return rc;
-        hipLaunchKernelGGL((k_transpose<float, float, false>), tgridT, dim3(256), 0, ctx->stream, Yt32, S32, nb, na,
-                           skip);
+        {
+            prof_scope pt(ctx, "k_transpose<float>");
+            hipLaunchKernelGGL((k_transpose<float, float, false>), tgridT, dim3(256), 0, ctx->stream, Yt32, S32, nb,
+                               na, skip);
+        }
         written = true;
     }
     if (mask & SQD_TERM_BB) {
@@ -670,7 +541,7 @@ int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma, 
     if (!written) hipLaunchKernelGGL(k_fill<float>, dim3(g), dim3(256), 0, ctx->stream, S32, dim, 0.0f, skip);
     if (mask & SQD_TERM_AB) {
         if (ab_path == SQD_AB_KH) {
-            if ((rc = sqd_sigma_ab_kh(ctx, sp, Cin, S32, 1, skip))) return rc;
+            if ((rc = sqd_sigma_ab_kh(ctx, sp, Cin, S32, Yab, 1, skip))) return rc;
         } else if (ybytes) {
             if ((rc = launch_ab_grouped<float>(ctx, sp, Cin, S32, Yab, ctx->eri32, skip))) return rc;
         } else if ((rc = launch_ab_direct<float>(ctx, sp, Cin, S32, ctx->eri32, skip))) {

@@ -1,0 +1,264 @@
+// Device bodies of the sigma kernels, shared by the single-space launches
+// (sigma.hip) and the batched persistent launches (davidson.hip).  Each body
+// processes one work unit (a block index of its own launch shape) of one
+// space described by an argument struct.
+#pragma once
+
+#include "sqd_internal.h"
+
+// Stage R rows of length ncols (row r starts at rows[r], or zeros when null)
+// into LDS as xs[col*R + r]; two columns per iteration so 2R independent
+// global loads are in flight per thread, stored as R contiguous values.
+template <typename T, int R>
+__device__ __forceinline__ void stage_rows(T* __restrict__ xs, const T* const (&rows)[R], int ncols) {
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    int col = tid;
+    for (; col + nthr < ncols; col += 2 * nthr) {
+        T a[R], b[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            a[r] = rows[r] ? rows[r][col] : (T)0;
+            b[r] = rows[r] ? rows[r][col + nthr] : (T)0;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            xs[col * R + r] = a[r];
+            xs[(col + nthr) * R + r] = b[r];
+        }
+    }
+    for (; col < ncols; col += nthr) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) xs[col * R + r] = rows[r] ? rows[r][col] : (T)0;
+    }
+    if (tid < R) xs[ncols * R + tid] = (T)0;
+}
+
+// ---------------------------------------------------------------- same spin
+template <typename T>
+struct ss_args {
+    const T* X;            // nrows x ncols
+    T* Y;
+    int64_t nrows, ncols;
+    const int* perm;       // sliced table of the column spin
+    int nslices;
+    const int* sl_s_off;
+    const int* sl_d_off;
+    const uint32_t* s_pk;
+    const T* s_val;
+    const int* d_nbr;
+    const T* d_val;
+    const uint64_t* row_str;   // strings of the row spin (cross-spin term)
+    const double* diag;        // fused DIAG term (or null)
+    int accumulate;
+};
+
+// Rows blk*R .. blk*R+R-1: Y (=|+=) same-spin singles and doubles of the column
+// spin.  LDS: xs[(ncols+1)*R] as [col][r]; ws[norb2*R] as [pq][r].
+template <typename T, int R>
+__device__ __forceinline__ void ss_block(const ss_args<T>& a, const T* __restrict__ jk, int norb, int64_t blk,
+                                         unsigned char* lds_raw) {
+    T* xs = reinterpret_cast<T*>(lds_raw);
+    const int norb2 = norb * norb;
+    const int64_t ncols = a.ncols, nrows = a.nrows;
+    T* ws = xs + (ncols + 1) * R;
+    const int64_t row0 = blk * R;
+    const int nthr = blockDim.x;
+    const int tid = threadIdx.x;
+    {
+        const T* rows[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) rows[r] = (row0 + r < nrows) ? a.X + (row0 + r) * ncols : nullptr;
+        stage_rows<T, R>(xs, rows, (int)ncols);
+    }
+    // cross-spin term of the staged rows: ws[pq][r] = sum_{k in row string} (pq|kk)
+    for (int idx = tid; idx < R * norb2; idx += nthr) {
+        const int r = idx / norb2, pq = idx - r * norb2;
+        const int64_t row = row0 + r;
+        T acc = (T)0;
+        if (row < nrows)
+            for (uint64_t x = a.row_str[row]; x; x &= x - 1)
+                acc += jk[(__ffsll((unsigned long long)x) - 1) * norb2 + pq];
+        ws[pq * R + r] = acc;
+    }
+    __syncthreads();
+    const int wave = tid >> 6, lane = tid & 63, nw = nthr >> 6;
+    for (int sl = wave; sl < a.nslices; sl += nw) {
+        T acc[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = (T)0;
+        const int s0 = a.sl_s_off[sl], s1 = a.sl_s_off[sl + 1];
+        auto single = [&](uint32_t e, T v) {
+            const int nbr = (int)(e & SQD_NBR_MASK);
+            const int pair = (int)((e >> SQD_PAIR_SHIFT) & SQD_PAIR_MASK);
+            const T* xr = xs + (int64_t)nbr * R;
+            const T* wr = ws + pair * R;
+            const bool neg = (e >> 31) != 0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const T w = wr[r];
+                acc[r] += (v + (neg ? -w : w)) * xr[r];
+            }
+        };
+        int k = s0;
+        for (; k + 4 <= s1; k += 4) {   // four table entries in flight
+            uint32_t e[4];
+            T v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                e[u] = a.s_pk[(int64_t)(k + u) * 64 + lane];
+                v[u] = a.s_val[(int64_t)(k + u) * 64 + lane];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) single(e[u], v[u]);
+        }
+        for (; k < s1; ++k) single(a.s_pk[(int64_t)k * 64 + lane], a.s_val[(int64_t)k * 64 + lane]);
+        const int d0 = a.sl_d_off[sl], d1 = a.sl_d_off[sl + 1];
+        auto dbl = [&](int nbr, T v) {
+            const T* xr = xs + (int64_t)nbr * R;
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r] += v * xr[r];
+        };
+        k = d0;
+        for (; k + 4 <= d1; k += 4) {
+            int nb4[4];
+            T v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                nb4[u] = a.d_nbr[(int64_t)(k + u) * 64 + lane];
+                v[u] = a.d_val[(int64_t)(k + u) * 64 + lane];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) dbl(nb4[u], v[u]);
+        }
+        for (; k < d1; ++k) dbl(a.d_nbr[(int64_t)k * 64 + lane], a.d_val[(int64_t)k * 64 + lane]);
+        const int t = a.perm[sl * 64 + lane];
+        if (t < ncols) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int64_t row = row0 + r;
+                if (row < nrows) {
+                    const int64_t o = row * ncols + t;
+                    T val = acc[r];
+                    if (a.diag) val += (T)(a.diag[o] * (double)xs[(int64_t)t * R + r]);
+                    if (a.accumulate) val += a.Y[o];
+                    a.Y[o] = val;
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- alpha-beta, grouped
+// The alpha single entries e (CSR position in the target row's list; source
+// row src(e), pair ai(e), sign s(e)) are grouped by pair ai and cut into chunks
+// of G entries that share ai.  One unit per chunk stages the G source rows of C
+// in LDS ([col][r]) and the row (ai|..) of the (pq|rs) matrix, then walks the
+// sliced beta singles table once for all G rows:
+//   Y[e][jb'] = s(e) * sum_{beta singles jb' <- jb (pair bj, s_b)} s_b (ai|bj) C[src(e)][jb]
+template <typename T>
+struct abg_args {
+    const T* C;
+    T* Y;
+    int64_t nb;
+    const int* grp;           // chunks x G CSR positions (-1 = padding)
+    const int* chunk_pair;
+    const uint32_t* a_pk;     // alpha singles (gather form)
+    const int* bperm;         // sliced beta singles
+    int nbslices;
+    const int* bsl_off;
+    const uint32_t* bs_pk;
+};
+
+template <typename T, int G>
+__device__ __forceinline__ void abg_block(const abg_args<T>& a, const T* __restrict__ V, int norb, int64_t chunk,
+                                          unsigned char* lds_raw) {
+    T* xs = reinterpret_cast<T*>(lds_raw);
+    const int norb2 = norb * norb;
+    const int64_t nb = a.nb;
+    T* vrow = xs + (nb + 1) * G;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int pair = a.chunk_pair[chunk];
+    int e[G];
+    T sgn[G];
+#pragma unroll
+    for (int r = 0; r < G; ++r) {
+        e[r] = a.grp[chunk * G + r];
+        sgn[r] = (e[r] >= 0 && (a.a_pk[e[r]] >> 31)) ? (T)-1 : (T)1;
+    }
+    {
+        const T* rows[G];
+#pragma unroll
+        for (int r = 0; r < G; ++r) rows[r] = (e[r] >= 0) ? a.C + (int64_t)(a.a_pk[e[r]] & SQD_NBR_MASK) * nb : nullptr;
+        stage_rows<T, G>(xs, rows, (int)nb);
+    }
+    for (int q = tid; q < norb2; q += nthr) vrow[q] = V[(int64_t)pair * norb2 + q];
+    __syncthreads();
+    const int wave = tid >> 6, lane = tid & 63, nw = nthr >> 6;
+    for (int sl = wave; sl < a.nbslices; sl += nw) {
+        T acc[G];
+#pragma unroll
+        for (int r = 0; r < G; ++r) acc[r] = (T)0;
+        const int c0 = a.bsl_off[sl], c1 = a.bsl_off[sl + 1];
+        auto one = [&](uint32_t b) {
+            const int nbr = (int)(b & SQD_NBR_MASK);
+            const int pb = (int)((b >> SQD_PAIR_SHIFT) & SQD_PAIR_MASK);
+            T v = vrow[pb];
+            if (b >> 31) v = -v;
+            const T* xr = xs + (int64_t)nbr * G;
+#pragma unroll
+            for (int r = 0; r < G; ++r) acc[r] += v * xr[r];
+        };
+        int col = c0;
+        for (; col + 4 <= c1; col += 4) {   // four table entries in flight
+            uint32_t b4[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) b4[u] = a.bs_pk[(int64_t)(col + u) * 64 + lane];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) one(b4[u]);
+        }
+        for (; col < c1; ++col) one(a.bs_pk[(int64_t)col * 64 + lane]);
+        const int tb = a.bperm[sl * 64 + lane];
+        if (tb < nb) {
+#pragma unroll
+            for (int r = 0; r < G; ++r)
+                if (e[r] >= 0) a.Y[(int64_t)e[r] * nb + tb] = sgn[r] * acc[r];
+        }
+    }
+}
+
+// sigma[ia][jb] += sum_{e in row ia} Y[e][jb] for the 256 columns jb of block jblk.
+template <typename T>
+__device__ __forceinline__ void gather_block(const T* __restrict__ Y, T* __restrict__ S, int64_t nb,
+                                             const int* __restrict__ a_off, int64_t ia, int64_t jblk) {
+    const int64_t jb = jblk * blockDim.x + threadIdx.x;
+    if (jb >= nb) return;
+    const int e0 = a_off[ia], e1 = a_off[ia + 1];
+    T acc = (T)0;
+    int e = e0;
+    for (; e + 3 < e1; e += 4)
+        acc += (Y[(int64_t)e * nb + jb] + Y[(int64_t)(e + 1) * nb + jb]) +
+               (Y[(int64_t)(e + 2) * nb + jb] + Y[(int64_t)(e + 3) * nb + jb]);
+    for (; e < e1; ++e) acc += Y[(int64_t)e * nb + jb];
+    S[ia * nb + jb] += acc;
+}
+
+// out[c][r] (=|+=) in[r][c] for the 64 x 64 tile (ty, tx); in is rows x cols.
+template <typename TI, typename TO, bool ADD>
+__device__ __forceinline__ void transpose_tile(const TI* __restrict__ in, TO* __restrict__ out, int64_t rows,
+                                               int64_t cols, int64_t ty, int64_t tx_, TI (*tile)[65]) {
+    const int64_t r0 = ty * 64, c0 = tx_ * 64;
+    const int tx = threadIdx.x & 63, tyy = threadIdx.x >> 6, ny = blockDim.x >> 6;
+    for (int k = tyy; k < 64; k += ny) {
+        const int64_t r = r0 + k, c = c0 + tx;
+        if (r < rows && c < cols) tile[k][tx] = in[r * cols + c];
+    }
+    __syncthreads();
+    for (int k = tyy; k < 64; k += ny) {
+        const int64_t c = c0 + k, r = r0 + tx;
+        if (r < rows && c < cols) {
+            TO v = (TO)tile[tx][k];
+            if (ADD) v += out[c * rows + r];
+            out[c * rows + r] = v;
+        }
+    }
+}

@@ -35,6 +35,39 @@ struct sqd_ctx {
     // scratch shared by products on this context
     void* scratch = nullptr;
     size_t scratch_bytes = 0;
+    // per-kernel HIP-event timers (sqd_profile)
+    bool profiling = false;
+    struct prof_rec { const char* name; hipEvent_t a, b; };
+    std::vector<prof_rec> prof;
+    std::vector<hipEvent_t> prof_pool;
+};
+
+// Records HIP events on the context's stream around the launches in its scope
+// while profiling is on (sqd_profile); names must be string literals.
+struct prof_scope {
+    sqd_ctx* ctx;
+    const char* name;
+    hipEvent_t a = nullptr;
+    static hipEvent_t take(sqd_ctx* c) {
+        if (!c->prof_pool.empty()) {
+            hipEvent_t e = c->prof_pool.back();
+            c->prof_pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    prof_scope(sqd_ctx* c, const char* n) : ctx(c), name(n) {
+        if (ctx->profiling && (a = take(ctx))) (void)hipEventRecord(a, ctx->stream);
+    }
+    ~prof_scope() {
+        if (!a) return;
+        hipEvent_t b = take(ctx);
+        if (!b) return;
+        (void)hipEventRecord(b, ctx->stream);
+        ctx->prof.push_back({name, a, b});
+    }
 };
 
 // Per-spin tables of one string set (Sec. V-A flattened lists).
@@ -92,6 +125,7 @@ struct sqd_space {
     int ab_nchunks = 0;
     int* ab_grp = nullptr;        // ab_nchunks * ab_G CSR positions (-1 = padding)
     int* ab_chunk_pair = nullptr; // pair index of each chunk
+    int* ab_rev = nullptr;        // alpha singles: entry of the neighbour's row pointing back
 };
 
 // ---- helpers (api.hip) ----
@@ -118,9 +152,11 @@ int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma,
                    int precision, unsigned mask, int ab_path, const float* c32_in,
                    const int* skip_flag);
 int sqd_sigma_auto_path(sqd_ctx* ctx, const sqd_space* sp, int precision);
+int sqd_ensure_ab_groups(sqd_ctx* ctx, sqd_space* sp, int G);
 
 // ---- kh.hip ----
-int sqd_sigma_ab_kh(sqd_ctx* ctx, sqd_space* sp, const void* c, void* sigma, int fp32,
+size_t sqd_kh_bytes(const sqd_space* sp, size_t es);
+int sqd_sigma_ab_kh(sqd_ctx* ctx, sqd_space* sp, const void* c, void* sigma, void* y, int fp32,
                     const int* skip_flag);
 
 // ---- davidson.hip ----

@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import weakref
 from typing import Optional, Sequence
 
 import numpy as np
@@ -76,7 +77,7 @@ EXPORTS = [
     "sqd_version", "sqd_create", "sqd_destroy", "sqd_last_error", "sqd_synchronize", "sqd_set_tuning",
     "sqd_get_tuning", "sqd_set_hamiltonian", "sqd_build_space", "sqd_space_free", "sqd_space_info",
     "sqd_get_tables", "sqd_diag", "sqd_sigma", "sqd_davidson_default_opts", "sqd_davidson",
-    "sqd_davidson_batched", "sqd_rdm",
+    "sqd_davidson_batched", "sqd_rdm", "sqd_profile", "sqd_profile_report",
 ]
 
 
@@ -113,6 +114,8 @@ def lib():
     L.sqd_davidson_batched.argtypes = [P, c_int, ctypes.POINTER(P), ctypes.POINTER(DavidsonOpts),
                                        ctypes.POINTER(d), ctypes.POINTER(P), ctypes.POINTER(Report)]
     L.sqd_rdm.argtypes = [P, P, P, P, P]
+    L.sqd_profile.argtypes = [P, c_int]
+    L.sqd_profile_report.argtypes = [P, ctypes.c_char_p, c_int]
     _lib = L
     return L
 
@@ -144,6 +147,7 @@ class Context:
         if stream is None:
             stream = torch.cuda.current_stream(device)
         self.stream = stream
+        self._spaces = weakref.WeakSet()
         self._h = ctypes.c_void_p()
         rc = lib().sqd_create(device, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(self._h))
         if rc != 0:
@@ -157,7 +161,10 @@ class Context:
         return rc
 
     def close(self):
+        """Free every space still open on this context, then the context."""
         if self._h:
+            for sp in list(self._spaces):
+                sp.close()
             lib().sqd_destroy(self._h)
             self._h = ctypes.c_void_p()
 
@@ -169,6 +176,20 @@ class Context:
 
     def synchronize(self):
         self._check(lib().sqd_synchronize(self._h), "sqd_synchronize")
+
+    def profile(self, enable: bool = True):
+        """Start/stop per-kernel HIP-event timers on this context's stream."""
+        self._check(lib().sqd_profile(self._h, 1 if enable else 0), "sqd_profile")
+
+    def profile_report(self) -> dict:
+        """{kernel name: (calls, total ms)} since the last report."""
+        buf = ctypes.create_string_buffer(1 << 16)
+        self._check(lib().sqd_profile_report(self._h, buf, len(buf)), "sqd_profile_report")
+        out = {}
+        for line in buf.value.decode().splitlines():
+            name, calls, ms = line.rsplit(" ", 2)
+            out[name] = (int(calls), float(ms))
+        return out
 
     def set_tuning(self, key: int, value: int):
         self._check(lib().sqd_set_tuning(self._h, key, value), "sqd_set_tuning")
@@ -234,11 +255,14 @@ class Space:
         self._h = handle
         self.na, self.nb = na, nb
         self.dim = na * nb
+        ctx._spaces.add(self)
 
     def close(self):
         if self._h:
-            lib().sqd_space_free(self._h)
+            if self.ctx._h:   # a closed context has freed its spaces already
+                lib().sqd_space_free(self._h)
             self._h = ctypes.c_void_p()
+            self.ctx._spaces.discard(self)
 
     def __del__(self):
         try:

@@ -22,7 +22,13 @@ def run(name: str, tol: float) -> dict:
     sp = core.Space.from_problem(prob)
     t0 = time.time()
     diag = sp.diag()
-    res = davidson.davidson(sp.sigma, diag, I.guess_noise(sp.dim), tol=tol)
+    if sp.dim > 100000:
+        # evaluate H once (same elements as the matrix-free oracle), then iterate
+        H = core.MemoisedH(sp)
+        apply_h = H.matvec
+    else:
+        apply_h = sp.sigma
+    res = davidson.davidson(apply_h, diag, I.guess_noise(sp.dim), tol=tol, max_iter=400)
     x = res.vector
     top = np.argsort(-np.abs(x))[:256]
     return {

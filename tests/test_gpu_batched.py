@@ -1,0 +1,90 @@
+"""Batched solves (one persistent launch per sigma term over all spaces,
+graph-captured iterations) against single-space solves and the oracle.
+
+Bars: energies <= 1e-8 Ha against dense eigh (small spaces), <= 1e-9 Ha
+against the single-space GPU solve of the same space (both converged to the
+same residual tolerance), mixed precision <= 1e-6 Ha.
+"""
+import numpy as np
+import pytest
+
+from paper_2601_16169_amd import inputs as I
+from oracle import core
+from tests.gpu_util import banner, need_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    need_gpu()
+    from paper_2601_16169_amd import sqd
+    c = sqd.Context(0)
+    yield c
+    c.close()
+
+
+def _batch(norb, n, counts, seed, nchol=None):
+    ints = I.make_integrals(norb, nchol or 2 * norb, seed=seed)
+    probs = []
+    for b, cnt in enumerate(counts):
+        s = I.sample_strings(norb, n, int(cnt), seed=seed * 1000 + b)
+        probs.append(I.Problem(f"b{b}", ints, n, n, s, s.copy()))
+    return ints, probs
+
+
+def test_batched_small_vs_dense(ctx):
+    torch = need_gpu()
+    banner("batched small vs dense")
+    ints, probs = _batch(8, 4, [12, 25, 40, 55, 70, 33], 61)
+    ctx.set_hamiltonian(ints.h, ints.eri)
+    spaces = [ctx.build_space(p.nalpha, p.nbeta, p.astr, p.bstr) for p in probs]
+    E, vecs, reps, rc = ctx.davidson_batched(spaces, tol=1e-10)
+    assert rc == 0
+    for p, e, v, r in zip(probs, E, vecs, reps):
+        H = core.Space.from_problem(p).dense()
+        w, U = np.linalg.eigh(H)
+        assert r["converged"] and abs(e - w[0]) <= 1e-8, (p.name, e, w[0])
+        x = v.cpu().numpy()
+        assert abs(np.linalg.norm(x) - 1) <= 1e-12
+        assert 1 - abs(x @ U[:, 0]) <= 1e-10
+    for s in spaces:
+        s.close()
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_batched_matches_single_space(ctx, mode):
+    """Uneven batch on norb 24 (the batched workload's orbital count) with
+    fewer and smaller spaces: each energy equals the single-space solve."""
+    torch = need_gpu()
+    from paper_2601_16169_amd import sqd
+    banner(f"batched vs single mode={mode}")
+    counts = [200, 450, 260, 700, 330]
+    ints, probs = _batch(24, 8, counts, 4, nchol=60)
+    ctx.set_hamiltonian(ints.h, ints.eri)
+    spaces = [ctx.build_space(p.nalpha, p.nbeta, p.astr, p.bstr) for p in probs]
+    E, vecs, reps, rc = ctx.davidson_batched(spaces, tol=1e-8, mode=mode, max_iter=400)
+    tolE = 1e-9 if mode == 0 else 1e-6
+    for s, p, e, v, r in zip(spaces, probs, E, vecs, reps):
+        assert r["converged"], (p.name, r["status"], r["residual"])
+        e1, x1, r1 = s.davidson(tol=1e-8, max_iter=400)
+        assert abs(e - e1) <= tolE, (p.name, e, e1)
+        if mode == 0:
+            assert 1 - abs(float(torch.dot(v, x1))) <= 1e-8
+        if mode == 1:
+            assert r["switch_iter"] >= 1
+    for s in spaces:
+        s.close()
+
+
+def test_batched_one_space_and_cap(ctx):
+    torch = need_gpu()
+    p = I.cfg1()
+    ctx.set_hamiltonian(p.ints.h, p.ints.eri)
+    s = ctx.build_space(4, 4, p.astr, p.bstr)
+    E, vecs, reps, rc = ctx.davidson_batched([s], tol=1e-10)
+    w = np.linalg.eigvalsh(core.Space.from_problem(p).dense())[0]
+    assert abs(E[0] - w) <= 1e-8
+    E, vecs, reps, rc = ctx.davidson_batched([s], tol=1e-14, max_iter=3)
+    assert rc == 1 and not reps[0]["converged"] and reps[0]["iterations"] == 3
+    s.close()

@@ -211,3 +211,75 @@ def test_error_codes(ctx):
     with pytest.raises(sqd.SQDError) as e:
         ctx.set_hamiltonian(p.ints.h, eri)
     assert e.value.code == -5
+
+
+KH_CASES = [SMALL[2], SMALL[3], SMALL[4], SMALL[7]]
+
+
+@pytest.mark.parametrize("name,make", KH_CASES)
+@pytest.mark.parametrize("precision", [0, 1])
+def test_sigma_ab_knowles_handy(ctx, name, make, precision):
+    """The MFMA Knowles-Handy alpha-beta path against the oracle."""
+    torch = need_gpu()
+    from paper_2601_16169_amd import sqd
+    banner(f"sigma KH {name} p={precision}")
+    p = make()
+    sp = _space(ctx, p)
+    c = I.random_vector(sp.dim, 14)
+    o = core.Space.from_problem(p).sigma(c, TERMS["AB"])
+    s = sp.sigma(torch.tensor(c, device="cuda:0"), precision=precision, terms=TERMS["AB"],
+                 ab_path=sqd.AB_KH).cpu().numpy()
+    if np.abs(o).max() == 0.0:
+        assert np.abs(s).max() == 0.0
+    else:
+        tol = 1e-12 if precision == 0 else 2e-6
+        assert max(rel_err(s, o)) <= tol
+    sp.close()
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+def test_sigma_ab_variants_cfg2(ctx, variant):
+    """Both direct alpha-beta kernels (grouped, row-staged) and KH agree on
+    the 4.0e6-determinant workload (sampled rows against the oracle)."""
+    torch = need_gpu()
+    from paper_2601_16169_amd import sqd
+    p = I.cfg2()
+    sp = _space(ctx, p)
+    c = I.random_vector(sp.dim, 22)
+    ct = torch.tensor(c, device="cuda:0")
+    ctx.set_tuning(sqd.TUNE_AB_VARIANT, variant)
+    try:
+        s = sp.sigma(ct, terms=TERMS["AB"]).cpu().numpy()
+    finally:
+        ctx.set_tuning(sqd.TUNE_AB_VARIANT, 0)
+    k = sp.sigma(ct, terms=TERMS["AB"], ab_path=sqd.AB_KH).cpu().numpy()
+    rows = _sampled_rows(sp.dim, 2048, 6)
+    o = core.Space.from_problem(p).sigma_rows(c, rows, TERMS["AB"])
+    scale = np.abs(o).max()
+    assert np.abs(s[rows] - o).max() <= 1e-12 * scale
+    assert np.abs(k[rows] - o).max() <= 1e-12 * scale
+    assert np.abs(s - k).max() <= 1e-12 * np.abs(k).max()
+    sp.close()
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("precision", [0, 1])
+def test_sigma_cfg3_sampled_rows(ctx, precision):
+    """The 2.56e8-determinant single-GPU share (norb 36, 12+12 electrons,
+    16000 strings per spin) in the launch shape of a full product; the oracle
+    evaluates 512 sampled rows (plus the first and last) one by one."""
+    torch = need_gpu()
+    banner(f"sigma cfg3 sampled precision={precision}")
+    p = I.cfg3()
+    sp = _space(ctx, p)
+    c = I.random_vector(sp.dim, 23)
+    ct = torch.tensor(c, device="cuda:0")
+    s = sp.sigma(ct, precision=precision)
+    rows = _sampled_rows(sp.dim, 512, 6)
+    got = s[torch.tensor(rows, device="cuda:0")].cpu().numpy()
+    del s, ct
+    o = core.Space.from_problem(p).sigma_rows(c, rows)
+    tol = 1e-12 if precision == 0 else 2e-6
+    err = np.abs(got - o) / np.abs(o).max()
+    assert err.max() <= tol, err.max()
+    sp.close()
