@@ -144,7 +144,7 @@ __global__ void __launch_bounds__(256) kb_gather(const bdesc* __restrict__ D, co
         const int t = units[u].y;
         const T* Y = (const T*)(sizeof(T) == 8 ? (const void*)d.Y64 : (const void*)d.Y32);
         T* S = (T*)(sizeof(T) == 8 ? (void*)d.sout : (void*)d.S32);
-        gather_block<T>(Y, S, d.nb, d.a_off, t / d.njb, t % d.njb);
+        gather_block<T>(Y, S, d.nb, d.ab64.ldy, d.ab64.bperm, d.a_off, t / d.njb, t % d.njb);
     }
 }
 
@@ -608,7 +608,8 @@ int sqd_davidson_batched_impl(sqd_ctx* ctx, int nspace, sqd_space* const* spaces
         part += d.nblk;
         d.ntx = (int)nblk(d.nb, 64);
         d.nty = (int)nblk(d.na, 64);
-        d.njb = (int)nblk(d.nb, 256);
+        const int64_t ldy = (int64_t)B.nslices * 64;
+        d.njb = (int)nblk(ldy, 256);
         PLAN_ALLOC(d.V, sizeof(double) * d.n * mmax);
         PLAN_ALLOC(d.AV, sizeof(double) * d.n * mmax);
         PLAN_ALLOC(d.T, sizeof(double) * d.n);
@@ -616,13 +617,13 @@ int sqd_davidson_batched_impl(sqd_ctx* ctx, int nspace, sqd_space* const* spaces
         PLAN_ALLOC(d.sout, sizeof(double) * d.n);
         PLAN_ALLOC(d.Ct, sizeof(double) * d.n);
         PLAN_ALLOC(d.Yt, sizeof(double) * d.n);
-        PLAN_ALLOC(d.Y64, sizeof(double) * (A.nnz_s * d.nb + 1));
+        PLAN_ALLOC(d.Y64, sizeof(double) * (A.nnz_s * ldy + 1));
         if (mixed) {
             PLAN_ALLOC(d.c32, sizeof(float) * d.n);
             PLAN_ALLOC(d.Ct32, sizeof(float) * d.n);
             PLAN_ALLOC(d.Yt32, sizeof(float) * d.n);
             PLAN_ALLOC(d.S32, sizeof(float) * d.n);
-            PLAN_ALLOC(d.Y32, sizeof(float) * (A.nnz_s * d.nb + 1));
+            PLAN_ALLOC(d.Y32, sizeof(float) * (A.nnz_s * ldy + 1));
         }
         d.diag = sp->diag;
         d.out = vecs[b];
@@ -637,10 +638,10 @@ int sqd_davidson_batched_impl(sqd_ctx* ctx, int nspace, sqd_space* const* spaces
                                 A.sell_s_v32, A.sell_d_nbr, A.sell_d_v32, B.str, nullptr, 0};
         d.bb32 = ss_args<float>{d.c32, d.S32, A.n, B.n, B.perm_ss, B.nslices, B.sl_s_off, B.sl_d_off, B.sell_s_pk,
                                 B.sell_s_v32, B.sell_d_nbr, B.sell_d_v32, A.str, nullptr, 1};
-        d.ab64 = abg_args<double>{d.cin, d.Y64, B.n, sp->ab_grp, sp->ab_chunk_pair, A.s_pk, B.perm_ab, B.nslices,
-                                  B.sl_ab_off, B.sell_ab_pk};
-        d.ab32 = abg_args<float>{d.c32, d.Y32, B.n, sp->ab_grp, sp->ab_chunk_pair, A.s_pk, B.perm_ab, B.nslices,
-                                 B.sl_ab_off, B.sell_ab_pk};
+        d.ab64 = abg_args<double>{d.cin, d.Y64, B.n, ldy, sp->ab_grp, sp->ab_chunk_pair, A.s_pk, B.perm_ab,
+                                  B.nslices, B.sl_ab_off, B.sell_ab_pk};
+        d.ab32 = abg_args<float>{d.c32, d.Y32, B.n, ldy, sp->ab_grp, sp->ab_chunk_pair, A.s_pk, B.perm_ab,
+                                 B.nslices, B.sl_ab_off, B.sell_ab_pk};
         for (int j = 0; j < d.nblk; ++j) vec.push_back(make_int2(b, j));
         for (int t = 0; t < d.ntx * d.nty; ++t) tr.push_back(make_int2(b, t));
         for (int64_t k = 0; k < d.na * d.njb; ++k) gath.push_back(make_int2(b, (int)k));

@@ -5,6 +5,7 @@
 #pragma once
 
 #include <cmath>
+#include <type_traits>
 
 #include "sqd_internal.h"
 
@@ -18,6 +19,28 @@ constexpr int kMaxBlocks = 1024;
 constexpr int kPstride = MM + 4;   // partial sums per block
 
 enum { DONE_RUNNING = 0, DONE_CONVERGED = 1, DONE_STALLED = 2, DONE_CAP = 3, DONE_SWITCH = 4 };
+
+// Calls f(std::integral_constant<int, NR>) with NR the smallest multiple of 4
+// (at most MT) not below cnt.  Loops over the rows of the basis then run to a
+// compile-time bound with every load issued before the first use; rows past
+// cnt are read from row cnt - 1 (always valid) and weighted by zero.  A
+// per-row branch instead makes each load wait for the one before it.
+template <int MT, int NR = 4, typename F>
+__device__ __forceinline__ void with_rows(int cnt, F&& f) {
+    if constexpr (NR >= MT) {
+        f(std::integral_constant<int, MT>{});
+    } else {
+        if (cnt <= NR) f(std::integral_constant<int, NR>{});
+        else with_rows<MT, NR + 4>(cnt, f);
+    }
+}
+
+// Row k of a block of vectors of length n, clamped to the last valid row
+// (row 0 when the block is empty).
+__device__ __forceinline__ const double* row_ptr(const double* B, int k, int cnt, int64_t n) {
+    const int r = k < cnt ? k : cnt - 1;
+    return B + (int64_t)(r > 0 ? r : 0) * n;
+}
 
 struct dav_state {
     int m;
@@ -44,6 +67,9 @@ struct dav_state {
     double hc[2];         // Gram-Schmidt coefficients after a collapse
     double hist_r[SQD_HIST];
     double hist_e[SQD_HIST];
+    int qn;               // Qp holds the eigenvectors of the leading qn x qn block of G (0: none)
+    int pad2_;
+    double Qp[MM * MM];
 };
 
 struct dav_params {
@@ -219,26 +245,42 @@ __device__ __forceinline__ void d_residual(const double* __restrict__ V, const d
     double acc[MT + 2];
 #pragma unroll
     for (int k = 0; k < MT + 2; ++k) acc[k] = 0.0;
-    for (int64_t i = (int64_t)bid * kThreads + threadIdx.x; i < n; i += (int64_t)nblk * kThreads) {
-        double x = 0.0, ax = 0.0;
+    with_rows<MT>(m, [&](auto nr_) {
+        constexpr int NR = decltype(nr_)::value;
+        double y[NR];
+        const double* vr[NR];
+        const double* ar[NR];
 #pragma unroll
-        for (int k = 0; k < MT; ++k)
-            if (k < m) {
-                const double yk = st->y[k];
-                x += yk * V[(int64_t)k * n + i];
-                ax += yk * AV[(int64_t)k * n + i];
+        for (int k = 0; k < NR; ++k) {
+            y[k] = (k < m) ? st->y[k] : 0.0;
+            vr[k] = row_ptr(V, k, m, n);
+            ar[k] = row_ptr(AV, k, m, n);
+        }
+        for (int64_t i = (int64_t)bid * kThreads + threadIdx.x; i < n; i += (int64_t)nblk * kThreads) {
+            double v[NR], a[NR];
+#pragma unroll
+            for (int k = 0; k < NR; ++k) {
+                v[k] = vr[k][i];
+                a[k] = ar[k][i];
             }
-        const double r = ax - theta * x;
-        double den = theta - diag[i];
-        if (fabs(den) < 1e-8) den = (den < 0.0) ? -1e-8 : 1e-8;
-        const double tv = r / den;
-        T[i] = tv;
-        acc[MT] += r * r;
-        acc[MT + 1] += tv * tv;
+            const double d = diag[i];
+            double x = 0.0, ax = 0.0;
 #pragma unroll
-        for (int k = 0; k < MT; ++k)
-            if (k < m) acc[k] += V[(int64_t)k * n + i] * tv;
-    }
+            for (int k = 0; k < NR; ++k) {
+                x += y[k] * v[k];
+                ax += y[k] * a[k];
+            }
+            const double r = ax - theta * x;
+            double den = theta - d;
+            if (fabs(den) < 1e-8) den = (den < 0.0) ? -1e-8 : 1e-8;
+            const double tv = r / den;
+            T[i] = tv;
+            acc[MT] += r * r;
+            acc[MT + 1] += tv * tv;
+#pragma unroll
+            for (int k = 0; k < NR; ++k) acc[k] += (k < m) ? v[k] * tv : 0.0;
+        }
+    });
     block_to_partial<MT + 2>(acc, partial, bid);
 }
 
@@ -337,30 +379,50 @@ __device__ __forceinline__ void d_collapse(double* __restrict__ V, double* __res
         keep = st->collapse;
     }
     const int m = st->m;
-    const double* q1 = force ? st->y : st->qc[0];
-    const double* q2 = st->qc[1];
-    for (int64_t i = (int64_t)bid * kThreads + threadIdx.x; i < n; i += (int64_t)nblk * kThreads) {
-        double x1 = 0.0, x2 = 0.0, a1 = 0.0, a2 = 0.0;
+    const double* q1p = force ? st->y : st->qc[0];
+    const double* q2p = st->qc[1];
+    with_rows<MT>(m, [&](auto nr_) {
+        constexpr int NR = decltype(nr_)::value;
+        double q1[NR], q2[NR];
+        const double* vr[NR];
+        const double* ar[NR];
 #pragma unroll
-        for (int k = 0; k < MT; ++k)
-            if (k < m) {
-                const double v = V[(int64_t)k * n + i];
-                x1 += q1[k] * v;
-                x2 += q2[k] * v;
-                if (!force) {
-                    const double av = AV[(int64_t)k * n + i];
-                    a1 += q1[k] * av;
-                    a2 += q2[k] * av;
-                }
-            }
-        V[i] = x1;
-        if (keep == 2) V[n + i] = x2;
-        if (!force) {
-            AV[i] = a1;
-            if (keep == 2) AV[n + i] = a2;
+        for (int k = 0; k < NR; ++k) {
+            q1[k] = (k < m) ? q1p[k] : 0.0;
+            q2[k] = (k < m) ? q2p[k] : 0.0;
+            vr[k] = row_ptr(V, k, m, n);
+            ar[k] = row_ptr(AV, k, m, n);
         }
-        if (cin) cin[i] = x1;
-    }
+        // every row is read before row 0 or 1 is written: the loads of one
+        // element precede its stores, and elements are independent
+        for (int64_t i = (int64_t)bid * kThreads + threadIdx.x; i < n; i += (int64_t)nblk * kThreads) {
+            double v[NR];
+#pragma unroll
+            for (int k = 0; k < NR; ++k) v[k] = vr[k][i];
+            double x1 = 0.0, x2 = 0.0;
+#pragma unroll
+            for (int k = 0; k < NR; ++k) {
+                x1 += q1[k] * v[k];
+                x2 += q2[k] * v[k];
+            }
+            if (!force) {
+                double a[NR];
+#pragma unroll
+                for (int k = 0; k < NR; ++k) a[k] = ar[k][i];
+                double a1 = 0.0, a2 = 0.0;
+#pragma unroll
+                for (int k = 0; k < NR; ++k) {
+                    a1 += q1[k] * a[k];
+                    a2 += q2[k] * a[k];
+                }
+                AV[i] = a1;
+                if (keep == 2) AV[n + i] = a2;
+            }
+            V[i] = x1;
+            if (keep == 2) V[n + i] = x2;
+            if (cin) cin[i] = x1;
+        }
+    });
 }
 
 // State after a collapse (force: m = 0, the next dots pass rebuilds G[0][0]).
@@ -369,11 +431,13 @@ __device__ __forceinline__ void f_collapse_fin(dav_state* st, int force) {
     if (force) {
         st->m = 0;
         st->collapse = 0;
+        st->qn = 0;
         return;
     }
     if (st->done || !st->collapse) return;
     const int keep = st->collapse;
     st->m = keep;
+    st->qn = 0;
     for (int k = 0; k < MM * MM; ++k) st->G[k] = 0.0;
     st->G[0] = st->Gc[0];
     if (keep == 2) {
@@ -398,17 +462,28 @@ __device__ __forceinline__ void d_orth1(const double* __restrict__ V, int64_t n,
     double acc[MT + 1];
 #pragma unroll
     for (int k = 0; k < MT + 1; ++k) acc[k] = 0.0;
-    for (int64_t i = (int64_t)bid * kThreads + threadIdx.x; i < n; i += (int64_t)nblk * kThreads) {
-        double t = T[i];
+    with_rows<MT>(m, [&](auto nr_) {
+        constexpr int NR = decltype(nr_)::value;
+        double h[NR];
+        const double* vr[NR];
 #pragma unroll
-        for (int k = 0; k < MT; ++k)
-            if (k < m) t -= st->h[k] * V[(int64_t)k * n + i];
-        T[i] = t;
-        acc[MT] += t * t;
+        for (int k = 0; k < NR; ++k) {
+            h[k] = (k < m) ? st->h[k] : 0.0;
+            vr[k] = row_ptr(V, k, m, n);
+        }
+        for (int64_t i = (int64_t)bid * kThreads + threadIdx.x; i < n; i += (int64_t)nblk * kThreads) {
+            double v[NR];
 #pragma unroll
-        for (int k = 0; k < MT; ++k)
-            if (k < m) acc[k] += V[(int64_t)k * n + i] * t;
-    }
+            for (int k = 0; k < NR; ++k) v[k] = vr[k][i];
+            double t = T[i];
+#pragma unroll
+            for (int k = 0; k < NR; ++k) t -= h[k] * v[k];
+            T[i] = t;
+            acc[MT] += t * t;
+#pragma unroll
+            for (int k = 0; k < NR; ++k) acc[k] += (k < m) ? v[k] * t : 0.0;
+        }
+    });
     block_to_partial<MT + 1>(acc, partial, bid);
 }
 
@@ -444,18 +519,37 @@ __device__ __forceinline__ void d_orth2(double* __restrict__ V, int64_t n, const
     const bool re = st->reortho != 0;
     double* vm = V + (int64_t)m * n;
     const bool lo = (st->phase == 0) && c32;
-    for (int64_t i = (int64_t)bid * kThreads + threadIdx.x; i < n; i += (int64_t)nblk * kThreads) {
-        double t = T[i];
-        if (re) {
-#pragma unroll
-            for (int k = 0; k < MT; ++k)
-                if (k < m) t -= st->h[k] * V[(int64_t)k * n + i];
+    if (!re) {
+        for (int64_t i = (int64_t)bid * kThreads + threadIdx.x; i < n; i += (int64_t)nblk * kThreads) {
+            const double t = T[i] * sc;
+            vm[i] = t;
+            cin[i] = t;
+            if (lo) c32[i] = (float)t;
         }
-        t *= sc;
-        vm[i] = t;
-        cin[i] = t;
-        if (lo) c32[i] = (float)t;
+        return;
     }
+    with_rows<MT>(m, [&](auto nr_) {
+        constexpr int NR = decltype(nr_)::value;
+        double h[NR];
+        const double* vr[NR];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            h[k] = (k < m) ? st->h[k] : 0.0;
+            vr[k] = row_ptr(V, k, m, n);
+        }
+        for (int64_t i = (int64_t)bid * kThreads + threadIdx.x; i < n; i += (int64_t)nblk * kThreads) {
+            double v[NR];
+#pragma unroll
+            for (int k = 0; k < NR; ++k) v[k] = vr[k][i];
+            double t = T[i];
+#pragma unroll
+            for (int k = 0; k < NR; ++k) t -= h[k] * v[k];
+            t *= sc;
+            vm[i] = t;
+            cin[i] = t;
+            if (lo) c32[i] = (float)t;
+        }
+    });
 }
 
 // AV[m] = S; partial columns 0..m: V[k] . S.
@@ -468,13 +562,22 @@ __device__ __forceinline__ void d_dots(const double* __restrict__ V, double* __r
 #pragma unroll
     for (int k = 0; k <= MT; ++k) acc[k] = 0.0;
     double* avm = AV + (int64_t)m * n;
-    for (int64_t i = (int64_t)bid * kThreads + threadIdx.x; i < n; i += (int64_t)nblk * kThreads) {
-        const double s = S[i];
-        avm[i] = s;
+    const int cnt = m + 1;   // rows 0..m, the new vector included (cnt <= MT)
+    with_rows<MT>(cnt, [&](auto nr_) {
+        constexpr int NR = decltype(nr_)::value;
+        const double* vr[NR];
 #pragma unroll
-        for (int k = 0; k <= MT; ++k)
-            if (k <= m) acc[k] += V[(int64_t)k * n + i] * s;
-    }
+        for (int k = 0; k < NR; ++k) vr[k] = row_ptr(V, k, cnt, n);
+        for (int64_t i = (int64_t)bid * kThreads + threadIdx.x; i < n; i += (int64_t)nblk * kThreads) {
+            double v[NR];
+#pragma unroll
+            for (int k = 0; k < NR; ++k) v[k] = vr[k][i];
+            const double s = S[i];
+            avm[i] = s;
+#pragma unroll
+            for (int k = 0; k < NR; ++k) acc[k] += (k < cnt) ? v[k] * s : 0.0;
+        }
+    });
     block_to_partial<MT + 1>(acc, partial, bid);
 }
 
@@ -487,6 +590,7 @@ __device__ __forceinline__ void f_dots_fin(const double* __restrict__ partial, i
     reduce_rows<MT + 1>(partial, nrows, out);
     __shared__ double A[MM * MM];
     __shared__ double Q[MM * MM];
+    __shared__ double B[MM * MM];
     __shared__ double rc[MM / 2], rs[MM / 2];
     __shared__ int rp[MM / 2], rq[MM / 2];
     __shared__ double red[2 * kWaves];
@@ -498,24 +602,60 @@ __device__ __forceinline__ void f_dots_fin(const double* __restrict__ partial, i
         st->G[m0 * MM + j] = out[j];
     }
     for (int k = t; k < MM; k += kThreads) st->y_prev[k] = st->y[k];
+    // Warm start: when Qp diagonalises the leading m0 x m0 block, rotate G by
+    // diag(Qp, 1) first; the result is diagonal but for its last row and
+    // column, and the sweeps below converge in two or three passes.
+    const bool warm = (st->qn == m0) && m0 > 0;
     __syncthreads();
     for (int k = t; k < MM * MM; k += kThreads) {
+        const int i = k / MM, j = k % MM;
+        double q = (i == j) ? 1.0 : 0.0;
+        if (warm && i < m0 && j < m0) q = st->Qp[k];
+        Q[k] = q;
         A[k] = st->G[k];
-        Q[k] = ((k / MM) == (k % MM)) ? 1.0 : 0.0;
     }
     if (t == 0) st->m = m;
     __syncthreads();
+    if (warm) {
+        for (int k = t; k < MM * MM; k += kThreads) {   // B = G Q
+            const int i = k / MM, j = k % MM;
+            double v = 0.0;
+            if (i < m && j < m)
+                for (int l = 0; l < m; ++l) v += A[i * MM + l] * Q[l * MM + j];
+            B[k] = v;
+        }
+        __syncthreads();
+        for (int k = t; k < MM * MM; k += kThreads) {   // A = Q^T B
+            const int i = k / MM, j = k % MM;
+            double v = 0.0;
+            if (i < m && j < m)
+                for (int l = 0; l < m; ++l) v += Q[l * MM + i] * B[l * MM + j];
+            A[k] = v;
+        }
+        __syncthreads();
+        for (int k = t; k < MM * MM; k += kThreads) {   // exact symmetry
+            const int i = k / MM, j = k % MM;
+            if (i < j && j < m) {
+                const double v = 0.5 * (A[i * MM + j] + A[j * MM + i]);
+                A[i * MM + j] = v;
+                A[j * MM + i] = v;
+            }
+        }
+        __syncthreads();
+    }
     if (m > 1) {
         const int n2 = (m + 1) & ~1;
         const int npair = n2 / 2;
         const int lane = t & 63, w = t >> 6;
         for (int sweep = 0; sweep < 50; ++sweep) {
             double off = 0.0, tot = 0.0;
-            for (int k = t; k < m * m; k += kThreads) {
-                const int i = k / m, j = k % m;
-                const double v = A[i * MM + j];
-                tot += v * v;
-                if (i != j) off += v * v;
+            for (int k = t; k < MM * MM; k += kThreads) {
+                const int i = k / MM, j = k % MM;
+                if (i < m && j < m) {
+                    const double v = A[k];
+                    tot += v * v;
+                    if (i != j) off += v * v;
+                }
             }
             for (int o = 32; o > 0; o >>= 1) {
                 off += __shfl_xor(off, o);
@@ -528,10 +668,14 @@ __device__ __forceinline__ void f_dots_fin(const double* __restrict__ partial, i
             __syncthreads();
             if (off <= 1e-28 * tot || off == 0.0) break;
             for (int step = 0; step < n2 - 1; ++step) {
+                // round-robin pairing: index 0 fixed, the others rotate
                 if (t < npair) {
                     const int pa = t, pb = n2 - 1 - t;
-                    int p = pa == 0 ? 0 : ((pa - 1 + step) % (n2 - 1)) + 1;
-                    int q = pb == 0 ? 0 : ((pb - 1 + step) % (n2 - 1)) + 1;
+                    int ia = pa - 1 + step, ib = pb - 1 + step;
+                    if (ia >= n2 - 1) ia -= n2 - 1;
+                    if (ib >= n2 - 1) ib -= n2 - 1;
+                    int p = pa == 0 ? 0 : ia + 1;
+                    int q = pb == 0 ? 0 : ib + 1;
                     if (p > q) { const int x = p; p = q; q = x; }
                     double c = 1.0, s = 0.0;
                     if (q < m) {
@@ -546,24 +690,33 @@ __device__ __forceinline__ void f_dots_fin(const double* __restrict__ partial, i
                     rc[t] = c; rs[t] = s; rp[t] = p; rq[t] = q;
                 }
                 __syncthreads();
-                for (int k = t; k < npair * m; k += kThreads) {   // rows: A <- J^T A
-                    const int pr = k / m, j = k % m;
-                    const int p = rp[pr], q = rq[pr];
-                    if (q >= m) continue;
-                    const double c = rc[pr], s = rs[pr];
-                    const double ap = A[p * MM + j], aq = A[q * MM + j];
-                    A[p * MM + j] = c * ap - s * aq;
-                    A[q * MM + j] = s * ap + c * aq;
+                // A <- J^T A J one 2 x 2 block per thread: the pairs are
+                // disjoint, so block (P1, P2) depends only on itself
+                for (int k = t; k < (MM / 2) * (MM / 2); k += kThreads) {
+                    const int b1 = k / (MM / 2), b2 = k % (MM / 2);
+                    if (b1 >= npair || b2 >= npair) continue;
+                    const int p1 = rp[b1], q1 = rq[b1], p2 = rp[b2], q2 = rq[b2];
+                    const bool v1 = q1 < m, v2 = q2 < m;
+                    const double c1 = rc[b1], s1 = rs[b1], c2 = rc[b2], s2 = rs[b2];
+                    if (s1 == 0.0 && s2 == 0.0) continue;
+                    const double app = A[p1 * MM + p2];
+                    const double apq = v2 ? A[p1 * MM + q2] : 0.0;
+                    const double aqp = v1 ? A[q1 * MM + p2] : 0.0;
+                    const double aqq = (v1 && v2) ? A[q1 * MM + q2] : 0.0;
+                    const double rpp = c1 * app - s1 * aqp, rpq = c1 * apq - s1 * aqq;
+                    const double rqp = s1 * app + c1 * aqp, rqq = s1 * apq + c1 * aqq;
+                    A[p1 * MM + p2] = c2 * rpp - s2 * rpq;
+                    if (v2) A[p1 * MM + q2] = s2 * rpp + c2 * rpq;
+                    if (v1) A[q1 * MM + p2] = c2 * rqp - s2 * rqq;
+                    if (v1 && v2) A[q1 * MM + q2] = s2 * rqp + c2 * rqq;
                 }
-                __syncthreads();
-                for (int k = t; k < npair * m; k += kThreads) {   // columns: A <- A J, Q <- Q J
-                    const int pr = k / m, i = k % m;
+                // Q <- Q J
+                for (int k = t; k < (MM / 2) * MM; k += kThreads) {
+                    const int pr = k / MM, i = k % MM;
+                    if (pr >= npair || i >= m) continue;
                     const int p = rp[pr], q = rq[pr];
-                    if (q >= m) continue;
+                    if (q >= m || rs[pr] == 0.0) continue;
                     const double c = rc[pr], s = rs[pr];
-                    const double ap = A[i * MM + p], aq = A[i * MM + q];
-                    A[i * MM + p] = c * ap - s * aq;
-                    A[i * MM + q] = s * ap + c * aq;
                     const double qp = Q[i * MM + p], qq = Q[i * MM + q];
                     Q[i * MM + p] = c * qp - s * qq;
                     Q[i * MM + q] = s * qp + c * qq;
@@ -572,6 +725,8 @@ __device__ __forceinline__ void f_dots_fin(const double* __restrict__ partial, i
             }
         }
     }
+    for (int k = t; k < MM * MM; k += kThreads) st->Qp[k] = Q[k];
+    if (t == 0) st->qn = m;
     if (t == 0) {
         int kmin = 0;
         for (int k = 1; k < m; ++k)
@@ -597,16 +752,25 @@ __device__ __forceinline__ void d_final(const double* __restrict__ V, int64_t n,
     __shared__ long long si[kThreads];
     double best = -1.0, nrm = 0.0;
     long long bi = -1;
-    for (int64_t i = (int64_t)bid * kThreads + threadIdx.x; i < n; i += (int64_t)nblk * kThreads) {
-        double x = 0.0;
+    with_rows<MT>(m, [&](auto nr_) {
+        constexpr int NR = decltype(nr_)::value;
+        double y[NR];
+        const double* vr[NR];
 #pragma unroll
-        for (int k = 0; k < MT; ++k)
-            if (k < m) x += st->y[k] * V[(int64_t)k * n + i];
-        out[i] = x;
-        nrm += x * x;
-        const double a = fabs(x);
-        if (a > best) { best = a; bi = i; }
-    }
+        for (int k = 0; k < NR; ++k) {
+            y[k] = (k < m) ? st->y[k] : 0.0;
+            vr[k] = row_ptr(V, k, m, n);
+        }
+        for (int64_t i = (int64_t)bid * kThreads + threadIdx.x; i < n; i += (int64_t)nblk * kThreads) {
+            double x = 0.0;
+#pragma unroll
+            for (int k = 0; k < NR; ++k) x += y[k] * vr[k][i];
+            out[i] = x;
+            nrm += x * x;
+            const double a = fabs(x);
+            if (a > best) { best = a; bi = i; }
+        }
+    });
     sv[threadIdx.x] = best; si[threadIdx.x] = bi; sn[threadIdx.x] = nrm;
     __syncthreads();
     for (int s = kThreads / 2; s > 0; s >>= 1) {

@@ -25,8 +25,12 @@ typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 
 template <typename T> struct mfma;
+// Accumulator layout (checked on gfx950): lane l, element q holds D[row][l % 16]
+// with row = 4 * (l / 16) + q for the f32 form but row = l / 16 + 4 * q for the
+// f64 form.  A[i][k] and B[k][j] come from lane i + 16 k and j + 16 k in both.
 template <> struct mfma<double> {
     using acc_t = d4_t;
+    static __device__ __forceinline__ int row(int lane, int q) { return (lane >> 4) + 4 * q; }
     static __device__ __forceinline__ acc_t zero() { return (acc_t){0.0, 0.0, 0.0, 0.0}; }
     static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -34,6 +38,7 @@ template <> struct mfma<double> {
 };
 template <> struct mfma<float> {
     using acc_t = f4_t;
+    static __device__ __forceinline__ int row(int lane, int q) { return 4 * (lane >> 4) + q; }
     static __device__ __forceinline__ acc_t zero() { return (acc_t){0.f, 0.f, 0.f, 0.f}; }
     static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -108,7 +113,7 @@ k_ab_kh(const T* __restrict__ C, T* __restrict__ Y, int64_t na, int64_t nb, cons
             // Y[rev(e)][jb'] = s_e * G[jb'][e]
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int t = w * 16 + 4 * (lane >> 4) + q;
+                const int t = w * 16 + M::row(lane, q);
                 const int64_t jb = jb0 + t;
                 if (jb < nb) {
                     const int n0 = lane & 15, n1 = 16 + (lane & 15);

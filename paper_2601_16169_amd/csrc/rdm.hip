@@ -25,6 +25,11 @@ inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
+// v_mfma_f64_16x16x4: A[i][k] from lane i + 16 k, B[k][j] from lane j + 16 k;
+// lane l, element q of the accumulator holds D[l / 16 + 4 q][l % 16] (checked on
+// gfx950; the f32 form of the same shape uses row 4 (l / 16) + q instead).
+__device__ __forceinline__ int acc_row(int lane, int q) { return (lane >> 4) + 4 * q; }
+
 // ---------------------------------------------------------------- P = A B^T
 // A: M x K, B: N x K (row-major, leading dimension K); P: M x N.  64 x 64
 // block tile, four waves of 32 x 32 (2 x 2 MFMA tiles), K steps of 16 in LDS.
@@ -69,7 +74,7 @@ k_gemm_nt(const double* __restrict__ A, const double* __restrict__ B, double* __
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int64_t r = m0 + wm + i * 16 + 4 * (lane >> 4) + q;
+                const int64_t r = m0 + wm + i * 16 + acc_row(lane, q);
                 const int64_t c = n0 + wn + j * 16 + (lane & 15);
                 if (r < M && c < N) P[r * N + c] = acc[i][j][q];
             }
@@ -262,7 +267,7 @@ k_rdm_ab(const double* __restrict__ C, int64_t na, int64_t nb, const uint64_t* _
                     const int ut = tile & 1, nt = tile >> 1;
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
-                        const int u = u0 + ut * 16 + 4 * (lane >> 4) + q;
+                        const int u = u0 + ut * 16 + acc_row(lane, q);
                         const int rs = n0 + nt * 16 + (lane & 15);
                         const double v = acc[t][q];
                         if (u < nu && rs < n2 && v != 0.0) {

@@ -154,7 +154,7 @@ k_ab_direct(const T* __restrict__ C, T* __restrict__ S, int64_t na, int64_t nb, 
                 v = V[(int64_t)pair * norb2 + pq];
                 if (e >> 31) v = -v;
             }
-            vs[pq * KC + k] = v;
+            vs[lds_cols<T, KC>::idx(pq, k)] = v;
         }
         __syncthreads();
 #pragma unroll
@@ -167,8 +167,9 @@ k_ab_direct(const T* __restrict__ C, T* __restrict__ S, int64_t na, int64_t nb, 
                     const uint32_t e = bs_pk[(int64_t)col * 64 + lane];
                     const int nbr = (int)(e & SQD_NBR_MASK);
                     const int pair = (int)((e >> SQD_PAIR_SHIFT) & SQD_PAIR_MASK);
-                    const T* cr = cs + (int64_t)nbr * KC;
-                    const T* vr = vs + pair * KC;
+                    T cr[KC], vr[KC];
+                    lds_cols<T, KC>::load(cs, nbr, cr);
+                    lds_cols<T, KC>::load(vs, pair, vr);
                     T t = (T)0;
 #pragma unroll
                     for (int k = 0; k < KC; ++k) t += vr[k] * cr[k];
@@ -206,10 +207,11 @@ k_ab_grouped(abg_args<T> a, const T* __restrict__ V, int norb, const int* __rest
 // sigma[ia][jb] += sum_{e = a_off[ia]}^{a_off[ia+1]-1} Y[e][jb]
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_ab_gather(const T* __restrict__ Y, T* __restrict__ S, int64_t na, int64_t nb, const int* __restrict__ a_off,
-            const int* __restrict__ skip) {
+k_ab_gather(const T* __restrict__ Y, T* __restrict__ S, int64_t na, int64_t nb, int64_t ldy,
+            const int* __restrict__ bperm, const int* __restrict__ a_off, const int* __restrict__ skip) {
     if (skip && *skip) return;
-    for (int64_t ia = blockIdx.y; ia < na; ia += gridDim.y) gather_block<T>(Y, S, nb, a_off, ia, blockIdx.x);
+    for (int64_t ia = blockIdx.y; ia < na; ia += gridDim.y)
+        gather_block<T>(Y, S, nb, ldy, bperm, a_off, ia, blockIdx.x);
 }
 
 constexpr int kAbMaxJ = 8;
@@ -365,7 +367,7 @@ size_t ab_grouped_bytes(sqd_ctx* ctx, const sqd_space* sp, size_t es) {
     const int variant = ctx->tune[SQD_TUNE_AB_VARIANT];
     if (variant == 2) return 0;
     if (ab_group_size(ctx, sp) == 0) return 0;
-    const size_t bytes = (size_t)sp->sp[0].nnz_s * (size_t)sp->sp[1].n * es;
+    const size_t bytes = (size_t)sp->sp[0].nnz_s * (size_t)sp->sp[1].nslices * 64 * es;
     const size_t cap = (size_t)64 << 30;   // keep the intermediate below 64 GiB
     if (variant == 0 && bytes > cap) return 0;
     return bytes + 256;
@@ -381,8 +383,8 @@ int launch_ab_grouped(sqd_ctx* ctx, sqd_space* sp, const T* C, T* S, T* Y, const
     if (sp->ab_nchunks > 0) {
         const int nw = ctx->tune[SQD_TUNE_AB_WAVES] ? ctx->tune[SQD_TUNE_AB_WAVES] : 16;
         const size_t lds = ((size_t)(B.n + 1) * G + (size_t)sp->norb * sp->norb) * sizeof(T);
-        abg_args<T> args{C, Y, B.n, sp->ab_grp, sp->ab_chunk_pair, A.s_pk, B.perm_ab, B.nslices, B.sl_ab_off,
-                         B.sell_ab_pk};
+        abg_args<T> args{C, Y, B.n, (int64_t)B.nslices * 64, sp->ab_grp, sp->ab_chunk_pair, A.s_pk, B.perm_ab,
+                         B.nslices, B.sl_ab_off, B.sell_ab_pk};
         prof_scope ps(ctx, sizeof(T) == 8 ? "k_ab_grouped<double>" : "k_ab_grouped<float>");
 #define SQD_ABG_LAUNCH(GG)                                                                                   \
     case GG:                                                                                                 \
@@ -400,8 +402,9 @@ int launch_ab_grouped(sqd_ctx* ctx, sqd_space* sp, const T* C, T* S, T* Y, const
     }
     const unsigned gy = (unsigned)(A.n < 65535 ? A.n : 65535);
     prof_scope ps(ctx, sizeof(T) == 8 ? "k_ab_gather<double>" : "k_ab_gather<float>");
-    hipLaunchKernelGGL((k_ab_gather<T>), dim3(nblk(B.n, 256), gy), dim3(256), 0, ctx->stream, Y, S, A.n, B.n,
-                       A.s_off, skip);
+    const int64_t ldy = (int64_t)B.nslices * 64;
+    hipLaunchKernelGGL((k_ab_gather<T>), dim3(nblk(ldy, 256), gy), dim3(256), 0, ctx->stream, Y, S, A.n, B.n, ldy,
+                       B.perm_ab, A.s_off, skip);
     SQD_HIP(ctx, hipGetLastError());
     return SQD_OK;
 }

@@ -6,11 +6,46 @@
 
 #include "sqd_internal.h"
 
+// LDS layout of R values per column c (staged rows of C, or rows of the
+// cross-spin table): column c owns R * sizeof(T) bytes at c * R.  Lanes read
+// whole columns at random c in 16-byte pieces; when a column is two or four
+// 16-byte pieces, the pieces are stored XOR-permuted by bits of c above those
+// that already select the bank group, so that for any piece index the 64
+// lanes spread over all LDS banks instead of a quarter or half of them.
+template <typename T, int R>
+struct lds_cols {
+    static constexpr int kE = 16 / (int)sizeof(T);                 // elements per 16-byte piece
+    static constexpr int kU = (R * (int)sizeof(T)) / 16;           // pieces per column (0: under 16 bytes)
+    static constexpr bool kSwz = (kU == 2 || kU == 4);
+    __device__ static __forceinline__ int swz(int64_t c) {
+        return kU == 4 ? (int)((c >> 2) & 3) : (int)((c >> 3) & 1);
+    }
+    __device__ static __forceinline__ int64_t idx(int64_t c, int r) {
+        if constexpr (kSwz) return c * R + (((r / kE) ^ swz(c)) * kE) + (r % kE);
+        else return c * R + r;
+    }
+    __device__ static __forceinline__ void load(const T* __restrict__ xs, int64_t c, T (&v)[R]) {
+        if constexpr (kSwz) {
+            const int f = swz(c);
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const T* src = xs + c * R + ((u ^ f) * kE);
+#pragma unroll
+                for (int w = 0; w < kE; ++w) v[u * kE + w] = src[w];
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[r] = xs[c * R + r];
+        }
+    }
+};
+
 // Stage R rows of length ncols (row r starts at rows[r], or zeros when null)
-// into LDS as xs[col*R + r]; two columns per iteration so 2R independent
-// global loads are in flight per thread, stored as R contiguous values.
+// into LDS in the lds_cols<T, R> layout; two columns per iteration so 2R
+// independent global loads are in flight per thread.  Column ncols is zero.
 template <typename T, int R>
 __device__ __forceinline__ void stage_rows(T* __restrict__ xs, const T* const (&rows)[R], int ncols) {
+    using L = lds_cols<T, R>;
     const int tid = threadIdx.x, nthr = blockDim.x;
     int col = tid;
     for (; col + nthr < ncols; col += 2 * nthr) {
@@ -22,15 +57,15 @@ __device__ __forceinline__ void stage_rows(T* __restrict__ xs, const T* const (&
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            xs[col * R + r] = a[r];
-            xs[(col + nthr) * R + r] = b[r];
+            xs[L::idx(col, r)] = a[r];
+            xs[L::idx(col + nthr, r)] = b[r];
         }
     }
     for (; col < ncols; col += nthr) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) xs[col * R + r] = rows[r] ? rows[r][col] : (T)0;
+        for (int r = 0; r < R; ++r) xs[L::idx(col, r)] = rows[r] ? rows[r][col] : (T)0;
     }
-    if (tid < R) xs[ncols * R + tid] = (T)0;
+    if (tid < R) xs[(int64_t)ncols * R + tid] = (T)0;
 }
 
 // ---------------------------------------------------------------- same spin
@@ -78,7 +113,7 @@ __device__ __forceinline__ void ss_block(const ss_args<T>& a, const T* __restric
         if (row < nrows)
             for (uint64_t x = a.row_str[row]; x; x &= x - 1)
                 acc += jk[(__ffsll((unsigned long long)x) - 1) * norb2 + pq];
-        ws[pq * R + r] = acc;
+        ws[lds_cols<T, R>::idx(pq, r)] = acc;
     }
     __syncthreads();
     const int wave = tid >> 6, lane = tid & 63, nw = nthr >> 6;
@@ -90,14 +125,12 @@ __device__ __forceinline__ void ss_block(const ss_args<T>& a, const T* __restric
         auto single = [&](uint32_t e, T v) {
             const int nbr = (int)(e & SQD_NBR_MASK);
             const int pair = (int)((e >> SQD_PAIR_SHIFT) & SQD_PAIR_MASK);
-            const T* xr = xs + (int64_t)nbr * R;
-            const T* wr = ws + pair * R;
+            T xr[R], wr[R];
+            lds_cols<T, R>::load(xs, nbr, xr);
+            lds_cols<T, R>::load(ws, pair, wr);
             const bool neg = (e >> 31) != 0;
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const T w = wr[r];
-                acc[r] += (v + (neg ? -w : w)) * xr[r];
-            }
+            for (int r = 0; r < R; ++r) acc[r] += (v + (neg ? -wr[r] : wr[r])) * xr[r];
         };
         int k = s0;
         for (; k + 4 <= s1; k += 4) {   // four table entries in flight
@@ -114,7 +147,8 @@ __device__ __forceinline__ void ss_block(const ss_args<T>& a, const T* __restric
         for (; k < s1; ++k) single(a.s_pk[(int64_t)k * 64 + lane], a.s_val[(int64_t)k * 64 + lane]);
         const int d0 = a.sl_d_off[sl], d1 = a.sl_d_off[sl + 1];
         auto dbl = [&](int nbr, T v) {
-            const T* xr = xs + (int64_t)nbr * R;
+            T xr[R];
+            lds_cols<T, R>::load(xs, nbr, xr);
 #pragma unroll
             for (int r = 0; r < R; ++r) acc[r] += v * xr[r];
         };
@@ -139,7 +173,7 @@ __device__ __forceinline__ void ss_block(const ss_args<T>& a, const T* __restric
                 if (row < nrows) {
                     const int64_t o = row * ncols + t;
                     T val = acc[r];
-                    if (a.diag) val += (T)(a.diag[o] * (double)xs[(int64_t)t * R + r]);
+                    if (a.diag) val += (T)(a.diag[o] * (double)xs[lds_cols<T, R>::idx(t, r)]);
                     if (a.accumulate) val += a.Y[o];
                     a.Y[o] = val;
                 }
@@ -152,14 +186,17 @@ __device__ __forceinline__ void ss_block(const ss_args<T>& a, const T* __restric
 // The alpha single entries e (CSR position in the target row's list; source
 // row src(e), pair ai(e), sign s(e)) are grouped by pair ai and cut into chunks
 // of G entries that share ai.  One unit per chunk stages the G source rows of C
-// in LDS ([col][r]) and the row (ai|..) of the (pq|rs) matrix, then walks the
-// sliced beta singles table once for all G rows:
-//   Y[e][jb'] = s(e) * sum_{beta singles jb' <- jb (pair bj, s_b)} s_b (ai|bj) C[src(e)][jb]
+// in LDS (lds_cols layout) and the row (ai|..) of the (pq|rs) matrix, then
+// walks the sliced beta singles table once for all G rows:
+//   Y[e][slot(jb')] = s(e) * sum_{beta singles jb' <- jb (pair bj, s_b)} s_b (ai|bj) C[src(e)][jb]
+// Y is written in slot order (slice * 64 + lane), so each wave stores 64
+// consecutive values; the gather maps slots back to beta strings.
 template <typename T>
 struct abg_args {
     const T* C;
-    T* Y;
+    T* Y;                     // nnz_alpha_singles x ldy, columns in sliced (slot) order
     int64_t nb;
+    int64_t ldy;              // 64 x number of beta slices
     const int* grp;           // chunks x G CSR positions (-1 = padding)
     const int* chunk_pair;
     const uint32_t* a_pk;     // alpha singles (gather form)
@@ -204,42 +241,54 @@ __device__ __forceinline__ void abg_block(const abg_args<T>& a, const T* __restr
             const int pb = (int)((b >> SQD_PAIR_SHIFT) & SQD_PAIR_MASK);
             T v = vrow[pb];
             if (b >> 31) v = -v;
-            const T* xr = xs + (int64_t)nbr * G;
+            T xr[G];
+            lds_cols<T, G>::load(xs, nbr, xr);
 #pragma unroll
             for (int r = 0; r < G; ++r) acc[r] += v * xr[r];
         };
         int col = c0;
-        for (; col + 4 <= c1; col += 4) {   // four table entries in flight
+        for (; col + 8 <= c1; col += 8) {   // eight table entries in flight
+            uint32_t b8[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) b8[u] = a.bs_pk[(int64_t)(col + u) * 64 + lane];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) one(b8[u]);
+        }
+        if (col + 4 <= c1) {
             uint32_t b4[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) b4[u] = a.bs_pk[(int64_t)(col + u) * 64 + lane];
 #pragma unroll
             for (int u = 0; u < 4; ++u) one(b4[u]);
+            col += 4;
         }
         for (; col < c1; ++col) one(a.bs_pk[(int64_t)col * 64 + lane]);
-        const int tb = a.bperm[sl * 64 + lane];
-        if (tb < nb) {
+        // padding lanes read only the zero column: their value is zero
+        const int64_t slot = (int64_t)sl * 64 + lane;
 #pragma unroll
-            for (int r = 0; r < G; ++r)
-                if (e[r] >= 0) a.Y[(int64_t)e[r] * nb + tb] = sgn[r] * acc[r];
-        }
+        for (int r = 0; r < G; ++r)
+            if (e[r] >= 0) a.Y[(int64_t)e[r] * a.ldy + slot] = sgn[r] * acc[r];
     }
 }
 
-// sigma[ia][jb] += sum_{e in row ia} Y[e][jb] for the 256 columns jb of block jblk.
+// sigma[ia][perm(p)] += sum_{e in row ia} Y[e][p] for the 256 slots p of block
+// jblk (coalesced reads of Y; slots of padding lanes are skipped).
 template <typename T>
-__device__ __forceinline__ void gather_block(const T* __restrict__ Y, T* __restrict__ S, int64_t nb,
-                                             const int* __restrict__ a_off, int64_t ia, int64_t jblk) {
-    const int64_t jb = jblk * blockDim.x + threadIdx.x;
-    if (jb >= nb) return;
+__device__ __forceinline__ void gather_block(const T* __restrict__ Y, T* __restrict__ S, int64_t nb, int64_t ldy,
+                                             const int* __restrict__ bperm, const int* __restrict__ a_off,
+                                             int64_t ia, int64_t jblk) {
+    const int64_t p = jblk * blockDim.x + threadIdx.x;
+    if (p >= ldy) return;
+    const int tb = bperm[p];
+    if (tb >= nb) return;
     const int e0 = a_off[ia], e1 = a_off[ia + 1];
     T acc = (T)0;
     int e = e0;
     for (; e + 3 < e1; e += 4)
-        acc += (Y[(int64_t)e * nb + jb] + Y[(int64_t)(e + 1) * nb + jb]) +
-               (Y[(int64_t)(e + 2) * nb + jb] + Y[(int64_t)(e + 3) * nb + jb]);
-    for (; e < e1; ++e) acc += Y[(int64_t)e * nb + jb];
-    S[ia * nb + jb] += acc;
+        acc += (Y[(int64_t)e * ldy + p] + Y[(int64_t)(e + 1) * ldy + p]) +
+               (Y[(int64_t)(e + 2) * ldy + p] + Y[(int64_t)(e + 3) * ldy + p]);
+    for (; e < e1; ++e) acc += Y[(int64_t)e * ldy + p];
+    S[ia * nb + tb] += acc;
 }
 
 // out[c][r] (=|+=) in[r][c] for the 64 x 64 tile (ty, tx); in is rows x cols.

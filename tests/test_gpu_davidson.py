@@ -136,7 +136,18 @@ def test_cfg2_against_stored_oracle(ctx, mode):
     xv = x.cpu().numpy()
     idx = np.array(gold["top_index"])
     ref = np.array(gold["top_value"])
-    assert np.abs(xv[idx] - ref).max() <= (1e-7 if mode == 0 else 1e-5)
+    # Phase: the largest-magnitude entry is positive.  When the two largest
+    # magnitudes agree to within the solver tolerance (a flip-odd state puts
+    # equal weight on (ia, ib) and (ib, ia)), either choice satisfies the rule,
+    # so the vectors are compared up to that one global sign and the rule is
+    # checked on the GPU vector itself.
+    k = int(np.argmax(np.abs(xv)))
+    assert xv[k] > 0
+    mag = np.abs(ref)
+    sgn = 1.0
+    if mag[0] - mag[1] <= 1e-6 * mag[0]:
+        sgn = float(np.sign(xv[idx] @ ref))
+    assert np.abs(sgn * xv[idx] - ref).max() <= (1e-7 if mode == 0 else 1e-5)
     rows = np.unique(np.concatenate([idx[:64], np.random.default_rng(3).choice(sp.dim, 512, replace=False)]))
     hx = core.Space.from_problem(p).sigma_rows(xv, rows)
     assert np.abs(hx - E * xv[rows]).max() <= 1e-7
