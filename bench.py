@@ -255,8 +255,10 @@ def _traffic(name):
     src = vals.get("source")
     if not src or "bytes_per_launch" not in vals:
         return None
-    h = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()[:16]
-    if h != vals.get("source_sha256"):
+    h = hashlib.sha256()
+    for f in src.split():
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest()[:16] != vals.get("source_sha256"):
         return None
     return float(vals["bytes_per_launch"])
 

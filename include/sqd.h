@@ -90,7 +90,8 @@ extern "C" {
 #define SQD_TUNE_AB_VARIANT 6  /* direct alpha-beta kernel: 1 grouped by alpha pair (with an
                                   intermediate of nnz_singles_alpha x nb values and a gather),
                                   2 staged per target row (no intermediate); 0 = auto */
-#define SQD_TUNE_COUNT 7
+#define SQD_TUNE_AB_GROUP 7    /* alpha singles per grouped alpha-beta unit: 1,2,4,8 (0 = auto) */
+#define SQD_TUNE_COUNT 8
 
 typedef struct sqd_ctx sqd_ctx;      /* opaque, library-owned */
 typedef struct sqd_space sqd_space;  /* opaque, library-owned */

@@ -135,7 +135,7 @@ int sqd_set_tuning(sqd_ctx* ctx, int key, int value) {
     if (key < 0 || key >= SQD_TUNE_COUNT) return sqd_fail(ctx, SQD_E_INVALID_ARG, "unknown tuning key");
     static const int allowed[SQD_TUNE_COUNT][5] = {
         {0, 1, 2, 4, 8}, {0, 1, 2, 4, 8}, {0, 4, 8, 16, -1}, {0, 4, 8, 16, -1}, {0, 1, 2, -1, -1}, {0, 32, 64, -1, -1},
-        {0, 1, 2, -1, -1}};
+        {0, 1, 2, -1, -1}, {0, 1, 2, 4, 8}};
     bool ok = false;
     for (int v : allowed[key]) ok |= (v == value);
     if (!ok) return sqd_fail(ctx, SQD_E_INVALID_ARG, "tuning value not allowed for key " + std::to_string(key));

@@ -36,7 +36,6 @@ struct bdesc {
     int nblk;        // vector-kernel blocks of this space
     int part0;       // first partial row
     int ntx, nty;    // transpose tiles of C (na x nb): x over nb, y over na
-    int njb;         // gather blocks per alpha row
     double* V;
     double* AV;
     double* T;
@@ -136,15 +135,17 @@ __global__ void __launch_bounds__(256) kb_transpose(const bdesc* __restrict__ D,
     }
 }
 
-template <typename T>
+// One unit per (space, alpha row); STAGED: rows assembled in LDS (gather_row).
+template <typename T, bool STAGED>
 __global__ void __launch_bounds__(256) kb_gather(const bdesc* __restrict__ D, const int2* __restrict__ units, int nunits) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    T* row = STAGED ? reinterpret_cast<T*>(lds_raw) : nullptr;
     for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
         const bdesc& d = D[units[u].x];
         if (d.st->done) continue;
-        const int t = units[u].y;
         const T* Y = (const T*)(sizeof(T) == 8 ? (const void*)d.Y64 : (const void*)d.Y32);
         T* S = (T*)(sizeof(T) == 8 ? (void*)d.sout : (void*)d.S32);
-        gather_block<T>(Y, S, d.nb, d.ab64.ldy, d.ab64.bperm, d.a_off, t / d.njb, t % d.njb);
+        gather_row<T>(Y, S, d.nb, d.ab64.ldy, d.ab64.bperm, d.a_off, units[u].y, row);
     }
 }
 
@@ -335,6 +336,7 @@ struct batch_plan {
     std::vector<void*> allocs;
     int R = 0, G = 0, Rf = 0;
     size_t lds_ss64 = 0, lds_ss32 = 0, lds_ab64 = 0, lds_ab32 = 0;
+    size_t gather_lds64 = 0;   // FP64 row bytes of the staged gather (0: in-place gather)
     int grid_persist = 0;
 };
 
@@ -377,7 +379,12 @@ int batched_sigma(sqd_ctx* ctx, batch_plan& p, hipStream_t s, int prec, int nw_s
                            p.counters + 1, ctx->jk64, norb);
         hipLaunchKernelGGL((kb_ab_grouped<double, G>), gp, dim3(64 * nw_ab), p.lds_ab64, s, p.D, p.abg.dev, p.abg.n,
                            p.counters + 2, ctx->eri, norb);
-        hipLaunchKernelGGL((kb_gather<double>), sgrid(p.gath.n), dim3(256), 0, s, p.D, p.gath.dev, p.gath.n);
+        if (p.gather_lds64)
+            hipLaunchKernelGGL((kb_gather<double, true>), sgrid(p.gath.n), dim3(256), p.gather_lds64, s, p.D,
+                               p.gath.dev, p.gath.n);
+        else
+            hipLaunchKernelGGL((kb_gather<double, false>), sgrid(p.gath.n), dim3(256), 0, s, p.D, p.gath.dev,
+                               p.gath.n);
     } else {
         hipLaunchKernelGGL((kb_transpose<float>), sgrid(p.tr.n), dim3(256), 0, s, p.D, 0, p.tr.dev, p.tr.n);
         hipLaunchKernelGGL((kb_same_spin<float, RF>), gp, dim3(64 * nw_ss), p.lds_ss32, s, p.D, 1, p.ss_aa.dev,
@@ -387,7 +394,12 @@ int batched_sigma(sqd_ctx* ctx, batch_plan& p, hipStream_t s, int prec, int nw_s
                            p.ss_bb.n, p.counters + 4, ctx->jk32, norb);
         hipLaunchKernelGGL((kb_ab_grouped<float, G>), gp, dim3(64 * nw_ab), p.lds_ab32, s, p.D, p.abg.dev, p.abg.n,
                            p.counters + 5, ctx->eri32, norb);
-        hipLaunchKernelGGL((kb_gather<float>), sgrid(p.gath.n), dim3(256), 0, s, p.D, p.gath.dev, p.gath.n);
+        if (p.gather_lds64)
+            hipLaunchKernelGGL((kb_gather<float, true>), sgrid(p.gath.n), dim3(256), p.gather_lds64 / 2, s, p.D,
+                               p.gath.dev, p.gath.n);
+        else
+            hipLaunchKernelGGL((kb_gather<float, false>), sgrid(p.gath.n), dim3(256), 0, s, p.D, p.gath.dev,
+                               p.gath.n);
         hipLaunchKernelGGL(kb_combine, sgrid(p.vec.n), dim3(256), 0, s, p.D, p.vec.dev, p.vec.n);
     }
     return SQD_OK;
@@ -546,8 +558,9 @@ int pick_R(sqd_ctx* ctx, int64_t max_cols, int norb, size_t es, int forced) {
 }
 
 int pick_G(sqd_ctx* ctx, int64_t max_nb, int norb) {
-    for (int G : {8, 4, 2, 1})
-        if ((size_t)(max_nb + 1) * G * 8 + (size_t)norb * norb * 8 <= (size_t)ctx->max_lds) return G;
+    auto bytes = [&](int G) { return (size_t)(max_nb + 1) * G * 8 + (size_t)norb * norb * 8; };
+    for (int G : {8, 4, 2}) if (bytes(G) <= (size_t)ctx->max_lds / 2) return G;
+    for (int G : {8, 4, 2, 1}) if (bytes(G) <= (size_t)ctx->max_lds) return G;
     return 0;
 }
 
@@ -574,6 +587,7 @@ int sqd_davidson_batched_impl(sqd_ctx* ctx, int nspace, sqd_space* const* spaces
     p.lds_ss32 = ((size_t)(max_cols + 1) * p.R + (size_t)norb * norb * p.R) * 4;
     p.lds_ab64 = ((size_t)(max_nb + 1) * p.G + (size_t)norb * norb) * 8;
     p.lds_ab32 = ((size_t)(max_nb + 1) * p.G + (size_t)norb * norb) * 4;
+    p.gather_lds64 = (size_t)max_nb * 8 <= (size_t)(64 * 1024) ? (size_t)max_nb * 8 : 0;
     p.grid_persist = ctx->num_cu * 2;
     const bool mixed = o->mode == SQD_DAV_MIXED;
     const int mmax = o->m_max;
@@ -609,7 +623,7 @@ int sqd_davidson_batched_impl(sqd_ctx* ctx, int nspace, sqd_space* const* spaces
         d.ntx = (int)nblk(d.nb, 64);
         d.nty = (int)nblk(d.na, 64);
         const int64_t ldy = (int64_t)B.nslices * 64;
-        d.njb = (int)nblk(ldy, 256);
+
         PLAN_ALLOC(d.V, sizeof(double) * d.n * mmax);
         PLAN_ALLOC(d.AV, sizeof(double) * d.n * mmax);
         PLAN_ALLOC(d.T, sizeof(double) * d.n);
@@ -644,7 +658,7 @@ int sqd_davidson_batched_impl(sqd_ctx* ctx, int nspace, sqd_space* const* spaces
                                  B.nslices, B.sl_ab_off, B.sell_ab_pk};
         for (int j = 0; j < d.nblk; ++j) vec.push_back(make_int2(b, j));
         for (int t = 0; t < d.ntx * d.nty; ++t) tr.push_back(make_int2(b, t));
-        for (int64_t k = 0; k < d.na * d.njb; ++k) gath.push_back(make_int2(b, (int)k));
+        for (int64_t k = 0; k < d.na; ++k) gath.push_back(make_int2(b, (int)k));
         const double work = (double)(B.nnz_s + B.nnz_d) * A.n + (double)(A.nnz_s + A.nnz_d) * B.n +
                             (double)A.nnz_s * B.nnz_s;
         order.emplace_back(-work, b);

@@ -17,6 +17,7 @@ constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr int kMaxBlocks = 1024;
 constexpr int kPstride = MM + 4;   // partial sums per block
+constexpr int kStallWindow = 12;   // FP32 phase: iterations without a 10% better residual
 
 enum { DONE_RUNNING = 0, DONE_CONVERGED = 1, DONE_STALLED = 2, DONE_CAP = 3, DONE_SWITCH = 4 };
 
@@ -52,7 +53,7 @@ struct dav_state {
     int kmin;
     int nhist;
     int reortho;          // second Gram-Schmidt projection needed
-    int pad_;
+    int best_it;          // iteration of the smallest residual of the current phase
     int counter[8];       // last-block tickets, one per kernel kind
     double theta;
     double rnorm;
@@ -69,6 +70,7 @@ struct dav_state {
     double hist_e[SQD_HIST];
     int qn;               // Qp holds the eigenvectors of the leading qn x qn block of G (0: none)
     int pad2_;
+    double best_r;        // smallest residual of the current phase
     double Qp[MM * MM];
 };
 
@@ -305,11 +307,17 @@ __device__ __forceinline__ void f_res_fin(const double* __restrict__ partial, in
     }
     st->iter = it + 1;
     int done = DONE_RUNNING;
+    // smallest residual of this phase (a new best must improve by 10%)
+    if (it == st->phase_start || rn < 0.9 * st->best_r) {
+        st->best_r = rn;
+        st->best_it = it;
+    }
     if (st->phase == 0) {
         // FP32 phase: hand over to FP64 refinement below switch_tol, on
-        // reaching tol, or when the residual stops falling
-        const int inphase = st->iter - st->phase_start;
-        const bool stall = inphase >= 6 && it >= 5 && it - 5 < SQD_HIST && rn > 0.7 * st->hist_r[it - 5];
+        // reaching tol, or once the residual has not improved for
+        // kStallWindow iterations (the FP32 products' rounding floor; a
+        // Davidson residual is not monotone, so the window is long)
+        const bool stall = it - st->best_it >= kStallWindow;
         if (rn < prm.switch_tol || rn <= prm.tol || stall) done = DONE_SWITCH;
     } else if (rn <= prm.tol) {
         done = DONE_CONVERGED;

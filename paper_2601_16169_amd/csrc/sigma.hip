@@ -195,7 +195,7 @@ k_ab_direct(const T* __restrict__ C, T* __restrict__ S, int64_t na, int64_t nb, 
 
 // ---------------------------------------------------------------- alpha-beta, grouped by alpha pair
 // (body and layout: abg_block); a coalesced gather then adds
-// sigma[ia'][jb'] += sum_{e in row ia'} Y[e][jb'].
+// sigma[ia'][jb'] += sum_{e in row ia'} Y[e][slot(jb')].
 template <typename T, int G>
 __global__ void __launch_bounds__(1024)
 k_ab_grouped(abg_args<T> a, const T* __restrict__ V, int norb, const int* __restrict__ skip) {
@@ -204,15 +204,21 @@ k_ab_grouped(abg_args<T> a, const T* __restrict__ V, int norb, const int* __rest
     abg_block<T, G>(a, V, norb, blockIdx.x, lds_raw);
 }
 
-// sigma[ia][jb] += sum_{e = a_off[ia]}^{a_off[ia+1]-1} Y[e][jb]
-template <typename T>
+// sigma[ia][perm(p)] += sum_{e = a_off[ia]}^{a_off[ia+1]-1} Y[e][p] (gather_row),
+// one workgroup per alpha row; STAGED: the row is assembled in LDS first.
+template <typename T, bool STAGED>
 __global__ void __launch_bounds__(256)
 k_ab_gather(const T* __restrict__ Y, T* __restrict__ S, int64_t na, int64_t nb, int64_t ldy,
             const int* __restrict__ bperm, const int* __restrict__ a_off, const int* __restrict__ skip) {
     if (skip && *skip) return;
-    for (int64_t ia = blockIdx.y; ia < na; ia += gridDim.y)
-        gather_block<T>(Y, S, nb, ldy, bperm, a_off, ia, blockIdx.x);
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    T* row = STAGED ? reinterpret_cast<T*>(lds_raw) : nullptr;
+    for (int64_t ia = blockIdx.x; ia < na; ia += gridDim.x) gather_row<T>(Y, S, nb, ldy, bperm, a_off, ia, row);
 }
+
+// Longest alpha-beta output row assembled in LDS by the gather (larger rows are
+// added in place).
+constexpr int64_t kGatherStageBytes = 64 * 1024;
 
 constexpr int kAbMaxJ = 8;
 
@@ -239,7 +245,8 @@ int pick_rows(sqd_ctx* ctx, int64_t nrows, int64_t ncols, int norb, size_t es) {
         if (forced && R != forced) continue;
         const size_t lds = ((size_t)(ncols + 1) * R + (size_t)norb * norb * R) * es;
         if (lds > (size_t)ctx->max_lds) continue;
-        if (!forced && R > 1 && (nrows + R - 1) / R < ctx->num_cu) continue;
+        // enough row blocks to occupy (nearly) every compute unit
+        if (!forced && R > 1 && (nrows + R - 1) / R < (int64_t)ctx->num_cu * 9 / 10) continue;
         return R;
     }
     return 0;
@@ -263,7 +270,8 @@ int launch_same_spin(sqd_ctx* ctx, const T* X, T* Y, int64_t nrows, int64_t ncol
     const size_t es = sizeof(T);
     const int R = pick_rows(ctx, nrows, ncols, norb, es);
     if (R == 0) return sqd_fail(ctx, SQD_E_LIMIT, "same-spin row does not fit in LDS (too many strings)");
-    int nw = ctx->tune[SQD_TUNE_SS_WAVES] ? ctx->tune[SQD_TUNE_SS_WAVES] : 8;
+    // measured on MI355X: 16 waves hide the table latency best with 8 staged rows
+    int nw = ctx->tune[SQD_TUNE_SS_WAVES] ? ctx->tune[SQD_TUNE_SS_WAVES] : (R == 8 ? 16 : 8);
     const size_t lds = ((size_t)(ncols + 1) * R + (size_t)norb * norb * R) * es;
     const dim3 grid(nblk(nrows, R)), block(64 * nw);
     const T* sv = nullptr; const T* dv = nullptr;
@@ -325,8 +333,13 @@ int launch_ab_direct(sqd_ctx* ctx, const sqd_space* sp, const T* C, T* S, const 
 // C (FP64) that fit in LDS next to one row of (pq|rs).
 int ab_group_size(sqd_ctx* ctx, const sqd_space* sp) {
     const size_t nb = (size_t)sp->sp[1].n, n2 = (size_t)sp->norb * sp->norb;
-    for (int G : {8, 4, 2, 1})
-        if ((nb + 1) * G * sizeof(double) + n2 * sizeof(double) <= (size_t)ctx->max_lds) return G;
+    const int forced = ctx->tune[SQD_TUNE_AB_GROUP];
+    auto bytes = [&](int G) { return (nb + 1) * G * sizeof(double) + n2 * sizeof(double); };
+    if (forced) return bytes(forced) <= (size_t)ctx->max_lds ? forced : 0;
+    // largest group that leaves room for two workgroups per compute unit (one
+    // stages while the other computes), else the largest that fits
+    for (int G : {8, 4, 2}) if (bytes(G) <= (size_t)ctx->max_lds / 2) return G;
+    for (int G : {8, 4, 2, 1}) if (bytes(G) <= (size_t)ctx->max_lds) return G;
     return 0;
 }
 
@@ -381,7 +394,7 @@ int launch_ab_grouped(sqd_ctx* ctx, sqd_space* sp, const T* C, T* S, T* Y, const
     int rc = ensure_ab_groups_impl(ctx, sp, G);
     if (rc) return rc;
     if (sp->ab_nchunks > 0) {
-        const int nw = ctx->tune[SQD_TUNE_AB_WAVES] ? ctx->tune[SQD_TUNE_AB_WAVES] : 16;
+        const int nw = ctx->tune[SQD_TUNE_AB_WAVES] ? ctx->tune[SQD_TUNE_AB_WAVES] : (sizeof(T) == 8 ? 16 : 8);
         const size_t lds = ((size_t)(B.n + 1) * G + (size_t)sp->norb * sp->norb) * sizeof(T);
         abg_args<T> args{C, Y, B.n, (int64_t)B.nslices * 64, sp->ab_grp, sp->ab_chunk_pair, A.s_pk, B.perm_ab,
                          B.nslices, B.sl_ab_off, B.sell_ab_pk};
@@ -400,11 +413,17 @@ int launch_ab_grouped(sqd_ctx* ctx, sqd_space* sp, const T* C, T* S, T* Y, const
         }
 #undef SQD_ABG_LAUNCH
     }
-    const unsigned gy = (unsigned)(A.n < 65535 ? A.n : 65535);
+    const unsigned gx = (unsigned)std::min<int64_t>(A.n, 1 << 20);
     prof_scope ps(ctx, sizeof(T) == 8 ? "k_ab_gather<double>" : "k_ab_gather<float>");
     const int64_t ldy = (int64_t)B.nslices * 64;
-    hipLaunchKernelGGL((k_ab_gather<T>), dim3(nblk(ldy, 256), gy), dim3(256), 0, ctx->stream, Y, S, A.n, B.n, ldy,
-                       B.perm_ab, A.s_off, skip);
+    const int64_t row_bytes = B.n * (int64_t)sizeof(T);
+    if (A.n == 0 || B.n == 0) return SQD_OK;
+    if (row_bytes <= kGatherStageBytes)
+        hipLaunchKernelGGL((k_ab_gather<T, true>), dim3(gx), dim3(256), (size_t)row_bytes, ctx->stream, Y, S, A.n,
+                           B.n, ldy, B.perm_ab, A.s_off, skip);
+    else
+        hipLaunchKernelGGL((k_ab_gather<T, false>), dim3(gx), dim3(256), 0, ctx->stream, Y, S, A.n, B.n, ldy,
+                           B.perm_ab, A.s_off, skip);
     SQD_HIP(ctx, hipGetLastError());
     return SQD_OK;
 }

@@ -4,6 +4,8 @@
 // space described by an argument struct.
 #pragma once
 
+#include <type_traits>
+
 #include "sqd_internal.h"
 
 // LDS layout of R values per column c (staged rows of C, or rows of the
@@ -271,24 +273,51 @@ __device__ __forceinline__ void abg_block(const abg_args<T>& a, const T* __restr
     }
 }
 
-// sigma[ia][perm(p)] += sum_{e in row ia} Y[e][p] for the 256 slots p of block
-// jblk (coalesced reads of Y; slots of padding lanes are skipped).
+// sigma[ia][perm(p)] += sum_{e in row ia} Y[e][p] over all slots p of row ia,
+// one 256-thread workgroup per row: each thread reads two adjacent slots with
+// one vector load (ldy is a multiple of 64), eight rows of Y in flight.  With
+// `row` (LDS, nb values) the sums are placed by target first and the row of
+// sigma is then updated with coalesced accesses; without it (rows too long
+// for LDS) each sum is added in place.
 template <typename T>
-__device__ __forceinline__ void gather_block(const T* __restrict__ Y, T* __restrict__ S, int64_t nb, int64_t ldy,
-                                             const int* __restrict__ bperm, const int* __restrict__ a_off,
-                                             int64_t ia, int64_t jblk) {
-    const int64_t p = jblk * blockDim.x + threadIdx.x;
-    if (p >= ldy) return;
-    const int tb = bperm[p];
-    if (tb >= nb) return;
+__device__ __forceinline__ void gather_row(const T* __restrict__ Y, T* __restrict__ S, int64_t nb, int64_t ldy,
+                                           const int* __restrict__ bperm, const int* __restrict__ a_off, int64_t ia,
+                                           T* row) {
+    using T2 = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
     const int e0 = a_off[ia], e1 = a_off[ia + 1];
-    T acc = (T)0;
-    int e = e0;
-    for (; e + 3 < e1; e += 4)
-        acc += (Y[(int64_t)e * ldy + p] + Y[(int64_t)(e + 1) * ldy + p]) +
-               (Y[(int64_t)(e + 2) * ldy + p] + Y[(int64_t)(e + 3) * ldy + p]);
-    for (; e < e1; ++e) acc += Y[(int64_t)e * ldy + p];
-    S[ia * nb + tb] += acc;
+    T* srow = S + ia * nb;
+    for (int64_t p = 2 * (int64_t)threadIdx.x; p < ldy; p += 2 * (int64_t)blockDim.x) {
+        T a0 = (T)0, a1 = (T)0;
+        int e = e0;
+        for (; e + 8 <= e1; e += 8) {
+            T2 v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = *reinterpret_cast<const T2*>(Y + (int64_t)(e + u) * ldy + p);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                a0 += v[u].x;
+                a1 += v[u].y;
+            }
+        }
+        for (; e < e1; ++e) {
+            const T2 v = *reinterpret_cast<const T2*>(Y + (int64_t)e * ldy + p);
+            a0 += v.x;
+            a1 += v.y;
+        }
+        const int t0 = bperm[p], t1 = bperm[p + 1];
+        if (row) {
+            if (t0 < nb) row[t0] = a0;
+            if (t1 < nb) row[t1] = a1;
+        } else {
+            if (t0 < nb) srow[t0] += a0;
+            if (t1 < nb) srow[t1] += a1;
+        }
+    }
+    if (row) {
+        __syncthreads();
+        for (int64_t j = threadIdx.x; j < nb; j += blockDim.x) srow[j] += row[j];
+        __syncthreads();
+    }
 }
 
 // out[c][r] (=|+=) in[r][c] for the 64 x 64 tile (ty, tx); in is rows x cols.

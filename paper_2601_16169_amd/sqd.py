@@ -24,7 +24,8 @@ FP64, FP32 = 0, 1
 AB_AUTO, AB_DIRECT, AB_KH = 0, 1, 2
 DAV_FP64, DAV_MIXED = 0, 1
 SINGLES, DOUBLES = 0, 1
-TUNE_SS_ROWS, TUNE_AB_CHUNK, TUNE_AB_WAVES, TUNE_SS_WAVES, TUNE_AB_PATH, TUNE_KH_TILE, TUNE_AB_VARIANT = range(7)
+(TUNE_SS_ROWS, TUNE_AB_CHUNK, TUNE_AB_WAVES, TUNE_SS_WAVES, TUNE_AB_PATH, TUNE_KH_TILE, TUNE_AB_VARIANT,
+ TUNE_AB_GROUP) = range(8)
 MMAX, HIST = 32, 512
 
 ERRORS = {
