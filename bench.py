@@ -49,7 +49,7 @@ def main():
     ap.add_argument("--workload", default="cfg2")
     ap.add_argument("--no-davidson", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--profile-only", action="store_true",
                     help="only the timed sigma loop (for profilers)")
     a = ap.parse_args()

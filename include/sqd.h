@@ -114,7 +114,10 @@ typedef struct {
     int mode;                    /* SQD_DAV_FP64 or SQD_DAV_MIXED                */
     double switch_tol;           /* mixed: leave FP32 sigma when ||r|| < switch_tol */
     int ab_path;                 /* SQD_AB_*                                      */
-    const double* guess_noise_dev; /* optional (dim): start = e_argmin(H_II) + noise */
+    const double* guess_noise_dev; /* optional (dim): start = e_argmin(H_II) + noise; when both this
+                                      and guess_dev are NULL the library adds its own noise of norm
+                                      about 1e-3 (SplitMix64 counter stream 0), so that the start is
+                                      not confined to one spin-flip symmetry sector */
     const double* guess_dev;       /* optional (dim): explicit start vector; overrides */
     int check_every;             /* host polls the device convergence flag every k
                                     iterations (>= 1); iterations past convergence

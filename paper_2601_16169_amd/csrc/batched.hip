@@ -244,30 +244,17 @@ __global__ void __launch_bounds__(kThreads) kb_pick_fin(const bdesc* __restrict_
     const bdesc& d = D[blockIdx.x];
     f_pick_fin<MODE>(partial + (size_t)d.part0 * kPstride, d.nblk, d.st);
 }
-// SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): a counter-based 64-bit mix.
-__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
-    x += 0x9E3779B97F4A7C15ull;
-    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
-    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
-    return x ^ (x >> 31);
-}
-
-// Start vector of space b: e_kmin plus noise of norm about 1e-3 (uniform
-// entries of zero mean and variance 1e-6/n from SplitMix64 of (b, i)), so that
-// a guess with the spin-flip symmetry of an S_a = S_b space still reaches a
-// flip-odd lowest state; |V0|^2 partials.
+// Start vector of space b: e_kmin plus start_noise of counter stream b;
+// |V0|^2 partials.
 __global__ void __launch_bounds__(kThreads) kb_start(const bdesc* __restrict__ D, const int2* __restrict__ units,
                                                      int nunits, double* __restrict__ partial) {
     for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
         const int b = units[u].x;
         const bdesc& d = D[b];
         const int64_t kmin = d.st->kmin;
-        const double amp = 1e-3 * sqrt(3.0 / (double)d.n);
         double acc[1] = {0.0};
         for (int64_t i = (int64_t)units[u].y * kThreads + threadIdx.x; i < d.n; i += (int64_t)d.nblk * kThreads) {
-            const uint64_t r = splitmix64(((uint64_t)b << 40) ^ (uint64_t)i);
-            const double uni = (double)(r >> 11) * (1.0 / 9007199254740992.0);   // [0, 1)
-            const double v = (i == kmin ? 1.0 : 0.0) + amp * (2.0 * uni - 1.0);
+            const double v = (i == kmin ? 1.0 : 0.0) + start_noise((uint64_t)b, i, d.n);
             d.V[i] = v;
             acc[0] += v * v;
         }

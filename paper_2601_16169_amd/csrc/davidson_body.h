@@ -18,6 +18,8 @@ constexpr int kWaves = kThreads / 64;
 constexpr int kMaxBlocks = 1024;
 constexpr int kPstride = MM + 4;   // partial sums per block
 constexpr int kStallWindow = 12;   // FP32 phase: iterations without a 10% better residual
+constexpr double kStallFrom = 1e-4;  // ... counted once the residual is below this times |theta|
+constexpr double kFloor32 = 2e-6;    // 30 FP32 unit roundoffs: FP32 products carry no more digits
 
 enum { DONE_RUNNING = 0, DONE_CONVERGED = 1, DONE_STALLED = 2, DONE_CAP = 3, DONE_SWITCH = 4 };
 
@@ -203,6 +205,26 @@ __device__ __forceinline__ void f_pick_fin(const double* __restrict__ partial, i
 }
 
 // V[0] = start vector (explicit guess, or e_kmin + noise), and |V[0]|^2 partials.
+// SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): a counter-based 64-bit mix.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+// Entry i of the library's start noise for counter stream `stream`: uniform of
+// zero mean and variance 1e-6 / n, so the noise has norm about 1e-3.  It lets a
+// start on e_kmin, which has the spin-flip symmetry of an S_a = S_b space, reach
+// a lowest state of the other symmetry.
+__device__ __forceinline__ double start_noise(uint64_t stream, int64_t i, int64_t n) {
+    const uint64_t r = splitmix64((stream << 40) ^ (uint64_t)i);
+    const double uni = (double)(r >> 11) * (1.0 / 9007199254740992.0);   // [0, 1)
+    return 1e-3 * sqrt(3.0 / (double)n) * (2.0 * uni - 1.0);
+}
+
+// V0 = guess, or e_kmin + noise (the caller's, else start_noise stream 0);
+// |V0|^2 partials.
 __device__ __forceinline__ void d_start(const double* __restrict__ guess, const double* __restrict__ noise,
                                                     int64_t n, const dav_state* st, double* __restrict__ V0,
                                                     double* __restrict__ partial, int64_t bid, int64_t nblk) {
@@ -211,7 +233,7 @@ __device__ __forceinline__ void d_start(const double* __restrict__ guess, const 
     for (int64_t i = (int64_t)bid * kThreads + threadIdx.x; i < n; i += (int64_t)nblk * kThreads) {
         double v;
         if (guess) v = guess[i];
-        else v = (i == kmin ? 1.0 : 0.0) + (noise ? noise[i] : 0.0);
+        else v = (i == kmin ? 1.0 : 0.0) + (noise ? noise[i] : start_noise(0, i, n));
         V0[i] = v;
         acc[0] += v * v;
     }
@@ -314,11 +336,13 @@ __device__ __forceinline__ void f_res_fin(const double* __restrict__ partial, in
     }
     if (st->phase == 0) {
         // FP32 phase: hand over to FP64 refinement below switch_tol, on
-        // reaching tol, or once the residual has not improved for
-        // kStallWindow iterations (the FP32 products' rounding floor; a
-        // Davidson residual is not monotone, so the window is long)
-        const bool stall = it - st->best_it >= kStallWindow;
-        if (rn < prm.switch_tol || rn <= prm.tol || stall) done = DONE_SWITCH;
+        // reaching tol, below the FP32 floor (kFloor32 |theta|), or once the
+        // residual has not improved for kStallWindow iterations after falling
+        // below kStallFrom |theta| (a Davidson residual is not monotone: early
+        // plateaus and bumps are not the FP32 floor)
+        const double at = fabs(theta);
+        const bool stall = st->best_r < kStallFrom * at && it - st->best_it >= kStallWindow;
+        if (rn < prm.switch_tol || rn <= prm.tol || rn < kFloor32 * at || stall) done = DONE_SWITCH;
     } else if (rn <= prm.tol) {
         done = DONE_CONVERGED;
     }

@@ -152,3 +152,22 @@ def test_cfg2_against_stored_oracle(ctx, mode):
     hx = core.Space.from_problem(p).sigma_rows(xv, rows)
     assert np.abs(hx - E * xv[rows]).max() <= 1e-7
     sp.close()
+
+
+def test_default_start_reaches_flip_odd_ground_state(ctx):
+    """norb 6, 3+3, all strings, integral seed 9: the lowest state is odd under
+    the exchange of alpha and beta strings, which the start e_argmin(H_II) alone
+    (even) cannot reach.  With neither noise nor a guess passed, the library's
+    own start noise reaches it, in the single-space and the batched solver."""
+    need_gpu()
+    s = I.all_strings(6, 3)
+    p = I.Problem("flip_odd_6_3", I.make_integrals(6, 12, seed=9), 3, 3, s, s.copy())
+    sp = _space(ctx, p)
+    w = np.linalg.eigvalsh(core.Space.from_problem(p).dense())
+    E, x, rep = sp.davidson(tol=1e-10)
+    assert rep["converged"] and abs(E - w[0]) <= 1e-8, (E, w[:2])
+    xv = x.cpu().numpy().reshape(sp.na, sp.nb)
+    assert np.abs(xv + xv.T).max() <= 1e-8
+    Eb, _, reps, rc = ctx.davidson_batched([sp], tol=1e-10)
+    assert rc == 0 and abs(Eb[0] - w[0]) <= 1e-8
+    sp.close()
