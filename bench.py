@@ -231,7 +231,8 @@ def _algorithmic(name, info, sp):
     if name.startswith(("k_ab_grouped", "k_ab_direct", "k_ab_kh")):
         return "alu", 2.0 * t[3], "flop"
     if name.startswith("k_same_spin"):
-        return "alu", 2.0 * (t[1] + t[2]) / 2, "flop"
+        # [aa]: alpha-alpha launch (on C^T), [bb]: beta-beta launch
+        return "alu", 2.0 * (t[1] if name.endswith("[aa]") else t[2]), "flop"
     if name.startswith("k_ab_gather"):
         return "hbm", float(es) * (info["nnz_single"][0] * sp.nb + 2 * sp.dim), "byte"
     if name.startswith("k_transpose"):

@@ -154,6 +154,11 @@ int sqd_synchronize(sqd_ctx* ctx);
 /* Set a tuning parameter (SQD_TUNE_*); value 0 restores the automatic choice. */
 int sqd_set_tuning(sqd_ctx* ctx, int key, int value);
 int sqd_get_tuning(const sqd_ctx* ctx, int key, int* value);
+/* Free the device workspaces the context keeps between calls (the product
+ * and Davidson scratch, and the batched solver's arena, which holds every
+ * vector of every space of the last batch); the next call that needs them
+ * allocates them again.  Synchronises the context's stream. */
+int sqd_release_workspace(sqd_ctx* ctx);
 /* Per-kernel timers: while enabled, the single-space calls record HIP events
  * on the context's stream around each kernel they launch (the batched solver,
  * which replays captured graphs, records none). */

@@ -114,6 +114,10 @@ void sqd_destroy(sqd_ctx* ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     free_ham(ctx);
     if (ctx->scratch) (void)hipFree(ctx->scratch);
+    if (ctx->batch_arena) (void)hipFree(ctx->batch_arena);
+    if (ctx->batch_count_host) (void)hipHostFree(ctx->batch_count_host);
+    if (ctx->dav_arena) (void)hipFree(ctx->dav_arena);
+    if (ctx->dav_state_host) (void)hipHostFree(ctx->dav_state_host);
     for (auto& r : ctx->prof) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
@@ -140,6 +144,22 @@ int sqd_set_tuning(sqd_ctx* ctx, int key, int value) {
     for (int v : allowed[key]) ok |= (v == value);
     if (!ok) return sqd_fail(ctx, SQD_E_INVALID_ARG, "tuning value not allowed for key " + std::to_string(key));
     ctx->tune[key] = value;
+    return SQD_OK;
+}
+
+int sqd_release_workspace(sqd_ctx* ctx) {
+    if (!ctx) return SQD_E_INVALID_ARG;
+    SQD_HIP(ctx, hipSetDevice(ctx->device));
+    SQD_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (ctx->scratch) (void)hipFree(ctx->scratch);
+    if (ctx->batch_arena) (void)hipFree(ctx->batch_arena);
+    if (ctx->dav_arena) (void)hipFree(ctx->dav_arena);
+    ctx->scratch = nullptr;
+    ctx->scratch_bytes = 0;
+    ctx->batch_arena = nullptr;
+    ctx->batch_arena_bytes = 0;
+    ctx->dav_arena = nullptr;
+    ctx->dav_arena_bytes = 0;
     return SQD_OK;
 }
 

@@ -320,28 +320,11 @@ struct batch_plan {
     int* count_host = nullptr;
     double* partial = nullptr;
     dav_state* states = nullptr;
-    std::vector<void*> allocs;
     int R = 0, G = 0, Rf = 0;
     size_t lds_ss64 = 0, lds_ss32 = 0, lds_ab64 = 0, lds_ab32 = 0;
     size_t gather_lds64 = 0;   // FP64 row bytes of the staged gather (0: in-place gather)
     int grid_persist = 0;
 };
-
-int upload_units(sqd_ctx* ctx, std::vector<int2>& v, unit_list& out, std::vector<void*>& allocs) {
-    out.n = (int)v.size();
-    if (v.empty()) v.push_back(make_int2(0, 0));
-    int rc = sqd_alloc(ctx, (void**)&out.dev, sizeof(int2) * v.size(), nullptr);
-    if (rc) return rc;
-    allocs.push_back(out.dev);
-    SQD_HIP(ctx, hipMemcpy(out.dev, v.data(), sizeof(int2) * v.size(), hipMemcpyHostToDevice));
-    return SQD_OK;
-}
-
-void free_plan(batch_plan& p) {
-    for (void* a : p.allocs) (void)hipFree(a);
-    if (p.count_host) (void)hipHostFree(p.count_host);
-    p = batch_plan();
-}
 
 template <typename F>
 void lds_attr(F f, size_t bytes) {
@@ -403,8 +386,9 @@ int batched_run(sqd_ctx* ctx, batch_plan& p, const sqd_davidson_opts* o, double*
     prm.max_iter = o->max_iter;
     prm.m_max = o->m_max;
     prm.mixed = mixed;
-    const int nw_ss = ctx->tune[SQD_TUNE_SS_WAVES] ? ctx->tune[SQD_TUNE_SS_WAVES] : 8;
-    const int nw_ab = ctx->tune[SQD_TUNE_AB_WAVES] ? ctx->tune[SQD_TUNE_AB_WAVES] : 16;
+    const int nw_ss = ctx->tune[SQD_TUNE_SS_WAVES] ? ctx->tune[SQD_TUNE_SS_WAVES] : (R == 8 ? 16 : 8);
+    // measured on MI355X (the batched tuner's choice on 64 spaces of 200-3000 strings)
+    const int nw_ab = ctx->tune[SQD_TUNE_AB_WAVES] ? ctx->tune[SQD_TUNE_AB_WAVES] : 8;
     lds_attr(kb_same_spin<double, R>, p.lds_ss64);
     lds_attr(kb_same_spin<float, RF>, p.lds_ss32);
     lds_attr(kb_ab_grouped<double, G>, p.lds_ab64);
@@ -546,6 +530,8 @@ int pick_R(sqd_ctx* ctx, int64_t max_cols, int norb, size_t es, int forced) {
 
 int pick_G(sqd_ctx* ctx, int64_t max_nb, int norb) {
     auto bytes = [&](int G) { return (size_t)(max_nb + 1) * G * 8 + (size_t)norb * norb * 8; };
+    const int forced = ctx->tune[SQD_TUNE_AB_GROUP];
+    if (forced) return bytes(forced) <= (size_t)ctx->max_lds ? forced : 0;
     for (int G : {8, 4, 2}) if (bytes(G) <= (size_t)ctx->max_lds / 2) return G;
     for (int G : {8, 4, 2, 1}) if (bytes(G) <= (size_t)ctx->max_lds) return G;
     return 0;
@@ -578,18 +564,13 @@ int sqd_davidson_batched_impl(sqd_ctx* ctx, int nspace, sqd_space* const* spaces
     p.grid_persist = ctx->num_cu * 2;
     const bool mixed = o->mode == SQD_DAV_MIXED;
     const int mmax = o->m_max;
-    auto alloc = [&](void** ptr, size_t bytes) -> int {
-        int r = sqd_alloc(ctx, ptr, bytes, nullptr);
-        if (!r) p.allocs.push_back(*ptr);
-        return r;
-    };
-#define PLAN_ALLOC(ptr, bytes)                                 \
-    do {                                                       \
-        if ((rc = alloc((void**)&(ptr), (bytes)))) {           \
-            free_plan(p);                                      \
-            return rc;                                         \
-        }                                                      \
-    } while (0)
+    // Every device buffer of the plan is a slice of one arena that the context
+    // keeps (grown on demand) across calls: a batch of dozens of spaces needs
+    // hundreds of buffers, and allocating and freeing them per call costs more
+    // than a short solve.  Slices are requested first and bound to the arena
+    // once its size is known.
+    std::vector<std::pair<void**, size_t>> req;
+    auto want = [&](void** ptr, size_t bytes) { req.push_back({ptr, bytes}); };
     p.host.resize(nspace);
     int part = 0;
     std::vector<int2> vec, tr, ssbb, ssaa, abg, gath;
@@ -598,7 +579,7 @@ int sqd_davidson_batched_impl(sqd_ctx* ctx, int nspace, sqd_space* const* spaces
         sqd_space* sp = spaces[b];
         const spin_tables& A = sp->sp[0];
         const spin_tables& B = sp->sp[1];
-        if ((rc = sqd_ensure_ab_groups(ctx, sp, p.G))) { free_plan(p); return rc; }
+        if ((rc = sqd_ensure_ab_groups(ctx, sp, p.G))) return rc;
         bdesc& d = p.host[b];
         std::memset(&d, 0, sizeof(d));
         d.n = sp->dim;
@@ -610,26 +591,80 @@ int sqd_davidson_batched_impl(sqd_ctx* ctx, int nspace, sqd_space* const* spaces
         d.ntx = (int)nblk(d.nb, 64);
         d.nty = (int)nblk(d.na, 64);
         const int64_t ldy = (int64_t)B.nslices * 64;
-
-        PLAN_ALLOC(d.V, sizeof(double) * d.n * mmax);
-        PLAN_ALLOC(d.AV, sizeof(double) * d.n * mmax);
-        PLAN_ALLOC(d.T, sizeof(double) * d.n);
-        PLAN_ALLOC(d.cin, sizeof(double) * d.n);
-        PLAN_ALLOC(d.sout, sizeof(double) * d.n);
-        PLAN_ALLOC(d.Ct, sizeof(double) * d.n);
-        PLAN_ALLOC(d.Yt, sizeof(double) * d.n);
-        PLAN_ALLOC(d.Y64, sizeof(double) * (A.nnz_s * ldy + 1));
+        want((void**)&d.V, sizeof(double) * d.n * mmax);
+        want((void**)&d.AV, sizeof(double) * d.n * mmax);
+        want((void**)&d.T, sizeof(double) * d.n);
+        want((void**)&d.cin, sizeof(double) * d.n);
+        want((void**)&d.sout, sizeof(double) * d.n);
+        want((void**)&d.Ct, sizeof(double) * d.n);
+        want((void**)&d.Yt, sizeof(double) * d.n);
+        want((void**)&d.Y64, sizeof(double) * (A.nnz_s * ldy + 1));
         if (mixed) {
-            PLAN_ALLOC(d.c32, sizeof(float) * d.n);
-            PLAN_ALLOC(d.Ct32, sizeof(float) * d.n);
-            PLAN_ALLOC(d.Yt32, sizeof(float) * d.n);
-            PLAN_ALLOC(d.S32, sizeof(float) * d.n);
-            PLAN_ALLOC(d.Y32, sizeof(float) * (A.nnz_s * ldy + 1));
+            want((void**)&d.c32, sizeof(float) * d.n);
+            want((void**)&d.Ct32, sizeof(float) * d.n);
+            want((void**)&d.Yt32, sizeof(float) * d.n);
+            want((void**)&d.S32, sizeof(float) * d.n);
+            want((void**)&d.Y32, sizeof(float) * (A.nnz_s * ldy + 1));
         }
+        for (int j = 0; j < d.nblk; ++j) vec.push_back(make_int2(b, j));
+        for (int t = 0; t < d.ntx * d.nty; ++t) tr.push_back(make_int2(b, t));
+        for (int64_t k = 0; k < d.na; ++k) gath.push_back(make_int2(b, (int)k));
+        const double work = (double)(B.nnz_s + B.nnz_d) * A.n + (double)(A.nnz_s + A.nnz_d) * B.n +
+                            (double)A.nnz_s * B.nnz_s;
+        order.emplace_back(-work, b);
+    }
+    // longest-first: spaces by sigma work, their tiles in order
+    std::sort(order.begin(), order.end());
+    for (auto& ob : order) {
+        const int b = ob.second;
+        const bdesc& d = p.host[b];
+        for (int64_t r = 0; r < (d.na + p.R - 1) / p.R; ++r) ssbb.push_back(make_int2(b, (int)r));
+        for (int64_t r = 0; r < (d.nb + p.R - 1) / p.R; ++r) ssaa.push_back(make_int2(b, (int)r));
+        for (int c = 0; c < spaces[b]->ab_nchunks; ++c) abg.push_back(make_int2(b, c));
+    }
+    want((void**)&p.partial, sizeof(double) * (size_t)part * kPstride);
+    want((void**)&p.states, sizeof(dav_state) * nspace);
+    want((void**)&p.counters, sizeof(int) * 8);
+    want((void**)&p.count_dev, sizeof(int));
+    want((void**)&p.D, sizeof(bdesc) * nspace);
+    std::pair<std::vector<int2>*, unit_list*> lists[6] = {{&vec, &p.vec}, {&tr, &p.tr}, {&ssbb, &p.ss_bb},
+                                                          {&ssaa, &p.ss_aa}, {&abg, &p.abg}, {&gath, &p.gath}};
+    for (auto& l : lists) {
+        l.second->n = (int)l.first->size();
+        if (l.first->empty()) l.first->push_back(make_int2(0, 0));
+        want((void**)&l.second->dev, sizeof(int2) * l.first->size());
+    }
+    size_t total = 0;
+    for (auto& r : req) total += (r.second + 255) & ~(size_t)255;
+    if (ctx->batch_arena_bytes < total) {
+        if (ctx->batch_arena) {
+            (void)hipStreamSynchronize(ctx->stream);
+            (void)hipFree(ctx->batch_arena);
+            ctx->batch_arena = nullptr;
+            ctx->batch_arena_bytes = 0;
+        }
+        if ((rc = sqd_alloc(ctx, &ctx->batch_arena, total, nullptr))) return rc;
+        ctx->batch_arena_bytes = total;
+    }
+    {
+        char* base = static_cast<char*>(ctx->batch_arena);
+        size_t off = 0;
+        for (auto& r : req) {
+            *r.first = base + off;
+            off += (r.second + 255) & ~(size_t)255;
+        }
+    }
+    for (int b = 0; b < nspace; ++b) {
+        sqd_space* sp = spaces[b];
+        const spin_tables& A = sp->sp[0];
+        const spin_tables& B = sp->sp[1];
+        bdesc& d = p.host[b];
+        const int64_t ldy = (int64_t)B.nslices * 64;
         d.diag = sp->diag;
         d.out = vecs[b];
         d.noise = nullptr;
         d.a_off = A.s_off;
+        d.st = p.states + b;
         // same-spin: BB on C (rows alpha, columns beta, diagonal fused), AA on C^T
         d.aa64 = ss_args<double>{d.Ct, d.Yt, B.n, A.n, A.perm_ss, A.nslices, A.sl_s_off, A.sl_d_off, A.sell_s_pk,
                                  A.sell_s_v64, A.sell_d_nbr, A.sell_d_v64, B.str, nullptr, 0};
@@ -643,51 +678,22 @@ int sqd_davidson_batched_impl(sqd_ctx* ctx, int nspace, sqd_space* const* spaces
                                   B.nslices, B.sl_ab_off, B.sell_ab_pk};
         d.ab32 = abg_args<float>{d.c32, d.Y32, B.n, ldy, sp->ab_grp, sp->ab_chunk_pair, A.s_pk, B.perm_ab,
                                  B.nslices, B.sl_ab_off, B.sell_ab_pk};
-        for (int j = 0; j < d.nblk; ++j) vec.push_back(make_int2(b, j));
-        for (int t = 0; t < d.ntx * d.nty; ++t) tr.push_back(make_int2(b, t));
-        for (int64_t k = 0; k < d.na; ++k) gath.push_back(make_int2(b, (int)k));
-        const double work = (double)(B.nnz_s + B.nnz_d) * A.n + (double)(A.nnz_s + A.nnz_d) * B.n +
-                            (double)A.nnz_s * B.nnz_s;
-        order.emplace_back(-work, b);
     }
-    // longest-first: spaces by sigma work, their tiles in order (the
-    // schedule can be switched to submission order for comparison)
-    std::sort(order.begin(), order.end());
-    for (auto& ob : order) {
-        const int b = ob.second;
-        const bdesc& d = p.host[b];
-        for (int64_t r = 0; r < (d.na + p.R - 1) / p.R; ++r) ssbb.push_back(make_int2(b, (int)r));
-        for (int64_t r = 0; r < (d.nb + p.R - 1) / p.R; ++r) ssaa.push_back(make_int2(b, (int)r));
-        for (int c = 0; c < spaces[b]->ab_nchunks; ++c) abg.push_back(make_int2(b, c));
-    }
-    PLAN_ALLOC(p.partial, sizeof(double) * (size_t)part * kPstride);
-    PLAN_ALLOC(p.states, sizeof(dav_state) * nspace);
-    PLAN_ALLOC(p.counters, sizeof(int) * 8);
-    PLAN_ALLOC(p.count_dev, sizeof(int));
-    PLAN_ALLOC(p.D, sizeof(bdesc) * nspace);
-#undef PLAN_ALLOC
-    for (int b = 0; b < nspace; ++b) p.host[b].st = p.states + b;
-    if (hipHostMalloc((void**)&p.count_host, sizeof(int), hipHostMallocDefault) != hipSuccess) {
-        free_plan(p);
+    if (!ctx->batch_count_host &&
+        hipHostMalloc((void**)&ctx->batch_count_host, sizeof(int), hipHostMallocDefault) != hipSuccess) {
+        ctx->batch_count_host = nullptr;
         return sqd_fail(ctx, SQD_E_OOM, "pinned allocation failed");
     }
-    if ((rc = upload_units(ctx, vec, p.vec, p.allocs)) || (rc = upload_units(ctx, tr, p.tr, p.allocs)) ||
-        (rc = upload_units(ctx, ssbb, p.ss_bb, p.allocs)) || (rc = upload_units(ctx, ssaa, p.ss_aa, p.allocs)) ||
-        (rc = upload_units(ctx, abg, p.abg, p.allocs)) || (rc = upload_units(ctx, gath, p.gath, p.allocs))) {
-        free_plan(p);
-        return rc;
-    }
-    if (hipMemcpy(p.D, p.host.data(), sizeof(bdesc) * nspace, hipMemcpyHostToDevice) != hipSuccess) {
-        free_plan(p);
-        return sqd_fail(ctx, SQD_E_HIP, "descriptor upload failed");
-    }
+    p.count_host = ctx->batch_count_host;
+    for (auto& l : lists)
+        SQD_HIP(ctx, hipMemcpy(l.second->dev, l.first->data(), sizeof(int2) * l.first->size(),
+                               hipMemcpyHostToDevice));
+    SQD_HIP(ctx, hipMemcpy(p.D, p.host.data(), sizeof(bdesc) * nspace, hipMemcpyHostToDevice));
     // a private stream for graph capture, ordered after the context's stream
     hipStream_t s = nullptr;
     hipEvent_t ev = nullptr;
-    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess || hipEventCreate(&ev) != hipSuccess) {
-        free_plan(p);
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess || hipEventCreate(&ev) != hipSuccess)
         return sqd_fail(ctx, SQD_E_HIP, "stream creation failed");
-    }
     (void)hipEventRecord(ev, ctx->stream);
     (void)hipStreamWaitEvent(s, ev, 0);
     // the FP32 same-spin kernel stages as many rows as the FP64 one
@@ -714,6 +720,5 @@ int sqd_davidson_batched_impl(sqd_ctx* ctx, int nspace, sqd_space* const* spaces
     (void)hipStreamSynchronize(s);
     (void)hipEventDestroy(ev);
     (void)hipStreamDestroy(s);
-    free_plan(p);
     return rc;
 }

@@ -158,14 +158,6 @@ struct dav_work {
     dav_state* st_host = nullptr;  // pinned
 };
 
-static void free_work(dav_work& w) {
-    void* ps[] = {w.V, w.AV, w.T, w.cin, w.sout, w.c32, w.partial, w.st};
-    for (void* p : ps)
-        if (p) (void)hipFree(p);
-    if (w.st_host) (void)hipHostFree(w.st_host);
-    w = dav_work();
-}
-
 template <int MT>
 static int davidson_run(sqd_ctx* ctx, sqd_space* sp, const sqd_davidson_opts* o, double* energy, double* vec,
                         sqd_report* rep, dav_work& w, const dav_params& prm) {
@@ -273,26 +265,45 @@ int sqd_davidson_impl(sqd_ctx* ctx, sqd_space* sp, const sqd_davidson_opts* o, d
     const int mmax = o->m_max;
     dav_work w;
     int rc = SQD_OK;
-#define DAV_ALLOC(ptr, bytes)                                                     \
-    do {                                                                          \
-        if ((rc = sqd_alloc(ctx, (void**)&(ptr), (bytes), nullptr))) {            \
-            free_work(w);                                                         \
-            return rc;                                                            \
-        }                                                                         \
-    } while (0)
-    DAV_ALLOC(w.V, sizeof(double) * (size_t)n * mmax);
-    DAV_ALLOC(w.AV, sizeof(double) * (size_t)n * mmax);
-    DAV_ALLOC(w.T, sizeof(double) * n);
-    DAV_ALLOC(w.cin, sizeof(double) * n);
-    DAV_ALLOC(w.sout, sizeof(double) * n);
-    if (o->mode == SQD_DAV_MIXED) DAV_ALLOC(w.c32, sizeof(float) * n);
-    DAV_ALLOC(w.partial, sizeof(double) * kMaxBlocks * kPstride);
-    DAV_ALLOC(w.st, sizeof(dav_state));
-#undef DAV_ALLOC
-    if (hipHostMalloc((void**)&w.st_host, sizeof(dav_state), hipHostMallocDefault) != hipSuccess) {
-        free_work(w);
+    // The vectors live in an arena the context keeps (grown on demand) across
+    // calls, so repeated solves (finite differences, the sampling loop) do not
+    // allocate the m_max x dim basis every time.
+    std::pair<void**, size_t> req[] = {
+        {(void**)&w.V, sizeof(double) * (size_t)n * mmax},
+        {(void**)&w.AV, sizeof(double) * (size_t)n * mmax},
+        {(void**)&w.T, sizeof(double) * n},
+        {(void**)&w.cin, sizeof(double) * n},
+        {(void**)&w.sout, sizeof(double) * n},
+        {(void**)&w.c32, o->mode == SQD_DAV_MIXED ? sizeof(float) * n : 0},
+        {(void**)&w.partial, sizeof(double) * kMaxBlocks * kPstride},
+        {(void**)&w.st, sizeof(dav_state)},
+    };
+    size_t total = 0;
+    for (auto& r : req) total += (r.second + 255) & ~(size_t)255;
+    if (ctx->dav_arena_bytes < total) {
+        if (ctx->dav_arena) {
+            (void)hipStreamSynchronize(ctx->stream);
+            (void)hipFree(ctx->dav_arena);
+            ctx->dav_arena = nullptr;
+            ctx->dav_arena_bytes = 0;
+        }
+        if ((rc = sqd_alloc(ctx, &ctx->dav_arena, total, nullptr))) return rc;
+        ctx->dav_arena_bytes = total;
+    }
+    {
+        char* base = static_cast<char*>(ctx->dav_arena);
+        size_t off = 0;
+        for (auto& r : req) {
+            *r.first = r.second ? base + off : nullptr;
+            off += (r.second + 255) & ~(size_t)255;
+        }
+    }
+    if (!ctx->dav_state_host &&
+        hipHostMalloc((void**)&ctx->dav_state_host, sizeof(dav_state), hipHostMallocDefault) != hipSuccess) {
+        ctx->dav_state_host = nullptr;
         return sqd_fail(ctx, SQD_E_OOM, "pinned host allocation failed");
     }
+    w.st_host = static_cast<dav_state*>(ctx->dav_state_host);
     dav_params prm;
     prm.tol = o->tol;
     prm.switch_tol = o->switch_tol;
@@ -303,6 +314,5 @@ int sqd_davidson_impl(sqd_ctx* ctx, sqd_space* sp, const sqd_davidson_opts* o, d
     else if (mmax <= 16) rc = davidson_run<16>(ctx, sp, o, energy, vec, rep, w, prm);
     else if (mmax <= 24) rc = davidson_run<24>(ctx, sp, o, energy, vec, rep, w, prm);
     else rc = davidson_run<32>(ctx, sp, o, energy, vec, rep, w, prm);
-    free_work(w);
     return rc;
 }

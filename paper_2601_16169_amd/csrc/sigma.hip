@@ -266,7 +266,7 @@ int pick_chunk(sqd_ctx* ctx, int64_t nb, int norb, size_t es) {
 template <typename T>
 int launch_same_spin(sqd_ctx* ctx, const T* X, T* Y, int64_t nrows, int64_t ncols, const spin_tables& col,
                      const spin_tables& row, const T* jk, int norb, const double* diag, int accumulate,
-                     const int* skip) {
+                     const int* skip, const char* timer_name) {
     const size_t es = sizeof(T);
     const int R = pick_rows(ctx, nrows, ncols, norb, es);
     if (R == 0) return sqd_fail(ctx, SQD_E_LIMIT, "same-spin row does not fit in LDS (too many strings)");
@@ -279,7 +279,7 @@ int launch_same_spin(sqd_ctx* ctx, const T* X, T* Y, int64_t nrows, int64_t ncol
     else { sv = (const T*)col.sell_s_v32; dv = (const T*)col.sell_d_v32; }
     ss_args<T> args{X, Y, nrows, ncols, col.perm_ss, col.nslices, col.sl_s_off, col.sl_d_off, col.sell_s_pk, sv,
                     col.sell_d_nbr, dv, row.str, diag, accumulate};
-    prof_scope ps(ctx, sizeof(T) == 8 ? "k_same_spin<double>" : "k_same_spin<float>");
+    prof_scope ps(ctx, timer_name);
 #define SQD_SS_LAUNCH(RR)                                                                                    \
     case RR:                                                                                                 \
         set_lds(k_same_spin<T, RR>, (int)lds);                                                               \
@@ -493,7 +493,8 @@ int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma, 
                 hipLaunchKernelGGL((k_transpose<double, double, false>), tgrid, dim3(256), 0, ctx->stream, c, Ct, na,
                                    nb, skip);
             }
-            if ((rc = launch_same_spin<double>(ctx, Ct, Yt, nb, na, A, B, ctx->jk64, norb, nullptr, 0, skip))) return rc;
+            if ((rc = launch_same_spin<double>(ctx, Ct, Yt, nb, na, A, B, ctx->jk64, norb, nullptr, 0, skip,
+                                               "k_same_spin<double>[aa]"))) return rc;
             {
                 prof_scope pt(ctx, "k_transpose<double>");
                 hipLaunchKernelGGL((k_transpose<double, double, false>), tgridT, dim3(256), 0, ctx->stream, Yt, sigma,
@@ -503,7 +504,7 @@ int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma, 
         }
         if (mask & SQD_TERM_BB) {
             if ((rc = launch_same_spin<double>(ctx, c, sigma, na, nb, B, A, ctx->jk64, norb, diag, written ? 1 : 0,
-                                               skip)))
+                                               skip, "k_same_spin<double>[bb]")))
                 return rc;
             written = true;
         } else if (diag) {
@@ -546,7 +547,8 @@ int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma, 
             hipLaunchKernelGGL((k_transpose<float, float, false>), tgrid, dim3(256), 0, ctx->stream, Cin, Ct32, na, nb,
                                skip);
         }
-        if ((rc = launch_same_spin<float>(ctx, Ct32, Yt32, nb, na, A, B, ctx->jk32, norb, nullptr, 0, skip))) return rc;
+        if ((rc = launch_same_spin<float>(ctx, Ct32, Yt32, nb, na, A, B, ctx->jk32, norb, nullptr, 0, skip,
+                                              "k_same_spin<float>[aa]"))) return rc;
         {
             prof_scope pt(ctx, "k_transpose<float>");
             hipLaunchKernelGGL((k_transpose<float, float, false>), tgridT, dim3(256), 0, ctx->stream, Yt32, S32, nb,
@@ -556,7 +558,7 @@ int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma, 
     }
     if (mask & SQD_TERM_BB) {
         if ((rc = launch_same_spin<float>(ctx, Cin, S32, na, nb, B, A, ctx->jk32, norb, nullptr, written ? 1 : 0,
-                                          skip)))
+                                          skip, "k_same_spin<float>[bb]")))
             return rc;
         written = true;
     }

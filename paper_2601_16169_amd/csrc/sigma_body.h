@@ -42,30 +42,40 @@ struct lds_cols {
     }
 };
 
-// Stage R rows of length ncols (row r starts at rows[r], or zeros when null)
-// into LDS in the lds_cols<T, R> layout; two columns per iteration so 2R
-// independent global loads are in flight per thread.  Column ncols is zero.
+// Stage R rows of length ncols (row r starts at rows[r], or zeros when null;
+// rows[0] is never null) into LDS in the lds_cols<T, R> layout; column ncols
+// is zero.  Each thread takes four columns per pass and issues all 4R loads
+// before any store: null rows read row 0 and are zeroed by a select, columns
+// past the end read the last column and are not stored, so no load sits
+// behind a branch.
 template <typename T, int R>
 __device__ __forceinline__ void stage_rows(T* __restrict__ xs, const T* const (&rows)[R], int ncols) {
     using L = lds_cols<T, R>;
+    constexpr int kCols = 4;
     const int tid = threadIdx.x, nthr = blockDim.x;
-    int col = tid;
-    for (; col + nthr < ncols; col += 2 * nthr) {
-        T a[R], b[R];
+    const T* src[R];
+    bool ok[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            a[r] = rows[r] ? rows[r][col] : (T)0;
-            b[r] = rows[r] ? rows[r][col + nthr] : (T)0;
-        }
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            xs[L::idx(col, r)] = a[r];
-            xs[L::idx(col + nthr, r)] = b[r];
-        }
+    for (int r = 0; r < R; ++r) {
+        ok[r] = rows[r] != nullptr;
+        src[r] = ok[r] ? rows[r] : rows[0];
     }
-    for (; col < ncols; col += nthr) {
+    for (int col0 = tid; col0 < ncols; col0 += kCols * nthr) {
+        T v[kCols][R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) xs[L::idx(col, r)] = rows[r] ? rows[r][col] : (T)0;
+        for (int u = 0; u < kCols; ++u) {
+            const int c = min(col0 + u * nthr, ncols - 1);
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[u][r] = src[r][c];
+        }
+#pragma unroll
+        for (int u = 0; u < kCols; ++u) {
+            const int c = col0 + u * nthr;
+            if (c < ncols) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) xs[L::idx(c, r)] = ok[r] ? v[u][r] : (T)0;
+            }
+        }
     }
     if (tid < R) xs[(int64_t)ncols * R + tid] = (T)0;
 }
@@ -107,14 +117,25 @@ __device__ __forceinline__ void ss_block(const ss_args<T>& a, const T* __restric
         for (int r = 0; r < R; ++r) rows[r] = (row0 + r < nrows) ? a.X + (row0 + r) * ncols : nullptr;
         stage_rows<T, R>(xs, rows, (int)ncols);
     }
-    // cross-spin term of the staged rows: ws[pq][r] = sum_{k in row string} (pq|kk)
+    // cross-spin term of the staged rows: ws[pq][r] = sum_{k in row string} (pq|kk),
+    // summed over k in increasing order; every (pq|kk) is loaded (no load
+    // behind a branch) and unoccupied k contribute an exact zero
     for (int idx = tid; idx < R * norb2; idx += nthr) {
         const int r = idx / norb2, pq = idx - r * norb2;
         const int64_t row = row0 + r;
+        const uint64_t x = (row < nrows) ? a.row_str[row] : 0ull;
         T acc = (T)0;
-        if (row < nrows)
-            for (uint64_t x = a.row_str[row]; x; x &= x - 1)
-                acc += jk[(__ffsll((unsigned long long)x) - 1) * norb2 + pq];
+        int k = 0;
+        for (; k + 4 <= norb; k += 4) {
+            T v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = jk[(k + u) * norb2 + pq];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if ((x >> (k + u)) & 1ull) acc += v[u];
+        }
+        for (; k < norb; ++k)
+            if ((x >> k) & 1ull) acc += jk[k * norb2 + pq];
         ws[lds_cols<T, R>::idx(pq, r)] = acc;
     }
     __syncthreads();

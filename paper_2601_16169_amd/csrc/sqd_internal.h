@@ -35,6 +35,14 @@ struct sqd_ctx {
     // scratch shared by products on this context
     void* scratch = nullptr;
     size_t scratch_bytes = 0;
+    // workspace of the batched solver (grown on demand, kept across calls)
+    void* batch_arena = nullptr;
+    size_t batch_arena_bytes = 0;
+    int* batch_count_host = nullptr;   // pinned
+    // workspace of the single-space Davidson solver (grown on demand)
+    void* dav_arena = nullptr;
+    size_t dav_arena_bytes = 0;
+    void* dav_state_host = nullptr;    // pinned
     // per-kernel HIP-event timers (sqd_profile)
     bool profiling = false;
     struct prof_rec { const char* name; hipEvent_t a, b; };

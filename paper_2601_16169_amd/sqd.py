@@ -78,7 +78,7 @@ EXPORTS = [
     "sqd_version", "sqd_create", "sqd_destroy", "sqd_last_error", "sqd_synchronize", "sqd_set_tuning",
     "sqd_get_tuning", "sqd_set_hamiltonian", "sqd_build_space", "sqd_space_free", "sqd_space_info",
     "sqd_get_tables", "sqd_diag", "sqd_sigma", "sqd_davidson_default_opts", "sqd_davidson",
-    "sqd_davidson_batched", "sqd_rdm", "sqd_profile", "sqd_profile_report",
+    "sqd_davidson_batched", "sqd_rdm", "sqd_profile", "sqd_profile_report", "sqd_release_workspace",
 ]
 
 
@@ -116,6 +116,7 @@ def lib():
                                        ctypes.POINTER(d), ctypes.POINTER(P), ctypes.POINTER(Report)]
     L.sqd_rdm.argtypes = [P, P, P, P, P]
     L.sqd_profile.argtypes = [P, c_int]
+    L.sqd_release_workspace.argtypes = [P]
     L.sqd_profile_report.argtypes = [P, ctypes.c_char_p, c_int]
     _lib = L
     return L
@@ -177,6 +178,11 @@ class Context:
 
     def synchronize(self):
         self._check(lib().sqd_synchronize(self._h), "sqd_synchronize")
+
+    def release_workspace(self):
+        """Free the device workspaces kept between calls (product, Davidson
+        and batched-solver scratch)."""
+        self._check(lib().sqd_release_workspace(self._h), "sqd_release_workspace")
 
     def profile(self, enable: bool = True):
         """Start/stop per-kernel HIP-event timers on this context's stream."""

@@ -171,3 +171,28 @@ def test_default_start_reaches_flip_odd_ground_state(ctx):
     Eb, _, reps, rc = ctx.davidson_batched([sp], tol=1e-10)
     assert rc == 0 and abs(Eb[0] - w[0]) <= 1e-8
     sp.close()
+
+
+def test_workspace_reuse_and_release(ctx):
+    """Solves on spaces of different sizes reuse and grow the context's
+    workspaces; after sqd_release_workspace the next solve allocates again and
+    gives the same result."""
+    torch = need_gpu()
+    big = I.small_problem(8, 3, 4, 37, 53, 3)
+    small = I.small_problem(6, 3, 2, 13, 11, 2)
+    res = []
+    for p in (big, small, big):
+        sp = _space(ctx, p)
+        E, x, rep = sp.davidson(tol=1e-10, noise=_noise(torch, sp.dim))
+        res.append(E)
+        sp.close()
+    assert res[0] == res[2]
+    ctx.release_workspace()
+    sp = _space(ctx, big)
+    E, x, rep = sp.davidson(tol=1e-10, noise=_noise(torch, sp.dim))
+    assert E == res[0]
+    Eb, _, reps, rc = ctx.davidson_batched([sp], tol=1e-10)
+    ctx.release_workspace()
+    Eb2, _, reps, rc = ctx.davidson_batched([sp], tol=1e-10)
+    assert Eb == Eb2
+    sp.close()
