@@ -84,6 +84,41 @@ struct dav_params {
     int mixed;
 };
 
+// 1/x and 1/sqrt(x) from the hardware estimates refined by two Newton steps
+// (each squares the relative error, so two reach FP64 rounding); a dependent
+// chain far shorter than IEEE division and square root.
+__device__ __forceinline__ double rcp_refined(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) r = fma(r, fma(-x, r, 1.0), r);
+    return r;
+}
+__device__ __forceinline__ double rsqrt_refined(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) y = fma(y, fma(-h * y, y, 0.5), y);
+    return y;
+}
+
+// Rotation (c, s) that zeroes the (p, q) entry of a symmetric 2 x 2 block
+// [[app, apq], [apq, aqq]] (Rutishauser's smaller-angle choice, written with
+// d = aqq - app and e = 2 apq: t = sign(d) e / (|d| + hypot(d, e)), c =
+// 1/sqrt(1 + t^2), s = t c; sign(0) = +1).
+__device__ __forceinline__ void jacobi_rotation(double app, double aqq, double apq, double& c, double& s) {
+    const double d = aqq - app, e = 2.0 * apq;
+    const double h2 = d * d + e * e;
+    if (!(h2 > 1e-300)) {   // an entry this small is below any convergence test: leave it
+        c = 1.0;
+        s = 0.0;
+        return;
+    }
+    const double hyp = h2 * rsqrt_refined(h2);
+    const double t = (d >= 0.0 ? e : -e) * rcp_refined(fabs(d) + hyp);
+    c = rsqrt_refined(1.0 + t * t);
+    s = t * c;
+}
+
 // Block-wide sums of acc[0..NV) (wave shuffles, then one LDS slot per wave);
 // written to partial row `row`.  All NV entries are reduced so that every
 // register index is static.
@@ -620,9 +655,12 @@ __device__ __forceinline__ void f_dots_fin(const double* __restrict__ partial, i
     if (st->done) return;
     __shared__ double out[MT + 1];
     reduce_rows<MT + 1>(partial, nrows, out);
-    __shared__ double A[MM * MM];
-    __shared__ double Q[MM * MM];
-    __shared__ double B[MM * MM];
+    // row stride LS = MM + 1: rows of A, Q and B start in different LDS banks,
+    // so the column accesses of the rotations do not all hit one bank
+    constexpr int LS = MM + 1;
+    __shared__ double A[MM * LS];
+    __shared__ double Q[MM * LS];
+    __shared__ double B[MM * LS];
     __shared__ double rc[MM / 2], rs[MM / 2];
     __shared__ int rp[MM / 2], rq[MM / 2];
     __shared__ double red[2 * kWaves];
@@ -643,8 +681,8 @@ __device__ __forceinline__ void f_dots_fin(const double* __restrict__ partial, i
         const int i = k / MM, j = k % MM;
         double q = (i == j) ? 1.0 : 0.0;
         if (warm && i < m0 && j < m0) q = st->Qp[k];
-        Q[k] = q;
-        A[k] = st->G[k];
+        Q[i * LS + j] = q;
+        A[i * LS + j] = st->G[k];
     }
     if (t == 0) st->m = m;
     __syncthreads();
@@ -653,24 +691,24 @@ __device__ __forceinline__ void f_dots_fin(const double* __restrict__ partial, i
             const int i = k / MM, j = k % MM;
             double v = 0.0;
             if (i < m && j < m)
-                for (int l = 0; l < m; ++l) v += A[i * MM + l] * Q[l * MM + j];
-            B[k] = v;
+                for (int l = 0; l < m; ++l) v += A[i * LS + l] * Q[l * LS + j];
+            B[i * LS + j] = v;
         }
         __syncthreads();
         for (int k = t; k < MM * MM; k += kThreads) {   // A = Q^T B
             const int i = k / MM, j = k % MM;
             double v = 0.0;
             if (i < m && j < m)
-                for (int l = 0; l < m; ++l) v += Q[l * MM + i] * B[l * MM + j];
-            A[k] = v;
+                for (int l = 0; l < m; ++l) v += Q[l * LS + i] * B[l * LS + j];
+            A[i * LS + j] = v;
         }
         __syncthreads();
         for (int k = t; k < MM * MM; k += kThreads) {   // exact symmetry
             const int i = k / MM, j = k % MM;
             if (i < j && j < m) {
-                const double v = 0.5 * (A[i * MM + j] + A[j * MM + i]);
-                A[i * MM + j] = v;
-                A[j * MM + i] = v;
+                const double v = 0.5 * (A[i * LS + j] + A[j * LS + i]);
+                A[i * LS + j] = v;
+                A[j * LS + i] = v;
             }
         }
         __syncthreads();
@@ -684,7 +722,7 @@ __device__ __forceinline__ void f_dots_fin(const double* __restrict__ partial, i
             for (int k = t; k < MM * MM; k += kThreads) {
                 const int i = k / MM, j = k % MM;
                 if (i < m && j < m) {
-                    const double v = A[k];
+                    const double v = A[i * LS + j];
                     tot += v * v;
                     if (i != j) off += v * v;
                 }
@@ -711,13 +749,8 @@ __device__ __forceinline__ void f_dots_fin(const double* __restrict__ partial, i
                     if (p > q) { const int x = p; p = q; q = x; }
                     double c = 1.0, s = 0.0;
                     if (q < m) {
-                        const double apq = A[p * MM + q];
-                        if (apq != 0.0) {
-                            const double tau = (A[q * MM + q] - A[p * MM + p]) / (2.0 * apq);
-                            const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                            c = 1.0 / sqrt(1.0 + tt * tt);
-                            s = tt * c;
-                        }
+                        const double apq = A[p * LS + q];
+                        if (apq != 0.0) jacobi_rotation(A[p * LS + p], A[q * LS + q], apq, c, s);
                     }
                     rc[t] = c; rs[t] = s; rp[t] = p; rq[t] = q;
                 }
@@ -731,16 +764,16 @@ __device__ __forceinline__ void f_dots_fin(const double* __restrict__ partial, i
                     const bool v1 = q1 < m, v2 = q2 < m;
                     const double c1 = rc[b1], s1 = rs[b1], c2 = rc[b2], s2 = rs[b2];
                     if (s1 == 0.0 && s2 == 0.0) continue;
-                    const double app = A[p1 * MM + p2];
-                    const double apq = v2 ? A[p1 * MM + q2] : 0.0;
-                    const double aqp = v1 ? A[q1 * MM + p2] : 0.0;
-                    const double aqq = (v1 && v2) ? A[q1 * MM + q2] : 0.0;
+                    const double app = A[p1 * LS + p2];
+                    const double apq = v2 ? A[p1 * LS + q2] : 0.0;
+                    const double aqp = v1 ? A[q1 * LS + p2] : 0.0;
+                    const double aqq = (v1 && v2) ? A[q1 * LS + q2] : 0.0;
                     const double rpp = c1 * app - s1 * aqp, rpq = c1 * apq - s1 * aqq;
                     const double rqp = s1 * app + c1 * aqp, rqq = s1 * apq + c1 * aqq;
-                    A[p1 * MM + p2] = c2 * rpp - s2 * rpq;
-                    if (v2) A[p1 * MM + q2] = s2 * rpp + c2 * rpq;
-                    if (v1) A[q1 * MM + p2] = c2 * rqp - s2 * rqq;
-                    if (v1 && v2) A[q1 * MM + q2] = s2 * rqp + c2 * rqq;
+                    A[p1 * LS + p2] = c2 * rpp - s2 * rpq;
+                    if (v2) A[p1 * LS + q2] = s2 * rpp + c2 * rpq;
+                    if (v1) A[q1 * LS + p2] = c2 * rqp - s2 * rqq;
+                    if (v1 && v2) A[q1 * LS + q2] = s2 * rqp + c2 * rqq;
                 }
                 // Q <- Q J
                 for (int k = t; k < (MM / 2) * MM; k += kThreads) {
@@ -749,29 +782,29 @@ __device__ __forceinline__ void f_dots_fin(const double* __restrict__ partial, i
                     const int p = rp[pr], q = rq[pr];
                     if (q >= m || rs[pr] == 0.0) continue;
                     const double c = rc[pr], s = rs[pr];
-                    const double qp = Q[i * MM + p], qq = Q[i * MM + q];
-                    Q[i * MM + p] = c * qp - s * qq;
-                    Q[i * MM + q] = s * qp + c * qq;
+                    const double qp = Q[i * LS + p], qq = Q[i * LS + q];
+                    Q[i * LS + p] = c * qp - s * qq;
+                    Q[i * LS + q] = s * qp + c * qq;
                 }
                 __syncthreads();
             }
         }
     }
-    for (int k = t; k < MM * MM; k += kThreads) st->Qp[k] = Q[k];
+    for (int k = t; k < MM * MM; k += kThreads) st->Qp[k] = Q[(k / MM) * LS + k % MM];
     if (t == 0) st->qn = m;
     if (t == 0) {
         int kmin = 0;
         for (int k = 1; k < m; ++k)
-            if (A[k * MM + k] < A[kmin * MM + kmin]) kmin = k;
-        st->theta = A[kmin * MM + kmin];
+            if (A[k * LS + k] < A[kmin * LS + kmin]) kmin = k;
+        st->theta = A[kmin * LS + kmin];
         double nrm = 0.0;
-        for (int k = 0; k < m; ++k) nrm += Q[k * MM + kmin] * Q[k * MM + kmin];
+        for (int k = 0; k < m; ++k) nrm += Q[k * LS + kmin] * Q[k * LS + kmin];
         nrm = 1.0 / sqrt(nrm);
         // sign: keep continuity with the previous Ritz vector
         double dp = 0.0;
-        for (int k = 0; k < m; ++k) dp += Q[k * MM + kmin] * st->y_prev[k];
+        for (int k = 0; k < m; ++k) dp += Q[k * LS + kmin] * st->y_prev[k];
         if (dp < 0.0) nrm = -nrm;
-        for (int k = 0; k < MM; ++k) st->y[k] = (k < m) ? Q[k * MM + kmin] * nrm : 0.0;
+        for (int k = 0; k < MM; ++k) st->y[k] = (k < m) ? Q[k * LS + kmin] * nrm : 0.0;
     }
 }
 

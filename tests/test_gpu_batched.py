@@ -88,3 +88,29 @@ def test_batched_one_space_and_cap(ctx):
     E, vecs, reps, rc = ctx.davidson_batched([s], tol=1e-14, max_iter=3)
     assert rc == 1 and not reps[0]["converged"] and reps[0]["iterations"] == 3
     s.close()
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_batched_unequal_spins(ctx, mode):
+    """Spaces whose alpha and beta string sets differ (n_alpha != n_beta and
+    different counts) solved in one batch: each energy equals the single-space
+    solve and, for the smallest, dense eigh."""
+    need_gpu()
+    specs = [(8, 3, 4, 37, 53, 3), (8, 3, 4, 20, 45, 3), (8, 3, 4, 50, 12, 3)]
+    probs = [I.small_problem(*sp_) for sp_ in specs]
+    # one shared Hamiltonian: the integrals of the first problem
+    ints = probs[0].ints
+    ctx.set_hamiltonian(ints.h, ints.eri)
+    spaces = [ctx.build_space(p.nalpha, p.nbeta, p.astr, p.bstr) for p in probs]
+    E, vecs, reps, rc = ctx.davidson_batched(spaces, tol=1e-10, mode=mode, max_iter=400)
+    assert rc == 0
+    tolE = 1e-9 if mode == 0 else 1e-6
+    for s, e in zip(spaces, E):
+        e1, _, r1 = s.davidson(tol=1e-10, max_iter=400)
+        assert r1["converged"] and abs(e - e1) <= tolE
+    small = probs[2]
+    q = I.Problem(small.name, ints, small.nalpha, small.nbeta, small.astr, small.bstr)
+    w = np.linalg.eigvalsh(core.Space.from_problem(q).dense())
+    assert abs(E[2] - w[0]) <= (1e-8 if mode == 0 else 1e-6)
+    for s in spaces:
+        s.close()

@@ -6,6 +6,7 @@ for sigma; the oracle sums in a different order, so results are not
 bit-identical.  FP32 sigma: <= 2e-6 relative (single-precision storage and
 accumulation over a few hundred terms per row).
 """
+import json
 import numpy as np
 import pytest
 
@@ -282,4 +283,24 @@ def test_sigma_cfg3_sampled_rows(ctx, precision):
     tol = 1e-12 if precision == 0 else 2e-6
     err = np.abs(got - o) / np.abs(o).max()
     assert err.max() <= tol, err.max()
+    sp.close()
+
+
+def test_autotune_keeps_results(ctx, tmp_path, monkeypatch):
+    """The autotuner's search leaves a setting applied that still reproduces
+    the oracle's sigma, caches it, and re-applies it from the cache."""
+    torch = need_gpu()
+    from paper_2601_16169_amd import autotune, sqd
+    monkeypatch.setattr(autotune, "CACHE", str(tmp_path / "tune.json"))
+    p = SMALL[3][1]()
+    sp = _space(ctx, p)
+    r = autotune.tune(sp, precision=sqd.FP64, reps=2)
+    assert set(r) == {"ss", "ab"}
+    c = I.random_vector(sp.dim, 31)
+    ref = core.Space.from_problem(p).sigma(c)
+    got = sp.sigma(torch.tensor(c, device="cuda:0")).cpu().numpy()
+    assert max(rel_err(got, ref)) <= 1e-12
+    autotune.reset(ctx)
+    assert autotune.tune(sp, precision=sqd.FP64) == json.loads(json.dumps(r))
+    autotune.reset(ctx)
     sp.close()
