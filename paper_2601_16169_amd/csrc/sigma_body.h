@@ -176,6 +176,17 @@ __device__ __forceinline__ void ss_block(const ss_args<T>& a, const T* __restric
             for (int r = 0; r < R; ++r) acc[r] += v * xr[r];
         };
         k = d0;
+        for (; k + 8 <= d1; k += 8) {   // eight table entries in flight
+            int nb8[8];
+            T v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                nb8[u] = a.d_nbr[(int64_t)(k + u) * 64 + lane];
+                v[u] = a.d_val[(int64_t)(k + u) * 64 + lane];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) dbl(nb8[u], v[u]);
+        }
         for (; k + 4 <= d1; k += 4) {
             int nb4[4];
             T v[4];
