@@ -324,6 +324,7 @@ void sqd_space_free(sqd_space* sp) {
     if (sp->ab_grp) (void)hipFree(sp->ab_grp);
     if (sp->ab_chunk_pair) (void)hipFree(sp->ab_chunk_pair);
     if (sp->ab_rev) (void)hipFree(sp->ab_rev);
+    if (sp->ab_row_order) (void)hipFree(sp->ab_row_order);
     delete sp;
 }
 

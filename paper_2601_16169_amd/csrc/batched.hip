@@ -55,6 +55,7 @@ struct bdesc {
     float* S32;
     float* Y32;
     const int* a_off;
+    const int* a_order;   // alpha rows, heaviest first (gather order)
     ss_args<double> bb64, aa64;
     ss_args<float> bb32, aa32;
     abg_args<double> ab64;
@@ -145,7 +146,7 @@ __global__ void __launch_bounds__(256) kb_gather(const bdesc* __restrict__ D, co
         if (d.st->done) continue;
         const T* Y = (const T*)(sizeof(T) == 8 ? (const void*)d.Y64 : (const void*)d.Y32);
         T* S = (T*)(sizeof(T) == 8 ? (void*)d.sout : (void*)d.S32);
-        gather_row<T>(Y, S, d.nb, d.ab64.ldy, d.ab64.bperm, d.a_off, units[u].y, row);
+        gather_row<T>(Y, S, d.nb, d.ab64.ldy, d.ab64.bperm, d.a_off, d.a_order[units[u].y], row);
     }
 }
 
@@ -664,6 +665,7 @@ int sqd_davidson_batched_impl(sqd_ctx* ctx, int nspace, sqd_space* const* spaces
         d.out = vecs[b];
         d.noise = nullptr;
         d.a_off = A.s_off;
+        d.a_order = sp->ab_row_order;
         d.st = p.states + b;
         // same-spin: BB on C (rows alpha, columns beta, diagonal fused), AA on C^T
         d.aa64 = ss_args<double>{d.Ct, d.Yt, B.n, A.n, A.perm_ss, A.nslices, A.sl_s_off, A.sl_d_off, A.sell_s_pk,

@@ -209,11 +209,13 @@ k_ab_grouped(abg_args<T> a, const T* __restrict__ V, int norb, const int* __rest
 template <typename T, bool STAGED>
 __global__ void __launch_bounds__(256)
 k_ab_gather(const T* __restrict__ Y, T* __restrict__ S, int64_t na, int64_t nb, int64_t ldy,
-            const int* __restrict__ bperm, const int* __restrict__ a_off, const int* __restrict__ skip) {
+            const int* __restrict__ bperm, const int* __restrict__ a_off, const int* __restrict__ order,
+            const int* __restrict__ skip) {
     if (skip && *skip) return;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T* row = STAGED ? reinterpret_cast<T*>(lds_raw) : nullptr;
-    for (int64_t ia = blockIdx.x; ia < na; ia += gridDim.x) gather_row<T>(Y, S, nb, ldy, bperm, a_off, ia, row);
+    for (int64_t k = blockIdx.x; k < na; k += gridDim.x)
+        gather_row<T>(Y, S, nb, ldy, bperm, a_off, order[k], row);
 }
 
 // Longest alpha-beta output row assembled in LDS by the gather (larger rows are
@@ -364,6 +366,18 @@ int ensure_ab_groups_impl(sqd_ctx* ctx, sqd_space* sp, int G) {
     if (sp->ab_grp) { (void)hipFree(sp->ab_grp); sp->ab_grp = nullptr; }
     if (sp->ab_chunk_pair) { (void)hipFree(sp->ab_chunk_pair); sp->ab_chunk_pair = nullptr; }
     int rc;
+    if (!sp->ab_row_order) {
+        // gather order: heaviest alpha rows first, so that the rows with the
+        // most singles start together on different compute units
+        std::vector<int> off(A.n + 1);
+        SQD_HIP(ctx, hipMemcpy(off.data(), A.s_off, sizeof(int) * (A.n + 1), hipMemcpyDeviceToHost));
+        std::vector<int> order(A.n);
+        for (int64_t r = 0; r < A.n; ++r) order[r] = (int)r;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int x, int y) { return off[x + 1] - off[x] > off[y + 1] - off[y]; });
+        if ((rc = sqd_alloc(ctx, (void**)&sp->ab_row_order, sizeof(int) * (A.n + 1), &sp->bytes))) return rc;
+        SQD_HIP(ctx, hipMemcpy(sp->ab_row_order, order.data(), sizeof(int) * A.n, hipMemcpyHostToDevice));
+    }
     if ((rc = sqd_alloc(ctx, (void**)&sp->ab_grp, sizeof(int) * (grp.size() + 1), &sp->bytes))) return rc;
     if ((rc = sqd_alloc(ctx, (void**)&sp->ab_chunk_pair, sizeof(int) * (cp.size() + 1), &sp->bytes))) return rc;
     if (!grp.empty()) {
@@ -420,10 +434,10 @@ int launch_ab_grouped(sqd_ctx* ctx, sqd_space* sp, const T* C, T* S, T* Y, const
     if (A.n == 0 || B.n == 0) return SQD_OK;
     if (row_bytes <= kGatherStageBytes)
         hipLaunchKernelGGL((k_ab_gather<T, true>), dim3(gx), dim3(256), (size_t)row_bytes, ctx->stream, Y, S, A.n,
-                           B.n, ldy, B.perm_ab, A.s_off, skip);
+                           B.n, ldy, B.perm_ab, A.s_off, sp->ab_row_order, skip);
     else
         hipLaunchKernelGGL((k_ab_gather<T, false>), dim3(gx), dim3(256), 0, ctx->stream, Y, S, A.n, B.n, ldy,
-                           B.perm_ab, A.s_off, skip);
+                           B.perm_ab, A.s_off, sp->ab_row_order, skip);
     SQD_HIP(ctx, hipGetLastError());
     return SQD_OK;
 }
@@ -486,7 +500,19 @@ int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma, 
         double* Ct = (double*)scr;
         double* Yt = Ct + dim + 64;
         double* Yab = Yt + dim + 64;
+        // beta-beta (with the diagonal) writes sigma first, so that its
+        // scattered stores need no read of sigma; the alpha-alpha term comes
+        // back through a coalesced transpose that adds
         bool written = false;
+        if (mask & SQD_TERM_BB) {
+            if ((rc = launch_same_spin<double>(ctx, c, sigma, na, nb, B, A, ctx->jk64, norb, diag, 0, skip,
+                                               "k_same_spin<double>[bb]")))
+                return rc;
+            written = true;
+        } else if (diag) {
+            hipLaunchKernelGGL(k_diag_apply, dim3(g), dim3(256), 0, ctx->stream, diag, c, sigma, dim, 0, skip);
+            written = true;
+        }
         if (mask & SQD_TERM_AA) {
             {
                 prof_scope pt(ctx, "k_transpose<double>");
@@ -497,19 +523,13 @@ int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma, 
                                                "k_same_spin<double>[aa]"))) return rc;
             {
                 prof_scope pt(ctx, "k_transpose<double>");
-                hipLaunchKernelGGL((k_transpose<double, double, false>), tgridT, dim3(256), 0, ctx->stream, Yt, sigma,
-                                   nb, na, skip);
+                if (written)
+                    hipLaunchKernelGGL((k_transpose<double, double, true>), tgridT, dim3(256), 0, ctx->stream, Yt,
+                                       sigma, nb, na, skip);
+                else
+                    hipLaunchKernelGGL((k_transpose<double, double, false>), tgridT, dim3(256), 0, ctx->stream, Yt,
+                                       sigma, nb, na, skip);
             }
-            written = true;
-        }
-        if (mask & SQD_TERM_BB) {
-            if ((rc = launch_same_spin<double>(ctx, c, sigma, na, nb, B, A, ctx->jk64, norb, diag, written ? 1 : 0,
-                                               skip, "k_same_spin<double>[bb]")))
-                return rc;
-            written = true;
-        } else if (diag) {
-            hipLaunchKernelGGL(k_diag_apply, dim3(g), dim3(256), 0, ctx->stream, diag, c, sigma, dim, written ? 1 : 0,
-                               skip);
             written = true;
         }
         if (!written) hipLaunchKernelGGL(k_fill<double>, dim3(g), dim3(256), 0, ctx->stream, sigma, dim, 0.0, skip);
@@ -541,6 +561,12 @@ int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma, 
         Cin = C32;
     }
     bool written = false;
+    if (mask & SQD_TERM_BB) {
+        if ((rc = launch_same_spin<float>(ctx, Cin, S32, na, nb, B, A, ctx->jk32, norb, nullptr, 0, skip,
+                                          "k_same_spin<float>[bb]")))
+            return rc;
+        written = true;
+    }
     if (mask & SQD_TERM_AA) {
         {
             prof_scope pt(ctx, "k_transpose<float>");
@@ -551,15 +577,13 @@ int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma, 
                                               "k_same_spin<float>[aa]"))) return rc;
         {
             prof_scope pt(ctx, "k_transpose<float>");
-            hipLaunchKernelGGL((k_transpose<float, float, false>), tgridT, dim3(256), 0, ctx->stream, Yt32, S32, nb,
-                               na, skip);
+            if (written)
+                hipLaunchKernelGGL((k_transpose<float, float, true>), tgridT, dim3(256), 0, ctx->stream, Yt32, S32, nb,
+                                   na, skip);
+            else
+                hipLaunchKernelGGL((k_transpose<float, float, false>), tgridT, dim3(256), 0, ctx->stream, Yt32, S32, nb,
+                                   na, skip);
         }
-        written = true;
-    }
-    if (mask & SQD_TERM_BB) {
-        if ((rc = launch_same_spin<float>(ctx, Cin, S32, na, nb, B, A, ctx->jk32, norb, nullptr, written ? 1 : 0,
-                                          skip, "k_same_spin<float>[bb]")))
-            return rc;
         written = true;
     }
     if (!written) hipLaunchKernelGGL(k_fill<float>, dim3(g), dim3(256), 0, ctx->stream, S32, dim, 0.0f, skip);

@@ -134,6 +134,7 @@ struct sqd_space {
     int* ab_grp = nullptr;        // ab_nchunks * ab_G CSR positions (-1 = padding)
     int* ab_chunk_pair = nullptr; // pair index of each chunk
     int* ab_rev = nullptr;        // alpha singles: entry of the neighbour's row pointing back
+    int* ab_row_order = nullptr;  // alpha rows by decreasing number of singles (gather order)
 };
 
 // ---- helpers (api.hip) ----
