@@ -73,7 +73,8 @@ extern "C" {
 #define SQD_DAV_FP64 0
 #define SQD_DAV_MIXED 1   /* FP32 sigma until ||r|| < switch_tol, then FP64 refinement */
 
-#define SQD_MMAX 32       /* largest Davidson subspace                         */
+#define SQD_MMAX 32
+#define SQD_MAXLOCK 8     /* most roots of one sqd_davidson_roots call */       /* largest Davidson subspace                         */
 #define SQD_HIST 512      /* residual history kept in the report               */
 
 /* table kinds for sqd_get_tables */
@@ -231,6 +232,18 @@ void sqd_davidson_default_opts(sqd_davidson_opts* opts);
  * the tolerance was not reached; the outputs then hold the last Ritz pair. */
 int sqd_davidson(sqd_ctx* ctx, const sqd_space* space, const sqd_davidson_opts* opts,
                  double* energy_host, double* vec_dev, sqd_report* rep);
+
+/* The nroots lowest eigenpairs (1 <= nroots <= SQD_MAXLOCK), one after another:
+ * root j is the lowest root of the orthogonal complement of roots 0..j-1,
+ * every basis vector of its solve being projected against them (locking;
+ * classical Gram-Schmidt, repeated when it removes over half the norm).
+ * energies_host[nroots]; vecs_dev (nroots x dim doubles, row j = root j,
+ * caller-owned) normalised, largest-magnitude entry positive; reps[nroots]
+ * optional.  Root accuracy: each solve stops at opts->tol; the locked roots
+ * enter later solves with their residual error.  Synchronous.  Returns
+ * SQD_NOT_CONVERGED if any root missed the tolerance. */
+int sqd_davidson_roots(sqd_ctx* ctx, const sqd_space* space, const sqd_davidson_opts* opts, int nroots,
+                       double* energies_host, double* vecs_dev, sqd_report* reps);
 
 /* Many independent spaces built on the same context (same integrals) solved
  * together: one persistent launch per sigma term over a work queue of

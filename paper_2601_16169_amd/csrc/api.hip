@@ -427,7 +427,21 @@ int sqd_davidson(sqd_ctx* ctx, const sqd_space* spc, const sqd_davidson_opts* o,
     if (sp->ctx != ctx) return sqd_fail(ctx, SQD_E_INVALID_ARG, "space belongs to another context");
     if (ctx->norb != sp->norb) return sqd_fail(ctx, SQD_E_STATE, "integrals changed norb since the space was built");
     SQD_HIP(ctx, hipSetDevice(ctx->device));
-    return sqd_davidson_impl(ctx, sp, o, energy, vec, rep);
+    return sqd_davidson_impl(ctx, sp, o, energy, vec, rep, 1);
+}
+
+int sqd_davidson_roots(sqd_ctx* ctx, const sqd_space* spc, const sqd_davidson_opts* o, int nroots,
+                       double* energies, double* vecs, sqd_report* reps) {
+    if (!ctx || !spc || !energies || !vecs) return SQD_E_INVALID_ARG;
+    if (nroots < 1 || nroots > SQD_MAXLOCK) return sqd_fail(ctx, SQD_E_INVALID_ARG, "nroots must be 1..SQD_MAXLOCK");
+    int rc = check_opts(ctx, o);
+    if (rc) return rc;
+    sqd_space* sp = const_cast<sqd_space*>(spc);
+    if (sp->ctx != ctx) return sqd_fail(ctx, SQD_E_INVALID_ARG, "space belongs to another context");
+    if (ctx->norb != sp->norb) return sqd_fail(ctx, SQD_E_STATE, "integrals changed norb since the space was built");
+    if ((int64_t)nroots > sp->dim) return sqd_fail(ctx, SQD_E_INVALID_ARG, "more roots than determinants");
+    SQD_HIP(ctx, hipSetDevice(ctx->device));
+    return sqd_davidson_impl(ctx, sp, o, energies, vecs, reps, nroots);
 }
 
 int sqd_davidson_batched(sqd_ctx* ctx, int nspace, const sqd_space* const* spaces, const sqd_davidson_opts* o,

@@ -105,6 +105,31 @@ __global__ void __launch_bounds__(kThreads) k_final_scale(double* __restrict__ o
     d_final_scale(out, n, st, blockIdx.x, gridDim.x);
 }
 __global__ void k_set_phase(dav_state* st, int phase, int done) { f_set_phase(st, phase, done); }
+__global__ void __launch_bounds__(kThreads) k_xdots(const double* __restrict__ X, int nx, const double* __restrict__ V,
+                                                    int vrow, int64_t n, const dav_state* st, int round,
+                                                    double* __restrict__ partial) {
+    d_xdots(X, nx, V, vrow, n, st, round, partial, blockIdx.x, gridDim.x);
+}
+__global__ void __launch_bounds__(kThreads) k_xfin(const double* __restrict__ partial, int nrows, int nx,
+                                                   dav_state* st, int round) {
+    f_xfin(partial, nrows, nx, st, round);
+}
+__global__ void __launch_bounds__(kThreads) k_xapply(const double* __restrict__ X, int nx, double* __restrict__ V,
+                                                     int vrow, int64_t n, const dav_state* st, int round,
+                                                     double* __restrict__ cin, float* __restrict__ c32) {
+    d_xapply(X, nx, V, vrow, n, st, round, cin, c32, blockIdx.x, gridDim.x);
+}
+
+// Project V0 (vrow 0) or the appended row V[m] (vrow 1) against the nx locked
+// vectors X and normalise it; cin (and c32 in the FP32 phase) receive it.
+void lock_project(int g, hipStream_t s, const double* X, int nx, double* V, int vrow, int64_t n, dav_state* st,
+                  double* cin, float* c32, double* part) {
+    for (int round = 0; round < 2; ++round) {
+        hipLaunchKernelGGL(k_xdots, dim3(g), dim3(kThreads), 0, s, X, nx, V, vrow, n, st, round, part);
+        hipLaunchKernelGGL(k_xfin, dim3(1), dim3(kThreads), 0, s, part, g, nx, st, round);
+        hipLaunchKernelGGL(k_xapply, dim3(g), dim3(kThreads), 0, s, X, nx, V, vrow, n, st, round, cin, c32);
+    }
+}
 
 inline int grid_for(int64_t n) {
     int64_t b = (n + kThreads - 1) / kThreads;
@@ -158,9 +183,12 @@ struct dav_work {
     dav_state* st_host = nullptr;  // pinned
 };
 
+// One solve; with nx > 0 locked vectors X (orthonormal, nx x n) every basis
+// vector is kept orthogonal to them, giving the lowest root of their
+// orthogonal complement.
 template <int MT>
 static int davidson_run(sqd_ctx* ctx, sqd_space* sp, const sqd_davidson_opts* o, double* energy, double* vec,
-                        sqd_report* rep, dav_work& w, const dav_params& prm) {
+                        sqd_report* rep, dav_work& w, const dav_params& prm, const double* X, int nx) {
     using L = dav_launch<MT>;
     const auto t0 = std::chrono::steady_clock::now();
     const int64_t n = sp->dim;
@@ -181,8 +209,12 @@ static int davidson_run(sqd_ctx* ctx, sqd_space* sp, const sqd_davidson_opts* o,
     }
     hipLaunchKernelGGL(k_start, dim3(g), dim3(kThreads), 0, s, o->guess_dev, o->guess_noise_dev, n, w.st, w.V,
                        w.partial);
-    hipLaunchKernelGGL(k_norm_fin, dim3(1), dim3(kThreads), 0, s, w.partial, g, w.st);
-    hipLaunchKernelGGL(k_scale_copy, dim3(g), dim3(kThreads), 0, s, w.V, n, w.st, w.cin, w.c32);
+    if (nx > 0) {
+        lock_project(g, s, X, nx, w.V, 0, n, w.st, w.cin, w.c32, w.partial);
+    } else {
+        hipLaunchKernelGGL(k_norm_fin, dim3(1), dim3(kThreads), 0, s, w.partial, g, w.st);
+        hipLaunchKernelGGL(k_scale_copy, dim3(g), dim3(kThreads), 0, s, w.V, n, w.st, w.cin, w.c32);
+    }
     const int* skip = &w.st->done;
     int prec = prm.mixed ? SQD_FP32 : SQD_FP64;
     if ((rc = sqd_sigma_impl(ctx, sp, w.cin, w.sout, prec, SQD_TERM_ALL, o->ab_path, prm.mixed ? w.c32 : nullptr,
@@ -202,6 +234,8 @@ static int davidson_run(sqd_ctx* ctx, sqd_space* sp, const sqd_davidson_opts* o,
             L::collapse(g, s, w.V, w.AV, n, w.st, 0, nullptr);
             L::orth1(g, s, w.V, n, w.st, w.T, w.partial);
             L::orth2(g, s, w.V, n, w.st, w.T, w.cin, prec == SQD_FP32 ? w.c32 : nullptr);
+            if (nx > 0)
+                lock_project(g, s, X, nx, w.V, 1, n, w.st, w.cin, prec == SQD_FP32 ? w.c32 : nullptr, w.partial);
             if ((rc = sqd_sigma_impl(ctx, sp, w.cin, w.sout, prec, SQD_TERM_ALL, o->ab_path,
                                      prec == SQD_FP32 ? w.c32 : nullptr, skip)))
                 return rc;
@@ -260,7 +294,7 @@ static int davidson_run(sqd_ctx* ctx, sqd_space* sp, const sqd_davidson_opts* o,
 }
 
 int sqd_davidson_impl(sqd_ctx* ctx, sqd_space* sp, const sqd_davidson_opts* o, double* energy, double* vec,
-                      sqd_report* rep) {
+                      sqd_report* rep, int nroots_) {
     const int64_t n = sp->dim;
     const int mmax = o->m_max;
     dav_work w;
@@ -310,9 +344,17 @@ int sqd_davidson_impl(sqd_ctx* ctx, sqd_space* sp, const sqd_davidson_opts* o, d
     prm.max_iter = o->max_iter;
     prm.m_max = mmax;
     prm.mixed = o->mode == SQD_DAV_MIXED;
-    if (mmax <= 8) rc = davidson_run<8>(ctx, sp, o, energy, vec, rep, w, prm);
-    else if (mmax <= 16) rc = davidson_run<16>(ctx, sp, o, energy, vec, rep, w, prm);
-    else if (mmax <= 24) rc = davidson_run<24>(ctx, sp, o, energy, vec, rep, w, prm);
-    else rc = davidson_run<32>(ctx, sp, o, energy, vec, rep, w, prm);
+    const int nroots = nroots_ > 0 ? nroots_ : 1;
+    for (int j = 0; j < nroots; ++j) {
+        double* vj = vec + (int64_t)j * n;
+        sqd_report* rj = rep ? rep + j : nullptr;
+        int rj_rc;
+        if (mmax <= 8) rj_rc = davidson_run<8>(ctx, sp, o, energy + j, vj, rj, w, prm, vec, j);
+        else if (mmax <= 16) rj_rc = davidson_run<16>(ctx, sp, o, energy + j, vj, rj, w, prm, vec, j);
+        else if (mmax <= 24) rj_rc = davidson_run<24>(ctx, sp, o, energy + j, vj, rj, w, prm, vec, j);
+        else rj_rc = davidson_run<32>(ctx, sp, o, energy + j, vj, rj, w, prm, vec, j);
+        if (rj_rc < 0) return rj_rc;
+        if (rj_rc != SQD_OK) rc = rj_rc;
+    }
     return rc;
 }

@@ -71,8 +71,10 @@ struct dav_state {
     double hist_r[SQD_HIST];
     double hist_e[SQD_HIST];
     int qn;               // Qp holds the eigenvectors of the leading qn x qn block of G (0: none)
-    int pad2_;
+    int xredo;            // locked-vector projection needs a second pass
     double best_r;        // smallest residual of the current phase
+    double xc[SQD_MAXLOCK];   // X^T v of the vector being projected
+    double xscale;        // scale applied after the projection (1 / |v - X xc|, or 1)
     double Qp[MM * MM];
 };
 
@@ -869,6 +871,94 @@ __device__ __forceinline__ void d_final_scale(double* __restrict__ out, int64_t 
     const double sc = st->tinv;
     for (int64_t i = (int64_t)bid * kThreads + threadIdx.x; i < n; i += (int64_t)nblk * kThreads)
         out[i] *= sc;
+}
+
+// ---------------------------------------------------------------- locked roots
+// Projection of a vector v against nx locked, orthonormal vectors X (the
+// roots already found), so that the solve for the next root stays in their
+// orthogonal complement.  One classical Gram-Schmidt pass, normalised with
+// the norm it predicts; a second pass only when the first removed more than
+// half of the squared norm (then the predicted norm is not trusted).
+
+// partial column 0: |v|^2; columns 1..SQD_MAXLOCK: X_k . v (zero past nx)
+// v is V itself (vrow = 0) or row st->m of V (the vector just appended).
+__device__ __forceinline__ void d_xdots(const double* __restrict__ X, int nx, const double* __restrict__ V,
+                                        int vrow, int64_t n, const dav_state* st, int round,
+                                        double* __restrict__ partial, int64_t bid, int64_t nblk) {
+    if (st->done || (round == 1 && !st->xredo)) return;
+    const double* v = vrow ? V + (int64_t)st->m * n : V;
+    double acc[1 + SQD_MAXLOCK];
+#pragma unroll
+    for (int k = 0; k <= SQD_MAXLOCK; ++k) acc[k] = 0.0;
+    const double* xr[SQD_MAXLOCK];
+#pragma unroll
+    for (int k = 0; k < SQD_MAXLOCK; ++k) xr[k] = row_ptr(X, k, nx, n);
+    for (int64_t i = (int64_t)bid * kThreads + threadIdx.x; i < n; i += (int64_t)nblk * kThreads) {
+        const double vi = v[i];
+        double x[SQD_MAXLOCK];
+#pragma unroll
+        for (int k = 0; k < SQD_MAXLOCK; ++k) x[k] = xr[k][i];
+        acc[0] += vi * vi;
+#pragma unroll
+        for (int k = 0; k < SQD_MAXLOCK; ++k) acc[1 + k] += (k < nx) ? x[k] * vi : 0.0;
+    }
+    block_to_partial<1 + SQD_MAXLOCK>(acc, partial, bid);
+}
+
+__device__ __forceinline__ void f_xfin(const double* __restrict__ partial, int nrows, int nx, dav_state* st, int round) {
+    if (st->done || (round == 1 && !st->xredo)) return;
+    __shared__ double out[1 + SQD_MAXLOCK];
+    reduce_rows<1 + SQD_MAXLOCK>(partial, nrows, out);
+    if (threadIdx.x != 0) return;
+    double cc = 0.0;
+    for (int k = 0; k < SQD_MAXLOCK; ++k) {
+        st->xc[k] = (k < nx) ? out[1 + k] : 0.0;
+        cc += st->xc[k] * st->xc[k];
+    }
+    const double a2 = out[0], b2 = a2 - cc;
+    if (round == 0 && b2 < 0.5 * a2) {
+        st->xredo = 1;
+        st->xscale = 1.0;
+        return;
+    }
+    if (round == 0) st->xredo = 0;
+    if (!(b2 > 1e-28 * a2) || !(b2 > 0.0)) {   // nothing left outside the locked space
+        st->done = DONE_STALLED;
+        return;
+    }
+    st->xscale = 1.0 / sqrt(b2);
+}
+
+// v = (v - X xc) * xscale; after the last pass also cin (and c32) = v
+__device__ __forceinline__ void d_xapply(const double* __restrict__ X, int nx, double* __restrict__ V, int vrow,
+                                         int64_t n, const dav_state* st, int round, double* __restrict__ cin,
+                                         float* __restrict__ c32, int64_t bid, int64_t nblk) {
+    if (st->done || (round == 1 && !st->xredo)) return;
+    double* v = vrow ? V + (int64_t)st->m * n : V;
+    const bool last = (round == 1) || !st->xredo;
+    const double sc = st->xscale;
+    double c[SQD_MAXLOCK];
+    const double* xr[SQD_MAXLOCK];
+#pragma unroll
+    for (int k = 0; k < SQD_MAXLOCK; ++k) {
+        c[k] = (k < nx) ? st->xc[k] : 0.0;
+        xr[k] = row_ptr(X, k, nx, n);
+    }
+    const bool lo = (st->phase == 0) && c32;
+    for (int64_t i = (int64_t)bid * kThreads + threadIdx.x; i < n; i += (int64_t)nblk * kThreads) {
+        double x[SQD_MAXLOCK];
+#pragma unroll
+        for (int k = 0; k < SQD_MAXLOCK; ++k) x[k] = xr[k][i];
+        double t = v[i];
+#pragma unroll
+        for (int k = 0; k < SQD_MAXLOCK; ++k) t -= c[k] * x[k];
+        t *= sc;
+        v[i] = t;
+        if (last) {
+            cin[i] = t;
+            if (lo) c32[i] = (float)t;
+        }
+    }
 }
 
 __device__ __forceinline__ void f_set_phase(dav_state* st, int phase, int done) {

@@ -169,8 +169,8 @@ int sqd_sigma_ab_kh(sqd_ctx* ctx, sqd_space* sp, const void* c, void* sigma, voi
                     const int* skip_flag);
 
 // ---- davidson.hip ----
-int sqd_davidson_impl(sqd_ctx* ctx, sqd_space* sp, const sqd_davidson_opts* o,
-                      double* energy, double* vec, sqd_report* rep);
+int sqd_davidson_impl(sqd_ctx* ctx, sqd_space* sp, const sqd_davidson_opts* o, double* energy, double* vec,
+                      sqd_report* rep, int nroots);
 
 // ---- rdm.hip ----
 int sqd_rdm_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* rdm1, double* rdm2);

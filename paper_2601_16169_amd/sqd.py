@@ -79,6 +79,7 @@ EXPORTS = [
     "sqd_get_tuning", "sqd_set_hamiltonian", "sqd_build_space", "sqd_space_free", "sqd_space_info",
     "sqd_get_tables", "sqd_diag", "sqd_sigma", "sqd_davidson_default_opts", "sqd_davidson",
     "sqd_davidson_batched", "sqd_rdm", "sqd_profile", "sqd_profile_report", "sqd_release_workspace",
+    "sqd_davidson_roots",
 ]
 
 
@@ -117,6 +118,7 @@ def lib():
     L.sqd_rdm.argtypes = [P, P, P, P, P]
     L.sqd_profile.argtypes = [P, c_int]
     L.sqd_release_workspace.argtypes = [P]
+    L.sqd_davidson_roots.argtypes = [P, P, P, c_int, P, P, P]
     L.sqd_profile_report.argtypes = [P, ctypes.c_char_p, c_int]
     _lib = L
     return L
@@ -330,6 +332,23 @@ class Space:
         r = rep.as_dict()
         r["status_code"] = rc
         return e.value, out, r
+
+    def davidson_roots(self, nroots, tol=1e-8, max_iter=200, m_max=24, mode=DAV_FP64, switch_tol=1e-4,
+                       ab_path=AB_AUTO, noise=None, check_every=4):
+        """The nroots lowest eigenpairs: (energies, vectors (nroots x dim), reports)."""
+        torch = _torch()
+        vecs = torch.empty((nroots, self.dim), dtype=torch.float64, device=self._dev)
+        np_ = _dev_ptr(noise, numel=self.dim) if noise is not None else None
+        o = _opts(tol, max_iter, m_max, mode, switch_tol, ab_path, np_, None, check_every)
+        e = (ctypes.c_double * nroots)()
+        reps = (Report * nroots)()
+        rc = self.ctx._check(lib().sqd_davidson_roots(self.ctx._h, self._h, ctypes.byref(o), nroots, e,
+                                                      _dev_ptr(vecs, numel=nroots * self.dim), reps),
+                             "sqd_davidson_roots")
+        out = [r.as_dict() for r in reps]
+        for r in out:
+            r["status_code"] = rc
+        return list(e), vecs, out
 
     def rdm(self, c, two_body=True):
         torch = _torch()

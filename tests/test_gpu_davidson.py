@@ -196,3 +196,32 @@ def test_workspace_reuse_and_release(ctx):
     Eb2, _, reps, rc = ctx.davidson_batched([sp], tol=1e-10)
     assert Eb == Eb2
     sp.close()
+
+
+ROOT_CASES = [CASES[0], CASES[1], CASES[2]]
+
+
+@pytest.mark.parametrize("name,make,tol", ROOT_CASES)
+@pytest.mark.parametrize("mode", [0, 1])
+def test_roots_match_dense(ctx, name, make, tol, mode):
+    """Four lowest roots by locking against dense eigh: energies (1e-8 Ha FP64,
+    1e-6 Ha mixed), orthonormal vectors, each vector along its eigenvector
+    where the root is separated from its neighbours."""
+    torch = need_gpu()
+    banner(f"roots {name} mode={mode}")
+    p = make()
+    sp = _space(ctx, p)
+    w, U = np.linalg.eigh(core.Space.from_problem(p).dense())
+    k = 4
+    E, X, reps = sp.davidson_roots(k, tol=tol, mode=mode, max_iter=400, noise=_noise(torch, sp.dim))
+    assert all(r["converged"] for r in reps)
+    tolE = 1e-8 if mode == 0 else 1e-6
+    assert np.abs(np.array(E) - w[:k]).max() <= tolE, (E, w[:k])
+    Xn = X.cpu().numpy()
+    assert np.abs(Xn @ Xn.T - np.eye(k)).max() <= 1e-9
+    for j in range(k):
+        gap = min(abs(w[j] - w[j - 1]) if j else np.inf, abs(w[j + 1] - w[j]))
+        if gap > 1e-4:
+            assert 1 - abs(Xn[j] @ U[:, j]) <= (1e-8 if mode == 0 else 1e-5), (j, gap)
+        assert Xn[j][np.argmax(np.abs(Xn[j]))] > 0
+    sp.close()
