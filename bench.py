@@ -16,6 +16,7 @@ resident in HBM.  The same run also reports:
   * the CPU oracle timed on a bounded sample of rows on this host.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg2]
+       python bench.py --leg kh|rdm|roots [--workload cfg2|cfg5]   (secondary legs)
 """
 from __future__ import annotations
 
@@ -52,6 +53,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--profile-only", action="store_true",
                     help="only the timed sigma loop (for profilers)")
+    ap.add_argument("--leg", choices=("kh", "rdm", "roots"), default=None,
+                    help="instead of the headline: time the Knowles-Handy alpha-beta path against the direct one, "
+                         "the RDM backward kernels, or the four lowest roots (one JSON line each)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; --gpus must be 1 "
@@ -80,6 +84,9 @@ def main():
     log(f"tables built in {t_tables:.3f} s: {info}")
     c = torch.tensor(I.random_vector(sp.dim, 21), device=dev)
     out = torch.empty_like(c)
+    if a.leg:
+        _leg(a, ctx, sp, prob, c, out, info)
+        return
 
     def timed(fn, steps, warmup):
         for _ in range(warmup):
@@ -215,6 +222,58 @@ def main():
         log(f"cpu baseline {result['cpu_baseline']}")
 
     print(json.dumps(result))
+
+
+def _leg(a, ctx, sp, prob, c, out, info):
+    """Secondary measurements, one JSON line each (not the headline)."""
+    import torch
+    from paper_2601_16169_amd import inputs as I
+    from paper_2601_16169_amd import sqd
+
+    def kernels(fn):
+        for _ in range(a.warmup):
+            fn()
+        ctx.synchronize()
+        ctx.profile(True)
+        for _ in range(a.steps):
+            fn()
+        r = ctx.profile_report()
+        ctx.profile(False)
+        return {k: ms / n for k, (n, ms) in r.items()}
+
+    if a.leg == "kh":
+        # dense GEMM work of the KH form: 2 x nb x norb^2 x (alpha singles)
+        flops = 2.0 * info["nb"] * prob.norb ** 2 * info["nnz_single"][0]
+        for prec, name, peak in ((sqd.FP64, "fp64", PEAK_FP64_TFLOPS), (sqd.FP32, "fp32", PEAK_FP32_TFLOPS)):
+            d = kernels(lambda: sp.sigma(c, out, precision=prec, terms=sqd.TERM_AB))
+            k = kernels(lambda: sp.sigma(c, out, precision=prec, terms=sqd.TERM_AB, ab_path=sqd.AB_KH))
+            t = [v for n_, v in k.items() if n_.startswith("k_ab_kh")][0] / 1e3
+            print(json.dumps({"leg": "kh", "workload": prob.name, "precision": name, "direct_ms": d, "kh_ms": k,
+                              "kh_gemm_flops": flops, "kh_tflops": flops / t / 1e12,
+                              "kh_frac_of_mfma_peak": flops / t / 1e12 / peak}), flush=True)
+    elif a.leg == "rdm":
+        noise = torch.tensor(I.guess_noise(sp.dim), device="cuda:0")
+        E, x, rep = sp.davidson(tol=1e-8, noise=noise)
+        for two in (False, True):
+            sp.rdm(x, two_body=two)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(a.steps):
+                sp.rdm(x, two_body=two)
+            torch.cuda.synchronize()
+            print(json.dumps({"leg": "rdm", "workload": prob.name, "two_body": two,
+                              "ms": (time.perf_counter() - t) / a.steps * 1e3, "energy": E}), flush=True)
+    elif a.leg == "roots":
+        noise = torch.tensor(I.guess_noise(sp.dim), device="cuda:0")
+        for mode, name in ((sqd.DAV_FP64, "fp64"), (sqd.DAV_MIXED, "mixed")):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            E, X, reps = sp.davidson_roots(4, tol=1e-8, mode=mode, noise=noise, max_iter=400)
+            torch.cuda.synchronize()
+            print(json.dumps({"leg": "roots", "workload": prob.name, "mode": name,
+                              "seconds": time.perf_counter() - t, "energies": E,
+                              "iterations": [r["iterations"] for r in reps],
+                              "converged": all(r["converged"] for r in reps)}), flush=True)
 
 
 def _algorithmic(name, info, sp):
