@@ -17,6 +17,7 @@ resident in HBM.  The same run also reports:
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg2]
        python bench.py --leg kh|rdm|roots [--workload cfg2|cfg5]   (secondary legs)
+       python bench.py --leg batched [--tune]   (64 uneven spaces: batched vs one by one)
 """
 from __future__ import annotations
 
@@ -53,9 +54,12 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--profile-only", action="store_true",
                     help="only the timed sigma loop (for profilers)")
-    ap.add_argument("--leg", choices=("kh", "rdm", "roots"), default=None,
+    ap.add_argument("--leg", choices=("kh", "rdm", "roots", "batched"), default=None,
                     help="instead of the headline: time the Knowles-Handy alpha-beta path against the direct one, "
-                         "the RDM backward kernels, or the four lowest roots (one JSON line each)")
+                         "the RDM backward kernels, the four lowest roots, or the batched solver on 64 uneven "
+                         "spaces against solving them one by one (one JSON line each)")
+    ap.add_argument("--tune", action="store_true",
+                    help="batched leg: also time after tuning the batched tiles for these spaces")
     a = ap.parse_args()
     if a.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; --gpus must be 1 "
@@ -70,6 +74,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs a HIP device"
     dev = "cuda:0"
+    if a.leg == "batched":
+        _leg_batched(a)
+        return
     prob = I.WORKLOADS[a.workload]()
     log(f"workload {prob.name}: dim {prob.dim}")
     stream = torch.cuda.current_stream(0)
@@ -274,6 +281,84 @@ def _leg(a, ctx, sp, prob, c, out, info):
                               "seconds": time.perf_counter() - t, "energies": E,
                               "iterations": [r["iterations"] for r in reps],
                               "converged": all(r["converged"] for r in reps)}), flush=True)
+
+
+def _leg_batched(a):
+    """64 independent spaces (norb 24, 8+8 electrons, 200-3000 strings per
+    spin, shared integrals): one batched solve per mode against the
+    single-space solver run on each space in turn, same tolerance."""
+    import numpy as np
+    import torch
+    from paper_2601_16169_amd import autotune
+    from paper_2601_16169_amd import inputs as I
+    from paper_2601_16169_amd import sqd
+
+    probs = I.cfg4()
+    ctx = sqd.Context(0)
+    ctx.set_hamiltonian(probs[0].ints.h, probs[0].ints.eri, probs[0].ints.ecore)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    spaces = [ctx.build_space(p.nalpha, p.nbeta, p.astr, p.bstr) for p in probs]
+    torch.cuda.synchronize()
+    t_tables = time.perf_counter() - t
+    dims = [s.dim for s in spaces]
+    conn = sum(s.info()["conn_per_sigma"] for s in spaces)
+    head = {"leg": "batched", "workload": "cfg4_64_spaces_norb24_n8", "nspaces": len(spaces),
+            "sum_dim": int(sum(dims)), "min_dim": int(min(dims)), "max_dim": int(max(dims)),
+            "connections_per_sweep": int(conn), "tables_s": t_tables, "tol": 1e-8}
+
+    def solve_batched(mode):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        E, vecs, reps, rc = ctx.davidson_batched(spaces, tol=1e-8, max_iter=600, mode=mode)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        it = [r["iterations"] for r in reps]
+        del vecs
+        return el, np.array(E), {"iterations_min": min(it), "iterations_max": max(it),
+                                 "all_converged": all(r["converged"] for r in reps)}
+
+    def solve_each(mode):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        Es = []
+        for s in spaces:
+            e, x, r = s.davidson(tol=1e-8, max_iter=600, mode=mode)
+            Es.append(e)
+            del x
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, np.array(Es)
+
+    ctx.davidson_batched(spaces, tol=1e-8, max_iter=3)   # warm-up of every kernel
+    spaces[0].davidson(tol=1e-8, max_iter=3)
+    res = dict(head)
+    energies = {}
+    for mode, name in ((sqd.DAV_FP64, "fp64"), (sqd.DAV_MIXED, "mixed")):
+        el, E, st = solve_batched(mode)
+        res[f"batched_{name}_s"] = el
+        res[f"batched_{name}"] = st
+        energies[f"batched_{name}"] = E
+        log(f"batched {name}: {el:.3f} s {st}")
+        el, E = solve_each(mode)
+        res[f"one_by_one_{name}_s"] = el
+        energies[f"one_by_one_{name}"] = E
+        log(f"one by one {name}: {el:.3f} s")
+    if a.tune:
+        t = time.perf_counter()
+        autotune.tune_batched(ctx, spaces, mode=sqd.DAV_MIXED, use_cache=False)
+        res["tune_s"] = time.perf_counter() - t
+        for mode, name in ((sqd.DAV_FP64, "fp64"), (sqd.DAV_MIXED, "mixed")):
+            el, E, st = solve_batched(mode)
+            res[f"tuned_batched_{name}_s"] = el
+            energies[f"tuned_batched_{name}"] = E
+        res["tuned_setting"] = {k: ctx.get_tuning(k) for k in autotune.ALL_KEYS}
+    ref = energies["one_by_one_fp64"]
+    res["max_abs_dE_vs_one_by_one_fp64_Ha"] = {k: float(np.abs(v - ref).max()) for k, v in energies.items()
+                                              if k != "one_by_one_fp64"}
+    res["speedup_batched_mixed_vs_one_by_one_fp64"] = res["one_by_one_fp64_s"] / res["batched_mixed_s"]
+    for s in spaces:
+        s.close()
+    print(json.dumps(res), flush=True)
 
 
 def _algorithmic(name, info, sp):

@@ -163,8 +163,7 @@ k_ab_direct(const T* __restrict__ C, T* __restrict__ S, int64_t na, int64_t nb, 
             if (sl < nbslices) {
                 const int c0 = bsl_off[sl], c1 = bsl_off[sl + 1];
                 T a = acc[j];
-                for (int col = c0; col < c1; ++col) {
-                    const uint32_t e = bs_pk[(int64_t)col * 64 + lane];
+                auto one = [&](uint32_t e) {
                     const int nbr = (int)(e & SQD_NBR_MASK);
                     const int pair = (int)((e >> SQD_PAIR_SHIFT) & SQD_PAIR_MASK);
                     T cr[KC], vr[KC];
@@ -174,7 +173,24 @@ k_ab_direct(const T* __restrict__ C, T* __restrict__ S, int64_t na, int64_t nb, 
 #pragma unroll
                     for (int k = 0; k < KC; ++k) t += vr[k] * cr[k];
                     a += (e >> 31) ? -t : t;
+                };
+                int col = c0;
+                for (; col + 8 <= c1; col += 8) {   // eight table entries in flight
+                    uint32_t b8[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) b8[u] = bs_pk[(int64_t)(col + u) * 64 + lane];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) one(b8[u]);
                 }
+                if (col + 4 <= c1) {
+                    uint32_t b4[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) b4[u] = bs_pk[(int64_t)(col + u) * 64 + lane];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) one(b4[u]);
+                    col += 4;
+                }
+                for (; col < c1; ++col) one(bs_pk[(int64_t)col * 64 + lane]);
                 acc[j] = a;
             }
         }
