@@ -387,7 +387,8 @@ int batched_run(sqd_ctx* ctx, batch_plan& p, const sqd_davidson_opts* o, double*
     prm.max_iter = o->max_iter;
     prm.m_max = o->m_max;
     prm.mixed = mixed;
-    const int nw_ss = ctx->tune[SQD_TUNE_SS_WAVES] ? ctx->tune[SQD_TUNE_SS_WAVES] : (R == 8 ? 16 : 8);
+    const int nw_ss = ctx->tune[SQD_TUNE_SS_WAVES] ? ctx->tune[SQD_TUNE_SS_WAVES]
+                                                   : ((R == 8 || p.lds_ss64 > (size_t)ctx->max_lds / 2) ? 16 : 8);
     // measured on MI355X (the batched tuner's choice on 64 spaces of 200-3000 strings)
     const int nw_ab = ctx->tune[SQD_TUNE_AB_WAVES] ? ctx->tune[SQD_TUNE_AB_WAVES] : 8;
     lds_attr(kb_same_spin<double, R>, p.lds_ss64);

@@ -288,9 +288,12 @@ int launch_same_spin(sqd_ctx* ctx, const T* X, T* Y, int64_t nrows, int64_t ncol
     const size_t es = sizeof(T);
     const int R = pick_rows(ctx, nrows, ncols, norb, es);
     if (R == 0) return sqd_fail(ctx, SQD_E_LIMIT, "same-spin row does not fit in LDS (too many strings)");
-    // measured on MI355X: 16 waves hide the table latency best with 8 staged rows
-    int nw = ctx->tune[SQD_TUNE_SS_WAVES] ? ctx->tune[SQD_TUNE_SS_WAVES] : (R == 8 ? 16 : 8);
     const size_t lds = ((size_t)(ncols + 1) * R + (size_t)norb * norb * R) * es;
+    // measured on MI355X: 16 waves hide the table latency best with 8 staged
+    // rows, and whenever the LDS leaves room for one workgroup per CU only
+    // (long rows: the table is then streamed once per row from the caches)
+    int nw = ctx->tune[SQD_TUNE_SS_WAVES] ? ctx->tune[SQD_TUNE_SS_WAVES]
+                                          : ((R == 8 || lds > (size_t)ctx->max_lds / 2) ? 16 : 8);
     const dim3 grid(nblk(nrows, R)), block(64 * nw);
     const T* sv = nullptr; const T* dv = nullptr;
     if constexpr (sizeof(T) == 8) { sv = (const T*)col.sell_s_v64; dv = (const T*)col.sell_d_v64; }
@@ -424,8 +427,11 @@ int launch_ab_grouped(sqd_ctx* ctx, sqd_space* sp, const T* C, T* S, T* Y, const
     int rc = ensure_ab_groups_impl(ctx, sp, G);
     if (rc) return rc;
     if (sp->ab_nchunks > 0) {
-        const int nw = ctx->tune[SQD_TUNE_AB_WAVES] ? ctx->tune[SQD_TUNE_AB_WAVES] : (sizeof(T) == 8 ? 16 : 8);
         const size_t lds = ((size_t)(B.n + 1) * G + (size_t)sp->norb * sp->norb) * sizeof(T);
+        // measured on MI355X: 16 waves for FP64, and for FP32 when few rows
+        // share each table entry (G <= 2: the loop is latency-bound)
+        const int nw = ctx->tune[SQD_TUNE_AB_WAVES] ? ctx->tune[SQD_TUNE_AB_WAVES]
+                                                    : ((sizeof(T) == 8 || G <= 2) ? 16 : 8);
         abg_args<T> args{C, Y, B.n, (int64_t)B.nslices * 64, sp->ab_grp, sp->ab_chunk_pair, A.s_pk, B.perm_ab,
                          B.nslices, B.sl_ab_off, B.sell_ab_pk};
         prof_scope ps(ctx, sizeof(T) == 8 ? "k_ab_grouped<double>" : "k_ab_grouped<float>");

@@ -176,16 +176,34 @@ __device__ __forceinline__ void ss_block(const ss_args<T>& a, const T* __restric
             for (int r = 0; r < R; ++r) acc[r] += v * xr[r];
         };
         k = d0;
-        for (; k + 8 <= d1; k += 8) {   // eight table entries in flight
-            int nb8[8];
-            T v[8];
+        // table entries in flight: with one or two staged FP32 rows there is
+        // little LDS work per entry to cover the table's latency, so keep more
+        // loads out (measured on MI355X; FP64 with one row is slower at 16)
+        constexpr int kD = (R <= 2 && sizeof(T) == 4) ? 16 : 8;
+        for (; k + kD <= d1; k += kD) {
+            int nbd[kD];
+            T v[kD];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                nb8[u] = a.d_nbr[(int64_t)(k + u) * 64 + lane];
+            for (int u = 0; u < kD; ++u) {
+                nbd[u] = a.d_nbr[(int64_t)(k + u) * 64 + lane];
                 v[u] = a.d_val[(int64_t)(k + u) * 64 + lane];
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) dbl(nb8[u], v[u]);
+            for (int u = 0; u < kD; ++u) dbl(nbd[u], v[u]);
+        }
+        if constexpr (kD > 8) {
+            if (k + 8 <= d1) {
+                int nb8[8];
+                T v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    nb8[u] = a.d_nbr[(int64_t)(k + u) * 64 + lane];
+                    v[u] = a.d_val[(int64_t)(k + u) * 64 + lane];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) dbl(nb8[u], v[u]);
+                k += 8;
+            }
         }
         for (; k + 4 <= d1; k += 4) {
             int nb4[4];
@@ -281,12 +299,23 @@ __device__ __forceinline__ void abg_block(const abg_args<T>& a, const T* __restr
             for (int r = 0; r < G; ++r) acc[r] += v * xr[r];
         };
         int col = c0;
-        for (; col + 8 <= c1; col += 8) {   // eight table entries in flight
-            uint32_t b8[8];
+        constexpr int kD = G <= 2 ? 16 : 8;   // table entries in flight (more when few rows share each)
+        for (; col + kD <= c1; col += kD) {
+            uint32_t bd[kD];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) b8[u] = a.bs_pk[(int64_t)(col + u) * 64 + lane];
+            for (int u = 0; u < kD; ++u) bd[u] = a.bs_pk[(int64_t)(col + u) * 64 + lane];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) one(b8[u]);
+            for (int u = 0; u < kD; ++u) one(bd[u]);
+        }
+        if constexpr (kD > 8) {
+            if (col + 8 <= c1) {
+                uint32_t b8[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) b8[u] = a.bs_pk[(int64_t)(col + u) * 64 + lane];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) one(b8[u]);
+                col += 8;
+            }
         }
         if (col + 4 <= c1) {
             uint32_t b4[4];
