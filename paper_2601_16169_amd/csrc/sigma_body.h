@@ -335,7 +335,7 @@ __device__ __forceinline__ void abg_block(const abg_args<T>& a, const T* __restr
 }
 
 // sigma[ia][perm(p)] += sum_{e in row ia} Y[e][p] over all slots p of row ia,
-// one 256-thread workgroup per row: each thread reads two adjacent slots with
+// one workgroup per row: each thread reads two adjacent slots with
 // one vector load (ldy is a multiple of 64), eight rows of Y in flight.  With
 // `row` (LDS, nb values) the sums are placed by target first and the row of
 // sigma is then updated with coalesced accesses; without it (rows too long
