@@ -408,6 +408,32 @@ def _traffic(name):
     return float(vals["bytes_per_launch"])
 
 
+def _lds_util(name):
+    """LDS busy fraction (rocprofv3 LdsUtil) of this kernel from the committed
+    summary, or None when absent or the kernel source changed since."""
+    import hashlib
+    import re
+    path = os.path.join(PROFILES, "lds_sigma_cfg2.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"source: `([^`]*)`", text)
+    h = re.search(r"source_sha256: `([0-9a-f]+)`", text)
+    if not m or not h:
+        return None
+    d = hashlib.sha256()
+    for f in m.group(1).split():
+        d.update(open(os.path.join(ROOT, f), "rb").read())
+    if d.hexdigest()[:16] != h.group(1):
+        return None
+    base, es = name.split("<")[0], ("double" if "double" in name else "float")
+    for line in text.splitlines():
+        cells = [c.strip() for c in line.split("|")]
+        if len(cells) > 4 and cells[1].startswith(f"`void {base}<{es}"):
+            return float(cells[3]) / 100.0
+    return None
+
+
 def _roofline(kernels, info, sp, prob):
     """Roofline of the kernel with the largest share of the step."""
     name = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
@@ -419,7 +445,8 @@ def _roofline(kernels, info, sp, prob):
         peak = PEAK_FP64_TFLOPS if "double" in name else PEAK_FP32_TFLOPS
         ach, u = work / t / 1e12, "TFLOP/s"
     return {"kernel": name, "bound": bound, "achieved": ach, "peak": peak, "unit": u, "frac": ach / peak,
-            "traffic": _traffic(name), "algorithmic_per_launch": work, "algorithmic_unit": unit,
+            "traffic": _traffic(name), "lds_util": _lds_util(name),
+            "algorithmic_per_launch": work, "algorithmic_unit": unit,
             "launch_ms": t * 1e3, "share_of_step": kernels[name]["ms_per_step"] / sum(
                 v["ms_per_step"] for v in kernels.values())}
 
