@@ -62,8 +62,8 @@ def main():
                     help="batched leg: also time after tuning the batched tiles for these spaces")
     a = ap.parse_args()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; --gpus must be 1 "
-                          "(multi-GPU sharding is a design in DESIGN.md, not built)"}))
+        print(json.dumps({"error": "libsqd runs on one GPU; --gpus must be 1 "
+                          "(the multi-GPU sharding is designed but not implemented)"}))
         sys.exit(2)
 
     import numpy as np
