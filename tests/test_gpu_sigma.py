@@ -41,6 +41,7 @@ SMALL = [
     ("one_alpha_string", lambda: I.small_problem(6, 2, 3, 1, 20, 5)),
     ("one_beta_string", lambda: I.small_problem(6, 2, 3, 15, 1, 6)),
     ("zero_alpha_electrons", lambda: I.small_problem(5, 0, 2, 1, 10, 7)),
+    ("full_alpha_shell", lambda: I.small_problem(5, 5, 2, 1, 10, 10)),
     ("cfg1", I.cfg1),
 ]
 
@@ -212,6 +213,35 @@ def test_error_codes(ctx):
     with pytest.raises(sqd.SQDError) as e:
         ctx.set_hamiltonian(p.ints.h, eri)
     assert e.value.code == -5
+    ctx.set_hamiltonian(p.ints.h, p.ints.eri)
+    # empty string list, electron count above norb
+    with pytest.raises(sqd.SQDError) as e:
+        ctx.build_space(3, 2, np.zeros(0, dtype=np.uint64), p.bstr)
+    assert e.value.code == -1
+    with pytest.raises(sqd.SQDError) as e:
+        ctx.build_space(7, 2, p.astr, p.bstr)
+    assert e.value.code == -3
+    # tuning values outside the allowed sets
+    with pytest.raises(sqd.SQDError) as e:
+        ctx.set_tuning(sqd.TUNE_SS_ROWS, 3)
+    assert e.value.code == -1
+    with pytest.raises(sqd.SQDError) as e:
+        ctx.set_tuning(99, 1)
+    assert e.value.code == -1
+    # the space still works after the rejected calls
+    sp = ctx.build_space(3, 2, p.astr, p.bstr)
+    with pytest.raises(sqd.SQDError) as e:
+        sp.davidson_roots(9)           # more than SQD_MAXLOCK roots
+    assert e.value.code == -1
+    sp.close()
+    q = I.small_problem(3, 1, 1, 2, 2, 11)
+    ctx.set_hamiltonian(q.ints.h, q.ints.eri)
+    sq = ctx.build_space(1, 1, q.astr, q.bstr)
+    assert sq.dim == 4
+    with pytest.raises(sqd.SQDError) as e:
+        sq.davidson_roots(5)           # more roots than determinants
+    assert e.value.code == -1
+    sq.close()
 
 
 KH_CASES = [SMALL[2], SMALL[3], SMALL[4], SMALL[7]]
