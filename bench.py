@@ -408,9 +408,10 @@ def _traffic(name):
     return float(vals["bytes_per_launch"])
 
 
-def _lds_util(name):
-    """LDS busy fraction (rocprofv3 LdsUtil) of this kernel from the committed
-    summary, or None when absent or the kernel source changed since."""
+def _lds_util(name, column=3):
+    """LDS busy fraction (rocprofv3 LdsUtil; column 5: VALUBusy) of this
+    kernel from the committed summary, or None when absent or the kernel
+    source changed since."""
     import hashlib
     import re
     path = os.path.join(PROFILES, "lds_sigma_cfg2.md")
@@ -429,8 +430,11 @@ def _lds_util(name):
     base, es = name.split("<")[0], ("double" if "double" in name else "float")
     for line in text.splitlines():
         cells = [c.strip() for c in line.split("|")]
-        if len(cells) > 4 and cells[1].startswith(f"`void {base}<{es}"):
-            return float(cells[3]) / 100.0
+        if len(cells) > column + 1 and cells[1].startswith(f"`void {base}<{es}"):
+            try:
+                return float(cells[column]) / 100.0
+            except ValueError:
+                return None
     return None
 
 
@@ -445,7 +449,7 @@ def _roofline(kernels, info, sp, prob):
         peak = PEAK_FP64_TFLOPS if "double" in name else PEAK_FP32_TFLOPS
         ach, u = work / t / 1e12, "TFLOP/s"
     return {"kernel": name, "bound": bound, "achieved": ach, "peak": peak, "unit": u, "frac": ach / peak,
-            "traffic": _traffic(name), "lds_util": _lds_util(name),
+            "traffic": _traffic(name), "lds_util": _lds_util(name), "valu_busy": _lds_util(name, 5),
             "algorithmic_per_launch": work, "algorithmic_unit": unit,
             "launch_ms": t * 1e3, "share_of_step": kernels[name]["ms_per_step"] / sum(
                 v["ms_per_step"] for v in kernels.values())}
