@@ -253,7 +253,12 @@ def _leg(a, ctx, sp, prob, c, out, info):
         flops = 2.0 * info["nb"] * prob.norb ** 2 * info["nnz_single"][0]
         for prec, name, peak in ((sqd.FP64, "fp64", PEAK_FP64_TFLOPS), (sqd.FP32, "fp32", PEAK_FP32_TFLOPS)):
             d = kernels(lambda: sp.sigma(c, out, precision=prec, terms=sqd.TERM_AB))
-            k = kernels(lambda: sp.sigma(c, out, precision=prec, terms=sqd.TERM_AB, ab_path=sqd.AB_KH))
+            try:
+                k = kernels(lambda: sp.sigma(c, out, precision=prec, terms=sqd.TERM_AB, ab_path=sqd.AB_KH))
+            except sqd.SQDError as e:   # e.g. a source row too long for the KH tile's LDS
+                print(json.dumps({"leg": "kh", "workload": prob.name, "precision": name, "direct_ms": d,
+                                  "kh_error": str(e)}), flush=True)
+                continue
             t = [v for n_, v in k.items() if n_.startswith("k_ab_kh")][0] / 1e3
             print(json.dumps({"leg": "kh", "workload": prob.name, "precision": name, "direct_ms": d, "kh_ms": k,
                               "kh_gemm_flops": flops, "kh_tflops": flops / t / 1e12,
