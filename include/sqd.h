@@ -215,7 +215,12 @@ int sqd_diag(sqd_ctx* ctx, const sqd_space* space, double* diag_dev);
 /* sigma_dev = (selected terms of H) c_dev, both dim doubles, distinct buffers.
  * precision SQD_FP64 or SQD_FP32 (off-diagonal terms in FP32 with FP32
  * accumulation; the diagonal term and the result in FP64).  terms_mask is a
- * non-zero OR of SQD_TERM_*.  ab_path selects the alpha-beta algorithm. */
+ * non-zero OR of SQD_TERM_*.  ab_path selects the alpha-beta algorithm.
+ * The first call for a space and precision may allocate and synchronise (the
+ * grouped alpha-beta schedule, the context's scratch); later identical calls
+ * only enqueue kernels on the context's stream, so they can be captured in a
+ * HIP graph (the scratch is then shared by the graph and eager calls on the
+ * same context: do not run them concurrently). */
 int sqd_sigma(sqd_ctx* ctx, const sqd_space* space, const double* c_dev,
               double* sigma_dev, int precision, unsigned terms_mask, int ab_path);
 

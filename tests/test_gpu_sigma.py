@@ -120,6 +120,45 @@ def test_sigma_terms_fp32(ctx, name, make, term):
     sp.close()
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_sigma_graph_capture_replays(precision):
+    """sqd_sigma captured in a HIP graph (after a warm-up call has set up the
+    tables and scratch) replays to the eager result, every replay, with eager
+    library work and synchronisations between the replays."""
+    torch = need_gpu()
+    from paper_2601_16169_amd import sqd
+    banner(f"sigma graph capture precision {precision}")
+    stream = torch.cuda.Stream()
+    gctx = sqd.Context(0, stream)
+    try:
+        p = I.small_problem(10, 4, 3, 70, 97, 4)
+        sp = _space(gctx, p)
+        with torch.cuda.stream(stream):
+            c = torch.tensor(I.random_vector(sp.dim, 23), device="cuda:0")
+            c2 = torch.tensor(I.random_vector(sp.dim, 24), device="cuda:0")
+            out = torch.empty_like(c)
+            other = torch.empty_like(c)
+            eager = sp.sigma(c, precision=precision).clone()
+            sp.sigma(c, out, precision=precision)    # warm-up of this exact call
+        stream.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=stream):
+            sp.sigma(c, out, precision=precision)
+        for rep in range(4):
+            out.fill_(float("nan"))
+            graph.replay()
+            stream.synchronize()
+            assert torch.equal(out, eager), f"replay {rep} differs"
+            with torch.cuda.stream(stream):
+                sp.sigma(c2, other, precision=precision)   # eager work between replays
+            stream.synchronize()
+        o = core.Space.from_problem(p).sigma(I.random_vector(sp.dim, 23))
+        assert max(rel_err(eager.cpu().numpy(), o)) <= (1e-12 if precision == 0 else 2e-6)
+        sp.close()
+    finally:
+        gctx.close()
+
+
 def test_sigma_norb64_edge(ctx):
     """norb = 64: orbital indices up to 63 and the full 64-bit string."""
     torch = need_gpu()
