@@ -106,6 +106,10 @@ typedef struct {
                                 the diagonal included                           */
     int64_t conn_terms[4];   /* the same split as DIAG, AA, BB, AB              */
     int64_t device_bytes;    /* device memory held by the space                 */
+    int64_t kh_columns;      /* Knowles-Handy GEMM size: sum over 64-target beta
+                                tiles of targets x active pair columns (0 until
+                                the KH path has run on the space); its GEMM does
+                                2 x kh_columns x nnz_single[0] flops           */
 } sqd_space_info_t;
 
 typedef struct {

@@ -324,6 +324,9 @@ void sqd_space_free(sqd_space* sp) {
     if (sp->ab_grp) (void)hipFree(sp->ab_grp);
     if (sp->ab_chunk_pair) (void)hipFree(sp->ab_chunk_pair);
     if (sp->ab_rev) (void)hipFree(sp->ab_rev);
+    if (sp->kh_tile_off) (void)hipFree(sp->kh_tile_off);
+    if (sp->kh_pairs) (void)hipFree(sp->kh_pairs);
+    if (sp->kh_map) (void)hipFree(sp->kh_map);
     if (sp->ab_row_order) (void)hipFree(sp->ab_row_order);
     delete sp;
 }
@@ -348,6 +351,7 @@ int sqd_space_info(const sqd_space* sp, sqd_space_info_t* out) {
     out->conn_terms[3] = sp->sp[0].nnz_s * sp->sp[1].nnz_s;
     out->conn_per_sigma = out->conn_terms[0] + out->conn_terms[1] + out->conn_terms[2] + out->conn_terms[3];
     out->device_bytes = sp->bytes;
+    out->kh_columns = sp->kh_cols;
     return SQD_OK;
 }
 

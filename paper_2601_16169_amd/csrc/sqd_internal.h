@@ -135,6 +135,15 @@ struct sqd_space {
     int* ab_chunk_pair = nullptr; // pair index of each chunk
     int* ab_rev = nullptr;        // alpha singles: entry of the neighbour's row pointing back
     int* ab_row_order = nullptr;  // alpha rows by decreasing number of singles (gather order)
+    // Knowles-Handy beta tiles (64 targets each): the union of the pair columns
+    // their singles use, and for every (target, column) the source of that
+    // single (0: none, else source + 1, bit 31 = negative sign)
+    int kh_ntiles = 0;
+    int* kh_tile_off = nullptr;   // ntiles + 1 offsets into kh_pairs
+    int* kh_pairs = nullptr;      // ascending pair indices per tile
+    int* kh_map = nullptr;        // tile t: 64 x K_t entries at 64 * kh_tile_off[t]
+    int64_t kh_cols = 0;          // sum over tiles of (targets in tile) x K_t
+    int kh_kmax = 0;              // largest K_t
 };
 
 // ---- helpers (api.hip) ----

@@ -45,7 +45,7 @@ class SpaceInfo(ctypes.Structure):
                 ("na", ctypes.c_int64), ("nb", ctypes.c_int64), ("dim", ctypes.c_int64),
                 ("nnz_single", ctypes.c_int64 * 2), ("nnz_double", ctypes.c_int64 * 2),
                 ("conn_per_sigma", ctypes.c_int64), ("conn_terms", ctypes.c_int64 * 4),
-                ("device_bytes", ctypes.c_int64)]
+                ("device_bytes", ctypes.c_int64), ("kh_columns", ctypes.c_int64)]
 
 
 class DavidsonOpts(ctypes.Structure):
@@ -289,7 +289,7 @@ class Space:
         return {"norb": i.norb, "nalpha": i.nalpha, "nbeta": i.nbeta, "na": i.na, "nb": i.nb, "dim": i.dim,
                 "nnz_single": list(i.nnz_single), "nnz_double": list(i.nnz_double),
                 "conn_per_sigma": i.conn_per_sigma, "conn_terms": list(i.conn_terms),
-                "device_bytes": i.device_bytes}
+                "device_bytes": i.device_bytes, "kh_columns": i.kh_columns}
 
     def tables(self, spin: int, kind: int):
         n = self.na if spin == 0 else self.nb
