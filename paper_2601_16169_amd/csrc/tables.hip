@@ -249,6 +249,31 @@ __global__ void k_sell_fill_pk(const int* __restrict__ perm, int64_t n, int nsli
     }
 }
 
+// Order each target's entries in the sliced alpha-beta table by pair index,
+// so that lanes reading column k of a slice tend to look up nearby (often
+// equal) integrals.  Padding stays at the end of each lane's column list.
+__global__ void k_sell_sort_pairs(const int* __restrict__ perm, int64_t n, int nslices,
+                                  const int* __restrict__ sl_off, const int* __restrict__ off,
+                                  uint32_t* __restrict__ sell_pk) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (int64_t)nslices * 64) return;
+    const int sl = (int)(q >> 6), lane = (int)(q & 63);
+    const int r = perm[q];
+    if (r >= n) return;
+    const int len = off[r + 1] - off[r];
+    uint32_t* col = sell_pk + (int64_t)sl_off[sl] * 64 + lane;
+    auto key = [](uint32_t x) { return (x >> SQD_PAIR_SHIFT) & SQD_PAIR_MASK; };
+    for (int i = 1; i < len; ++i) {   // insertion sort over the lane's entries (strided by 64)
+        const uint32_t x = col[(int64_t)i * 64];
+        int j = i - 1;
+        while (j >= 0 && key(col[(int64_t)j * 64]) > key(x)) {
+            col[(int64_t)(j + 1) * 64] = col[(int64_t)j * 64];
+            --j;
+        }
+        col[(int64_t)(j + 1) * 64] = x;
+    }
+}
+
 __global__ void k_sell_fill_nbr(const int* __restrict__ perm, int64_t n, int nslices,
                                 const int* __restrict__ sl_off, const int* __restrict__ off,
                                 const int* __restrict__ nbr, int* __restrict__ sell_nbr,
@@ -498,6 +523,8 @@ int sqd_build_spin_tables(sqd_ctx* ctx, sqd_space* sp, int spin, const uint64_t*
     if ((rc = sqd_alloc(ctx, (void**)&t.sell_ab_pk, sizeof(uint32_t) * (tot_ab * 64 + 1), &sp->bytes))) return rc;
     hipLaunchKernelGGL(k_sell_fill_pk, dim3(t.nslices), dim3(256), 0, ctx->stream, t.perm_ab, n, t.nslices,
                        t.sl_ab_off, t.s_off, t.s_pk, t.sell_ab_pk, nullptr);
+    hipLaunchKernelGGL(k_sell_sort_pairs, dim3((unsigned)(((int64_t)t.nslices * 64 + 255) / 256)), dim3(256), 0,
+                       ctx->stream, t.perm_ab, n, t.nslices, t.sl_ab_off, t.s_off, t.sell_ab_pk);
     SQD_HIP(ctx, hipGetLastError());
     SQD_HIP(ctx, hipStreamSynchronize(ctx->stream));
     hipFree(mx_s); hipFree(mx_d);
