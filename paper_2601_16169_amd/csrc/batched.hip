@@ -259,7 +259,7 @@ __global__ void __launch_bounds__(kThreads) kb_start(const bdesc* __restrict__ D
             d.V[i] = v;
             acc[0] += v * v;
         }
-        block_to_partial<1>(acc, partial + (size_t)d.part0 * kPstride, units[u].y);
+        block_to_partial<1>(acc, partial + (size_t)d.part0 * kPstride, units[u].y, d.nblk);
         __syncthreads();
     }
 }

@@ -125,7 +125,7 @@ __device__ __forceinline__ void jacobi_rotation(double app, double aqq, double a
 // written to partial row `row`.  All NV entries are reduced so that every
 // register index is static.
 template <int NV>
-__device__ void block_to_partial(const double (&acc)[NV], double* __restrict__ partial, int64_t row) {
+__device__ void block_to_partial(const double (&acc)[NV], double* __restrict__ partial, int64_t row, int64_t nrows) {
     __shared__ double wred[kWaves][NV];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
@@ -138,7 +138,7 @@ __device__ void block_to_partial(const double (&acc)[NV], double* __restrict__ p
     if (threadIdx.x < NV) {
         double s = 0.0;
         for (int q = 0; q < kWaves; ++q) s += wred[q][threadIdx.x];
-        partial[(size_t)row * kPstride + threadIdx.x] = s;
+        partial[(size_t)threadIdx.x * nrows + row] = s;   // value-major: the reduction reads coalesced
     }
 }
 
@@ -151,9 +151,8 @@ __device__ void reduce_rows(const double* __restrict__ partial, int nrows, doubl
 #pragma unroll
     for (int j = 0; j < NV; ++j) acc[j] = 0.0;
     for (int b = threadIdx.x; b < nrows; b += kThreads) {
-        const double* row = partial + (size_t)b * kPstride;
 #pragma unroll
-        for (int j = 0; j < NV; ++j) acc[j] += row[j];
+        for (int j = 0; j < NV; ++j) acc[j] += partial[(size_t)j * nrows + b];
     }
     __shared__ double wred[kWaves][NV];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -274,7 +273,7 @@ __device__ __forceinline__ void d_start(const double* __restrict__ guess, const 
         V0[i] = v;
         acc[0] += v * v;
     }
-    block_to_partial<1>(acc, partial, bid);
+    block_to_partial<1>(acc, partial, bid, nblk);
 }
 
 __device__ __forceinline__ void f_norm_fin(const double* __restrict__ partial, int nrows, dav_state* st) {
@@ -342,7 +341,7 @@ __device__ __forceinline__ void d_residual(const double* __restrict__ V, const d
             for (int k = 0; k < NR; ++k) acc[k] += (k < m) ? v[k] * tv : 0.0;
         }
     });
-    block_to_partial<MT + 2>(acc, partial, bid);
+    block_to_partial<MT + 2>(acc, partial, bid, nblk);
 }
 
 // Convergence / cap / phase-switch decisions and the collapse plan.
@@ -553,7 +552,7 @@ __device__ __forceinline__ void d_orth1(const double* __restrict__ V, int64_t n,
             for (int k = 0; k < NR; ++k) acc[k] += (k < m) ? v[k] * t : 0.0;
         }
     });
-    block_to_partial<MT + 1>(acc, partial, bid);
+    block_to_partial<MT + 1>(acc, partial, bid, nblk);
 }
 
 template <int MT>
@@ -647,7 +646,7 @@ __device__ __forceinline__ void d_dots(const double* __restrict__ V, double* __r
             for (int k = 0; k < NR; ++k) acc[k] += (k < cnt) ? v[k] * s : 0.0;
         }
     });
-    block_to_partial<MT + 1>(acc, partial, bid);
+    block_to_partial<MT + 1>(acc, partial, bid, nblk);
 }
 
 // G[:, m] from the partials, m += 1, then the lowest eigenpair of G by
@@ -902,7 +901,7 @@ __device__ __forceinline__ void d_xdots(const double* __restrict__ X, int nx, co
 #pragma unroll
         for (int k = 0; k < SQD_MAXLOCK; ++k) acc[1 + k] += (k < nx) ? x[k] * vi : 0.0;
     }
-    block_to_partial<1 + SQD_MAXLOCK>(acc, partial, bid);
+    block_to_partial<1 + SQD_MAXLOCK>(acc, partial, bid, nblk);
 }
 
 __device__ __forceinline__ void f_xfin(const double* __restrict__ partial, int nrows, int nx, dav_state* st, int round) {
