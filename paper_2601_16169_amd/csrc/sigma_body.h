@@ -176,10 +176,10 @@ __device__ __forceinline__ void ss_block(const ss_args<T>& a, const T* __restric
             for (int r = 0; r < R; ++r) acc[r] += v * xr[r];
         };
         k = d0;
-        // table entries in flight: with one or two staged FP32 rows there is
-        // little LDS work per entry to cover the table's latency, so keep more
-        // loads out (measured on MI355X; FP64 with one row is slower at 16)
-        constexpr int kD = (R <= 2 && sizeof(T) == 4) ? 16 : 8;
+        // table entries in flight: sixteen for FP32, whose entries are half
+        // the bytes and whose LDS reads are cheaper; eight for FP64 (measured
+        // on MI355X: sixteen is slower there, with one row or eight)
+        constexpr int kD = sizeof(T) == 4 ? 16 : 8;
         for (; k + kD <= d1; k += kD) {
             int nbd[kD];
             T v[kD];
