@@ -283,7 +283,10 @@ def test_error_codes(ctx):
     sq.close()
 
 
-KH_CASES = [SMALL[2], SMALL[3], SMALL[4], SMALL[7]]
+# ragged tiles (53 and 97 beta strings), one alpha string, a beta side with no
+# singles (every tile has an empty pair union), no alpha electrons, full CI
+KH_CASES = [c for c in SMALL if c[0] in ("ragged_8_3_4", "sab_neq_10_4_3", "one_alpha_string", "one_beta_string",
+                                         "zero_alpha_electrons", "cfg1")]
 
 
 @pytest.mark.parametrize("name,make", KH_CASES)
