@@ -16,7 +16,7 @@ resident in HBM.  The same run also reports:
   * the CPU oracle timed on a bounded sample of rows on this host.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg2]
-       python bench.py --leg kh|rdm|roots [--workload cfg2|cfg5]   (secondary legs)
+       python bench.py --leg kh|rdm|roots [--workload cfg2|cfg3|cfg5|full14]   (secondary legs)
        python bench.py --leg batched [--tune]   (64 uneven spaces: batched vs one by one)
 """
 from __future__ import annotations

@@ -221,4 +221,13 @@ def small_problem(norb: int, nalpha: int, nbeta: int, na: int, nb: int, seed: in
     return Problem(f"small_{norb}_{nalpha}_{nbeta}_{na}_{nb}_{seed}", ints, nalpha, nbeta, a, b)
 
 
-WORKLOADS = {"cfg1": cfg1, "cfg2": cfg2, "cfg3": cfg3, "cfg5": cfg5}
+def full14() -> Problem:
+    """norb 14, 7+7, all 3432 strings per spin (full CI, dim 1.18e7): the
+    regime the Knowles-Handy form was made for, used to compare the two
+    alpha-beta paths."""
+    ints = make_integrals(14, 28, seed=9)
+    s = all_strings(14, 7)
+    return Problem("full_norb14_n7", ints, 7, 7, s, s.copy())
+
+
+WORKLOADS = {"cfg1": cfg1, "cfg2": cfg2, "cfg3": cfg3, "cfg5": cfg5, "full14": full14}
