@@ -287,6 +287,9 @@ def test_error_codes(ctx):
 # singles (every tile has an empty pair union), no alpha electrons, full CI
 KH_CASES = [c for c in SMALL if c[0] in ("ragged_8_3_4", "sab_neq_10_4_3", "one_alpha_string", "one_beta_string",
                                          "zero_alpha_electrons", "cfg1")]
+# 8008-string beta rows: in FP64 the source row no longer fits beside the
+# tiles at two workgroups per CU, so the kernel reads it from global memory
+KH_CASES.append(("kh_long_rows_16_3_6", lambda: I.small_problem(16, 3, 6, 24, 8008, 12)))
 
 
 @pytest.mark.parametrize("name,make", KH_CASES)
