@@ -35,7 +35,6 @@ void* sqd_ctx_scratch(sqd_ctx* ctx, size_t bytes, int* rc) {
     if (ctx->scratch_bytes >= bytes) return ctx->scratch;
     if (ctx->scratch) {
         (void)hipStreamSynchronize(ctx->stream);
-        if (ctx->side) (void)hipStreamSynchronize(ctx->side);
         (void)hipFree(ctx->scratch);
         ctx->scratch = nullptr;
         ctx->scratch_bytes = 0;
@@ -113,12 +112,6 @@ void sqd_destroy(sqd_ctx* ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
-    if (ctx->side) {
-        (void)hipStreamSynchronize(ctx->side);
-        (void)hipStreamDestroy(ctx->side);
-    }
-    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
-    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
     free_ham(ctx);
     if (ctx->scratch) (void)hipFree(ctx->scratch);
     if (ctx->batch_arena) (void)hipFree(ctx->batch_arena);
@@ -138,7 +131,6 @@ const char* sqd_last_error(const sqd_ctx* ctx) { return ctx ? ctx->err.c_str() :
 int sqd_synchronize(sqd_ctx* ctx) {
     if (!ctx) return SQD_E_INVALID_ARG;
     SQD_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    if (ctx->side) SQD_HIP(ctx, hipStreamSynchronize(ctx->side));
     return SQD_OK;
 }
 
@@ -159,7 +151,6 @@ int sqd_release_workspace(sqd_ctx* ctx) {
     if (!ctx) return SQD_E_INVALID_ARG;
     SQD_HIP(ctx, hipSetDevice(ctx->device));
     SQD_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    if (ctx->side) SQD_HIP(ctx, hipStreamSynchronize(ctx->side));
     if (ctx->scratch) (void)hipFree(ctx->scratch);
     if (ctx->batch_arena) (void)hipFree(ctx->batch_arena);
     if (ctx->dav_arena) (void)hipFree(ctx->dav_arena);
@@ -181,7 +172,6 @@ int sqd_profile(sqd_ctx* ctx, int enable) {
 int sqd_profile_report(sqd_ctx* ctx, char* buf, int len) {
     if (!ctx || !buf || len < 1) return SQD_E_INVALID_ARG;
     SQD_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    if (ctx->side) SQD_HIP(ctx, hipStreamSynchronize(ctx->side));
     std::vector<std::pair<std::string, std::pair<int, double>>> agg;
     for (auto& r : ctx->prof) {
         float ms = 0.f;

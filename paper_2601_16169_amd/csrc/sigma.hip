@@ -284,8 +284,7 @@ int pick_chunk(sqd_ctx* ctx, int64_t nb, int norb, size_t es) {
 template <typename T>
 int launch_same_spin(sqd_ctx* ctx, const T* X, T* Y, int64_t nrows, int64_t ncols, const spin_tables& col,
                      const spin_tables& row, const T* jk, int norb, const double* diag, int accumulate,
-                     const int* skip, const char* timer_name, hipStream_t st = nullptr) {
-    if (!st) st = ctx->stream;
+                     const int* skip, const char* timer_name) {
     const size_t es = sizeof(T);
     const int R = pick_rows(ctx, nrows, ncols, norb, es);
     if (R == 0) return sqd_fail(ctx, SQD_E_LIMIT, "same-spin row does not fit in LDS (too many strings)");
@@ -301,11 +300,11 @@ int launch_same_spin(sqd_ctx* ctx, const T* X, T* Y, int64_t nrows, int64_t ncol
     else { sv = (const T*)col.sell_s_v32; dv = (const T*)col.sell_d_v32; }
     ss_args<T> args{X, Y, nrows, ncols, col.perm_ss, col.nslices, col.sl_s_off, col.sl_d_off, col.sell_s_pk, sv,
                     col.sell_d_nbr, dv, row.str, diag, accumulate};
-    prof_scope ps(ctx, timer_name, st);
+    prof_scope ps(ctx, timer_name);
 #define SQD_SS_LAUNCH(RR)                                                                                    \
     case RR:                                                                                                 \
         set_lds(k_same_spin<T, RR>, (int)lds);                                                               \
-        hipLaunchKernelGGL((k_same_spin<T, RR>), grid, block, lds, st, args, jk, norb, skip);                \
+        hipLaunchKernelGGL((k_same_spin<T, RR>), grid, block, lds, ctx->stream, args, jk, norb, skip);       \
         break;
     switch (R) {
         SQD_SS_LAUNCH(1)
@@ -506,16 +505,6 @@ static int space_scratch_get(sqd_ctx* ctx, sqd_space* sp, size_t bytes, void** o
     return SQD_OK;
 }
 
-// The second stream and its fork/join events (created on the first product
-// that uses them, so a later product can be captured in a graph).
-static int ensure_side(sqd_ctx* ctx) {
-    if (ctx->side) return SQD_OK;
-    SQD_HIP(ctx, hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
-    SQD_HIP(ctx, hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
-    SQD_HIP(ctx, hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
-    return SQD_OK;
-}
-
 int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma, int precision, unsigned mask,
                    int ab_path, const float* c32_in, const int* skip) {
     int rc = sqd_ensure_diag(ctx, sp);
@@ -537,26 +526,8 @@ int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma, 
         double* Yt = Ct + dim + 64;
         double* Yab = Yt + dim + 64;
         // beta-beta (with the diagonal) writes sigma first, so that its
-        // scattered stores need no read of sigma; alpha-beta adds to it.  The
-        // alpha-alpha term runs on C^T on the second stream meanwhile (its
-        // LDS-bound kernel shares the CUs with the HBM-bound gather) and comes
-        // back through a coalesced transpose that adds, after the join.
-        const bool split = (mask & SQD_TERM_AA) && (mask & (SQD_TERM_BB | SQD_TERM_AB));
-        hipStream_t sa = ctx->stream;
-        if (split) {
-            if ((rc = ensure_side(ctx))) return rc;
-            SQD_HIP(ctx, hipEventRecord(ctx->ev_fork, ctx->stream));
-            SQD_HIP(ctx, hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
-            sa = ctx->side;
-        }
-        if (mask & SQD_TERM_AA) {
-            {
-                prof_scope pt(ctx, "k_transpose<double>", sa);
-                hipLaunchKernelGGL((k_transpose<double, double, false>), tgrid, dim3(256), 0, sa, c, Ct, na, nb, skip);
-            }
-            if ((rc = launch_same_spin<double>(ctx, Ct, Yt, nb, na, A, B, ctx->jk64, norb, nullptr, 0, skip,
-                                               "k_same_spin<double>[aa]", sa))) return rc;
-        }
+        // scattered stores need no read of sigma; the alpha-alpha term comes
+        // back through a coalesced transpose that adds
         bool written = false;
         if (mask & SQD_TERM_BB) {
             if ((rc = launch_same_spin<double>(ctx, c, sigma, na, nb, B, A, ctx->jk64, norb, diag, 0, skip,
@@ -567,10 +538,26 @@ int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma, 
             hipLaunchKernelGGL(k_diag_apply, dim3(g), dim3(256), 0, ctx->stream, diag, c, sigma, dim, 0, skip);
             written = true;
         }
-        if ((mask & SQD_TERM_AB) && !written) {
-            hipLaunchKernelGGL(k_fill<double>, dim3(g), dim3(256), 0, ctx->stream, sigma, dim, 0.0, skip);
+        if (mask & SQD_TERM_AA) {
+            {
+                prof_scope pt(ctx, "k_transpose<double>");
+                hipLaunchKernelGGL((k_transpose<double, double, false>), tgrid, dim3(256), 0, ctx->stream, c, Ct, na,
+                                   nb, skip);
+            }
+            if ((rc = launch_same_spin<double>(ctx, Ct, Yt, nb, na, A, B, ctx->jk64, norb, nullptr, 0, skip,
+                                               "k_same_spin<double>[aa]"))) return rc;
+            {
+                prof_scope pt(ctx, "k_transpose<double>");
+                if (written)
+                    hipLaunchKernelGGL((k_transpose<double, double, true>), tgridT, dim3(256), 0, ctx->stream, Yt,
+                                       sigma, nb, na, skip);
+                else
+                    hipLaunchKernelGGL((k_transpose<double, double, false>), tgridT, dim3(256), 0, ctx->stream, Yt,
+                                       sigma, nb, na, skip);
+            }
             written = true;
         }
+        if (!written) hipLaunchKernelGGL(k_fill<double>, dim3(g), dim3(256), 0, ctx->stream, sigma, dim, 0.0, skip);
         if (mask & SQD_TERM_AB) {
             if (ab_path == SQD_AB_KH) {
                 if ((rc = sqd_sigma_ab_kh(ctx, sp, c, sigma, Yab, 0, skip))) return rc;
@@ -580,21 +567,6 @@ int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma, 
                 return rc;
             }
         }
-        if (split) {
-            SQD_HIP(ctx, hipEventRecord(ctx->ev_join, ctx->side));
-            SQD_HIP(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0));
-        }
-        if (mask & SQD_TERM_AA) {
-            prof_scope pt(ctx, "k_transpose<double>");
-            if (written)
-                hipLaunchKernelGGL((k_transpose<double, double, true>), tgridT, dim3(256), 0, ctx->stream, Yt, sigma,
-                                   nb, na, skip);
-            else
-                hipLaunchKernelGGL((k_transpose<double, double, false>), tgridT, dim3(256), 0, ctx->stream, Yt, sigma,
-                                   nb, na, skip);
-            written = true;
-        }
-        if (!written) hipLaunchKernelGGL(k_fill<double>, dim3(g), dim3(256), 0, ctx->stream, sigma, dim, 0.0, skip);
         SQD_HIP(ctx, hipGetLastError());
         return SQD_OK;
     }
@@ -613,22 +585,6 @@ int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma, 
         hipLaunchKernelGGL((k_convert<double, float>), dim3(g), dim3(256), 0, ctx->stream, c, C32, dim, skip);
         Cin = C32;
     }
-    const bool split = (mask & SQD_TERM_AA) && (mask & (SQD_TERM_BB | SQD_TERM_AB));
-    hipStream_t sa = ctx->stream;
-    if (split) {
-        if ((rc = ensure_side(ctx))) return rc;
-        SQD_HIP(ctx, hipEventRecord(ctx->ev_fork, ctx->stream));
-        SQD_HIP(ctx, hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
-        sa = ctx->side;
-    }
-    if (mask & SQD_TERM_AA) {
-        {
-            prof_scope pt(ctx, "k_transpose<float>", sa);
-            hipLaunchKernelGGL((k_transpose<float, float, false>), tgrid, dim3(256), 0, sa, Cin, Ct32, na, nb, skip);
-        }
-        if ((rc = launch_same_spin<float>(ctx, Ct32, Yt32, nb, na, A, B, ctx->jk32, norb, nullptr, 0, skip,
-                                          "k_same_spin<float>[aa]", sa))) return rc;
-    }
     bool written = false;
     if (mask & SQD_TERM_BB) {
         if ((rc = launch_same_spin<float>(ctx, Cin, S32, na, nb, B, A, ctx->jk32, norb, nullptr, 0, skip,
@@ -636,10 +592,26 @@ int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma, 
             return rc;
         written = true;
     }
-    if ((mask & SQD_TERM_AB) && !written) {
-        hipLaunchKernelGGL(k_fill<float>, dim3(g), dim3(256), 0, ctx->stream, S32, dim, 0.0f, skip);
+    if (mask & SQD_TERM_AA) {
+        {
+            prof_scope pt(ctx, "k_transpose<float>");
+            hipLaunchKernelGGL((k_transpose<float, float, false>), tgrid, dim3(256), 0, ctx->stream, Cin, Ct32, na, nb,
+                               skip);
+        }
+        if ((rc = launch_same_spin<float>(ctx, Ct32, Yt32, nb, na, A, B, ctx->jk32, norb, nullptr, 0, skip,
+                                              "k_same_spin<float>[aa]"))) return rc;
+        {
+            prof_scope pt(ctx, "k_transpose<float>");
+            if (written)
+                hipLaunchKernelGGL((k_transpose<float, float, true>), tgridT, dim3(256), 0, ctx->stream, Yt32, S32, nb,
+                                   na, skip);
+            else
+                hipLaunchKernelGGL((k_transpose<float, float, false>), tgridT, dim3(256), 0, ctx->stream, Yt32, S32, nb,
+                                   na, skip);
+        }
         written = true;
     }
+    if (!written) hipLaunchKernelGGL(k_fill<float>, dim3(g), dim3(256), 0, ctx->stream, S32, dim, 0.0f, skip);
     if (mask & SQD_TERM_AB) {
         if (ab_path == SQD_AB_KH) {
             if ((rc = sqd_sigma_ab_kh(ctx, sp, Cin, S32, Yab, 1, skip))) return rc;
@@ -649,21 +621,6 @@ int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma, 
             return rc;
         }
     }
-    if (split) {
-        SQD_HIP(ctx, hipEventRecord(ctx->ev_join, ctx->side));
-        SQD_HIP(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0));
-    }
-    if (mask & SQD_TERM_AA) {
-        prof_scope pt(ctx, "k_transpose<float>");
-        if (written)
-            hipLaunchKernelGGL((k_transpose<float, float, true>), tgridT, dim3(256), 0, ctx->stream, Yt32, S32, nb, na,
-                               skip);
-        else
-            hipLaunchKernelGGL((k_transpose<float, float, false>), tgridT, dim3(256), 0, ctx->stream, Yt32, S32, nb, na,
-                               skip);
-        written = true;
-    }
-    if (!written) hipLaunchKernelGGL(k_fill<float>, dim3(g), dim3(256), 0, ctx->stream, S32, dim, 0.0f, skip);
     hipLaunchKernelGGL(k_combine, dim3(g), dim3(256), 0, ctx->stream, diag, c, S32, sigma, dim, skip);
     SQD_HIP(ctx, hipGetLastError());
     return SQD_OK;

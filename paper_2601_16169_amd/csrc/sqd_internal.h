@@ -17,10 +17,6 @@
 struct sqd_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
-    // second stream (default priority) for the alpha-alpha term, which runs
-    // beside the beta-beta and alpha-beta terms; created on first use
-    hipStream_t side = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::string err;
     int tune[SQD_TUNE_COUNT] = {0, 0, 0, 0, 0, 0, 0};
     int max_lds = 65536;          // bytes of LDS a workgroup may allocate
@@ -70,15 +66,14 @@ struct prof_scope {
         if (hipEventCreate(&e) != hipSuccess) return nullptr;
         return e;
     }
-    hipStream_t st = nullptr;
-    prof_scope(sqd_ctx* c, const char* n, hipStream_t s = nullptr) : ctx(c), name(n), st(s ? s : c->stream) {
-        if (ctx->profiling && (a = take(ctx))) (void)hipEventRecord(a, st);
+    prof_scope(sqd_ctx* c, const char* n) : ctx(c), name(n) {
+        if (ctx->profiling && (a = take(ctx))) (void)hipEventRecord(a, ctx->stream);
     }
     ~prof_scope() {
         if (!a) return;
         hipEvent_t b = take(ctx);
         if (!b) return;
-        (void)hipEventRecord(b, st);
+        (void)hipEventRecord(b, ctx->stream);
         ctx->prof.push_back({name, a, b});
     }
 };
