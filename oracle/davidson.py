@@ -8,9 +8,8 @@ textbook form with the readings stated here:
   start   x0 = e_k + noise, k = argmin H_II (lowest index on ties); v0 = x0/|x0|
   loop    G = V^T A V;  (theta, y) = lowest eigenpair of G (numpy.linalg.eigh)
           x = V y;  r = A x - theta x;  stop when |r|_2 <= tol
-          if m == m_max: restart on the current Ritz vector and the previous
-          one (orthonormalised inside the subspace; only the current one when
-          m_max < 3 or the two coincide)
+          if m == m_max: collapse the basis onto the current Ritz vector x
+          (V = [x], AV = [A x])
           t_I = r_I / (theta - H_II), a denominator of size < 1e-8 replaced by
           1e-8 with the same sign (+ when it is exactly zero)
           two rounds of classical Gram-Schmidt against V, normalise, append
@@ -61,7 +60,6 @@ def davidson(apply_h: Callable[[np.ndarray], np.ndarray], diag: np.ndarray,
     AV = [apply_h(V[0])]
     hist = []
     theta, x, rn = 0.0, V[0], np.inf
-    y_prev = np.ones(1)
     for it in range(1, max_iter + 1):
         Vm = np.array(V)
         AVm = np.array(AV)
@@ -69,10 +67,6 @@ def davidson(apply_h: Callable[[np.ndarray], np.ndarray], diag: np.ndarray,
         G = 0.5 * (G + G.T)
         w, Y = np.linalg.eigh(G)
         theta, y = float(w[0]), Y[:, 0]
-        yp = np.zeros(len(y))
-        yp[:len(y_prev)] = y_prev
-        if y @ yp < 0:
-            y = -y
         x = y @ Vm
         ax = y @ AVm
         r = ax - theta * x
@@ -80,17 +74,8 @@ def davidson(apply_h: Callable[[np.ndarray], np.ndarray], diag: np.ndarray,
         hist.append((theta, rn))
         if rn <= tol:
             return Result(theta, fix_phase(x / np.linalg.norm(x)), it, rn, True, hist)
-        y_prev = y
         if len(V) == m_max:
-            q2 = yp - (y @ yp) * y
-            q2 = q2 - (y @ q2) * y
-            if m_max >= 3 and q2 @ q2 > 1e-20:
-                q2 = q2 / np.linalg.norm(q2)
-                V, AV = [x, q2 @ Vm], [ax, q2 @ AVm]
-                y_prev = np.array([1.0, 0.0])
-            else:
-                V, AV = [x], [ax]
-                y_prev = np.ones(1)
+            V, AV = [x], [ax]
             Vm = np.array(V)
         t = precondition(r, theta, diag)
         for _ in range(2):

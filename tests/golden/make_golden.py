@@ -1,7 +1,20 @@
 """Write oracle reference values for the larger workloads into tests/golden/.
 
-Calls only the CPU oracle and the seeded input generators.  Usage:
-    python tests/golden/make_golden.py cfg2
+Calls only the CPU oracle and the seeded input generators; no value here comes
+from the HIP library.  Usage (from the repository root):
+
+    python tests/golden/make_golden.py cfg2       # 4.0e6 determinants: energy + vector samples
+    python tests/golden/make_golden.py cfg4       # the 8 smallest of the 64 batched spaces
+    python tests/golden/make_golden.py cfg5_rdm   # 1- and 2-RDM of a seeded vector, 1.6e7 determinants
+
+cfg2: the oracle Davidson (plain Davidson-Liu, collapse onto the current Ritz
+vector) over the memoised CSR copy of H (pinned to the matrix-free product by
+the CPU tests), converged to 1e-11 so that its vector is accurate to well
+below the element-wise test bar; stored are the energy and the vector on its
+4096 largest entries plus 65,536 seeded rows (`cfg2_oracle_vec.npz`).
+cfg4: the same solver on each of the 8 smallest spaces, tol 1e-10.
+cfg5_rdm: gamma and Gamma of c = random_vector(dim, 55) / |c| (a seeded
+input, so that the comparison does not depend on any solver).
 """
 import json
 import os
@@ -16,42 +29,97 @@ sys.path.insert(0, ROOT)
 from paper_2601_16169_amd import inputs as I  # noqa: E402
 from oracle import core, davidson  # noqa: E402
 
+HERE = os.path.dirname(os.path.abspath(__file__))
+CFG2_TOL = 1e-11
+CFG2_TOP = 4096
+CFG2_ROWS = 65536
+CFG2_ROW_SEED = 2024
+CFG4_NSMALL = 8
+CFG4_TOL = 1e-10
+CFG5_VEC_SEED = 55
 
-def run(name: str, tol: float) -> dict:
-    prob = I.WORKLOADS[name]()
+
+def cfg2_sample_rows(dim: int) -> np.ndarray:
+    """The seeded rows at which the cfg2 vector is stored (sorted)."""
+    return np.sort(np.random.default_rng(CFG2_ROW_SEED).choice(dim, size=CFG2_ROWS, replace=False))
+
+
+def cfg4_smallest() -> list:
+    """Indices of the CFG4_NSMALL smallest batches (ties by index)."""
+    counts = I.cfg4_counts()
+    return [int(k) for k in np.argsort(counts, kind="stable")[:CFG4_NSMALL]]
+
+
+def _solve(prob, tol, max_iter):
     sp = core.Space.from_problem(prob)
-    t0 = time.time()
     diag = sp.diag()
-    if sp.dim > 100000:
-        # evaluate H once (same elements as the matrix-free oracle), then iterate
-        H = core.MemoisedH(sp)
-        apply_h = H.matvec
-    else:
-        apply_h = sp.sigma
-    res = davidson.davidson(apply_h, diag, I.guess_noise(sp.dim), tol=tol, max_iter=400)
+    H = core.MemoisedH(sp)
+    res = davidson.davidson(H.matvec, diag, I.guess_noise(sp.dim), tol=tol, max_iter=max_iter)
+    return sp, res, H.nnz
+
+
+def run_cfg2() -> None:
+    t0 = time.time()
+    prob = I.cfg2()
+    sp, res, nnz = _solve(prob, CFG2_TOL, 2000)
     x = res.vector
-    top = np.argsort(-np.abs(x))[:256]
-    return {
+    top = np.argsort(-np.abs(x), kind="stable")[:CFG2_TOP]
+    rows = cfg2_sample_rows(sp.dim)
+    idx = np.unique(np.concatenate([top, rows]))
+    np.savez(os.path.join(HERE, "cfg2_oracle_vec.npz"), index=idx.astype(np.int64), value=x[idx])
+    out = {
         "workload": prob.name,
-        "source": "oracle/davidson.py over oracle/sqd_oracle.c (plain Davidson-Liu, FP64)",
-        "tol": tol,
+        "source": "oracle/davidson.py over oracle.core.MemoisedH (plain Davidson-Liu, FP64)",
+        "tol": CFG2_TOL,
         "energy": res.energy,
         "iterations": res.iterations,
         "residual": res.residual,
         "converged": res.converged,
         "dim": sp.dim,
-        "top_index": [int(k) for k in top],
-        "top_value": [float(x[k]) for k in top],
+        "nnz": nnz,
+        "vector_file": "cfg2_oracle_vec.npz",
+        "vector_rows": f"the {CFG2_TOP} largest |x| entries and {CFG2_ROWS} rows drawn with seed {CFG2_ROW_SEED}",
         "seconds": time.time() - t0,
         "threads": core.num_threads(),
     }
+    json.dump(out, open(os.path.join(HERE, "cfg2_oracle.json"), "w"), indent=1)
+    print(json.dumps({k: out[k] for k in ("energy", "iterations", "residual", "seconds")}), flush=True)
+
+
+def run_cfg4() -> None:
+    t0 = time.time()
+    probs = I.cfg4()
+    out = {"workload": "cfg4_64_spaces_norb24_n8", "tol": CFG4_TOL,
+           "source": "oracle/davidson.py over oracle.core.MemoisedH (plain Davidson-Liu, FP64)", "batches": []}
+    for b in cfg4_smallest():
+        p = probs[b]
+        sp, res, nnz = _solve(p, CFG4_TOL, 2000)
+        out["batches"].append({"index": b, "name": p.name, "dim": sp.dim, "nnz": nnz, "energy": res.energy,
+                               "iterations": res.iterations, "residual": res.residual,
+                               "converged": res.converged})
+        print(json.dumps(out["batches"][-1]), flush=True)
+    out["seconds"] = time.time() - t0
+    out["threads"] = core.num_threads()
+    json.dump(out, open(os.path.join(HERE, "cfg4_oracle.json"), "w"), indent=1)
+
+
+def cfg5_vector(dim: int) -> np.ndarray:
+    c = I.random_vector(dim, CFG5_VEC_SEED)
+    return c / np.linalg.norm(c)
+
+
+def run_cfg5_rdm() -> None:
+    t0 = time.time()
+    prob = I.cfg5()
+    sp = core.Space.from_problem(prob)
+    g1, g2 = sp.rdm(cfg5_vector(sp.dim))
+    np.savez(os.path.join(HERE, "cfg5_oracle_rdm.npz"), rdm1=g1, rdm2=g2)
+    meta = {"workload": prob.name, "vector": f"random_vector(dim, {CFG5_VEC_SEED}) normalised",
+            "source": "oracle.core.Space.rdm (definition-based enumeration)", "seconds": time.time() - t0,
+            "threads": core.num_threads(), "trace_rdm1": float(np.trace(g1))}
+    json.dump(meta, open(os.path.join(HERE, "cfg5_oracle_rdm.json"), "w"), indent=1)
+    print(json.dumps(meta), flush=True)
 
 
 if __name__ == "__main__":
-    name = sys.argv[1]
-    tol = float(sys.argv[2]) if len(sys.argv) > 2 else 1e-8
-    out = run(name, tol)
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{name}_oracle.json")
-    with open(path, "w") as f:
-        json.dump(out, f, indent=1)
-    print(json.dumps({k: out[k] for k in ("energy", "iterations", "residual", "seconds")}))
+    {"cfg2": run_cfg2, "cfg4": run_cfg4, "cfg5_rdm": run_cfg5_rdm}[sys.argv[1]]()

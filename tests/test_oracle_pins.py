@@ -208,6 +208,85 @@ def test_davidson_small_restart_path():
     assert r.converged and abs(r.energy - E) <= 1e-9
 
 
+@pytest.mark.parametrize("norb,na_el,nb_el,na,nb,seed", [
+    (6, 3, 3, 20, 20, 31),    # complete-size subsets, equal electron counts
+    (7, 3, 2, 25, 18, 32),    # S_alpha != S_beta, n_alpha != n_beta
+    (8, 4, 1, 30, 8, 33),     # complete beta set of one electron
+    (5, 0, 2, 1, 10, 34),     # no alpha electrons: a single empty alpha string
+])
+def test_memoised_h_matches_matrix_free_and_dense(norb, na_el, nb_el, na, nb, seed):
+    """The CSR copy of H that the larger Davidson runs iterate with holds the
+    same matrix as the matrix-free product and the dense H (itself pinned to
+    Jordan-Wigner above): row pointers, column indices and values all checked
+    by products with unit and random vectors, and the diagonal stored first."""
+    p = I.small_problem(norb, na_el, nb_el, na, nb, seed)
+    sp_ = _space(p)
+    M = core.MemoisedH(sp_)
+    H = sp_.dense()
+    # the stored pattern is exactly the set of connected pairs
+    assert M.nnz == int(sum(M.rowptr[r + 1] - M.rowptr[r] for r in range(sp_.dim)))
+    assert np.all(M.cols[M.rowptr[:-1]] == np.arange(sp_.dim))
+    D = np.zeros_like(H)
+    for r in range(sp_.dim):
+        k0, k1 = M.rowptr[r], M.rowptr[r + 1]
+        assert len(set(M.cols[k0:k1].tolist())) == k1 - k0     # no column stored twice
+        D[r, M.cols[k0:k1]] = M.vals[k0:k1]
+    assert np.abs(D - H).max() <= 1e-15 * max(1.0, np.abs(H).max())
+    for seed_c in (1, 2):
+        c = I.random_vector(sp_.dim, seed_c)
+        s = sp_.sigma(c)
+        y = M.matvec(c)
+        assert np.abs(y - s).max() <= 1e-14 * np.abs(s).max()
+        assert np.abs(y - H @ c).max() <= 1e-13 * np.abs(s).max()
+
+
+def test_memoised_h_only_doubles_and_isolated_strings():
+    """Strings without any in-set single: alpha strings four bits apart
+    (doubles only) and one beta string (no same-spin partner at all)."""
+    norb = 8
+    ints = I.make_integrals(norb, 8, seed=35)
+    a = np.array(sorted([0b00001111, 0b00111100, 0b11110000]), dtype=np.uint64)
+    b = np.array([0b00000111], dtype=np.uint64)
+    sp_ = core.Space(norb, a, b, ints.h, ints.eri)
+    M = core.MemoisedH(sp_)
+    H = sp_.dense()
+    c = I.random_vector(sp_.dim, 3)
+    assert np.abs(M.matvec(c) - H @ c).max() <= 1e-14 * np.abs(H @ c).max()
+    assert np.abs(M.matvec(c) - sp_.sigma(c)).max() <= 1e-14 * np.abs(H @ c).max()
+
+
+def test_memoised_h_large_space_sampled_rows():
+    """A space of dimension 1.6e5 (HF-biased strings, norb 16): the CSR
+    product equals the matrix-free product on 2000 seeded rows."""
+    norb = 16
+    ints = I.make_integrals(norb, 20, seed=36)
+    s = I.sample_strings(norb, 8, 400, seed=136)
+    sp_ = core.Space(norb, s, s, ints.h, ints.eri)
+    assert sp_.dim > 100000
+    M = core.MemoisedH(sp_)
+    c = I.random_vector(sp_.dim, 4)
+    rows = np.sort(np.random.default_rng(5).choice(sp_.dim, size=2000, replace=False))
+    ref = sp_.sigma_rows(c, rows)
+    y = M.matvec(c)
+    assert np.abs(y[rows] - ref).max() <= 1e-14 * np.abs(ref).max()
+    assert np.all(M.cols[M.rowptr[:-1]] == np.arange(sp_.dim))
+
+
+def test_davidson_collapse_reaches_dense_energy():
+    """Plain collapse onto the current Ritz vector at m_max (the restart rule
+    of the oracle) on cfg1 and two small spaces: the converged energy is the
+    dense one to 1e-10, whatever m_max."""
+    for p, tol in ((I.cfg1(), 1e-10), (I.small_problem(7, 3, 2, 25, 18, 32), 1e-10),
+                   (I.small_problem(8, 4, 4, 40, 40, 37), 1e-10)):
+        sp_ = _space(p)
+        E = np.linalg.eigvalsh(sp_.dense())[0]
+        M = core.MemoisedH(sp_)    # pinned to the matrix-free product above
+        for m_max in (4, 12, 24):
+            r = davidson.davidson(M.matvec, sp_.diag(), I.guess_noise(sp_.dim), tol=tol, m_max=m_max,
+                                  max_iter=600)
+            assert r.converged and abs(r.energy - E) <= 1e-10, (p.name, m_max, r.energy - E)
+
+
 # ---------------------------------------------------------------- RDMs
 
 def test_rdms_match_jordan_wigner():
