@@ -12,10 +12,17 @@ resident in HBM.  The same run also reports:
     refinement, both from the same start vector and to the same residual
     tolerance, with the energy difference to the stored oracle value;
   * the roofline of the dominant kernel, timed live with HIP events on the
-    stream it runs on;
+    stream it runs on, and a roofline line for every kernel of the step:
+    t_roof = max(B / 8 TB/s, F / peak, VALU lane-ops / 3.9e13) against the
+    measured launch time (B, F algorithmic; VALU lane-ops from the committed
+    SQ_INSTS_VALU counter summary while the kernel sources still match it);
+  * the 2.56e8-determinant workload (norb 36): sigma FP64 / FP32 and Davidson
+    FP64 vs mixed, both against an FP64 solve converged to 1e-10;
+  * the 64-space batched workload (norb 24): batched FP64 and mixed solves,
+    the 8 smallest spaces against the oracle's stored energies;
   * the CPU oracle timed on a bounded sample of rows on this host.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg2]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg2] [--no-cfg3] [--no-cfg4]
        python bench.py --leg kh|rdm|roots [--workload cfg2|cfg3|cfg5|full14]   (secondary legs)
        python bench.py --leg batched [--tune]   (64 uneven spaces: batched vs one by one)
 """
@@ -35,6 +42,7 @@ if ROOT not in sys.path:
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
+PEAK_VALU_OPS = 256 * 4 * 16 * 2.4e9   # vector lane-operations per second (256 CUs x 4 SIMD16 x 2.4 GHz)
 COPY_BYTES = 1 << 28
 PROFILES = os.path.join(ROOT, "profiles")
 
@@ -52,6 +60,8 @@ def main():
     ap.add_argument("--no-davidson", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cfg3", action="store_true", help="skip the 2.56e8-determinant secondary keys")
+    ap.add_argument("--no-cfg4", action="store_true", help="skip the 64-space batched secondary keys")
     ap.add_argument("--profile-only", action="store_true",
                     help="only the timed sigma loop (for profilers)")
     ap.add_argument("--leg", choices=("kh", "rdm", "roots", "batched"), default=None,
@@ -109,13 +119,14 @@ def main():
     t64 = timed(lambda: sp.sigma(c, out, precision=sqd.FP64), a.steps, a.warmup)
     log(f"sigma fp64 {t64 * 1e3:.3f} ms")
     if a.profile_only:
-        # plain copy of known size, for scaling the HBM byte counters
-        src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        # a plain elementwise kernel of known size (reads COPY_BYTES, writes
+        # COPY_BYTES), for checking the scale of the HBM byte counters
+        src = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.mul(src, 2.0, out=dst)
         torch.cuda.synchronize()
-        log(f"copy calibration: {COPY_BYTES} bytes read + written per copy")
+        log(f"copy calibration: {COPY_BYTES} bytes read + written per elementwise kernel")
         return
     t32 = timed(lambda: sp.sigma(c, out, precision=sqd.FP32), a.steps, a.warmup)
     log(f"sigma fp32 {t32 * 1e3:.3f} ms")
@@ -149,7 +160,9 @@ def main():
     kernels = {k: {"calls_per_step": n / a.steps, "ms_per_step": ms / a.steps, "ms_per_launch": ms / n}
                for k, (n, ms) in kern.items()}
     log(f"kernels {kernels}")
-    roofline = _roofline(kernels, info, sp, prob)
+    counters = _counters(a.workload)
+    roofline = _roofline(kernels, info, sp, counters)
+    kernel_roofs = [_kernel_roofline(k, v, info, sp, counters) for k, v in kernels.items()]
     conn = info["conn_per_sigma"]
     result = {
         "metric": "sigma (H.c) Gdet/s + Davidson time-to-converge, mixed vs FP64, one GPU",
@@ -173,6 +186,7 @@ def main():
         "kernels": kernels,
         "tables_s": t_tables,
         "roofline": roofline,
+        "kernel_rooflines": kernel_roofs,
     }
 
     # ---- Davidson, FP64 vs mixed
@@ -199,6 +213,16 @@ def main():
         dmx, xmx = dav["mixed"]
         dmx["abs_err_vs_fp64_Ha"] = abs(dmx["energy"] - d64["energy"])
         dmx["vector_err_vs_fp64"] = float(1.0 - abs(torch.dot(x64, xmx)))
+        vec_path = os.path.join(ROOT, "tests", "golden", f"{a.workload}_oracle_vec.npz")
+        if os.path.exists(vec_path):
+            # the oracle's vector (converged to 1e-11) on its stored rows
+            z = np.load(vec_path)
+            idx = torch.tensor(z["index"], device=dev)
+            ref = z["value"]
+            for name, (d, x) in dav.items():
+                got = x[idx].cpu().numpy()
+                d["vector_max_abs_err_vs_oracle_rows"] = float(np.abs(got - ref).max())
+                d["vector_rows_compared"] = int(len(ref))
         result["davidson"] = {"tol": 1e-8, "fp64": d64, "mixed": dmx,
                               "speedup_mixed_vs_fp64": d64["seconds"] / dmx["seconds"],
                               "oracle_energy": gold["energy"] if gold else None}
@@ -228,7 +252,122 @@ def main():
                                   "max_rel_err_gpu_vs_oracle_rows": err}
         log(f"cpu baseline {result['cpu_baseline']}")
 
+    if a.workload == "cfg2":
+        sp.close()
+        ctx.release_workspace()
+        del c, out
+        torch.cuda.empty_cache()
+        if not a.no_cfg3:
+            result["cfg3"] = _secondary_cfg3(a, ctx)
+        if not a.no_cfg4:
+            result["cfg4"] = _secondary_cfg4(a)
     print(json.dumps(result))
+
+
+def _secondary_cfg3(a, ctx):
+    """2.56e8 determinants (norb 36, 12+12, 16000 strings per spin):
+    sigma FP64 / FP32 and Davidson FP64 vs mixed, both compared with an FP64
+    solve converged to 1e-10 (the oracle cannot iterate at this size; its
+    sampled-row sigma parity is a GPU test)."""
+    import torch
+    from paper_2601_16169_amd import inputs as I
+    from paper_2601_16169_amd import sqd
+    prob = I.cfg3()
+    ctx.set_hamiltonian(prob.ints.h, prob.ints.eri, prob.ints.ecore)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    sp = ctx.build_space(prob.nalpha, prob.nbeta, prob.astr, prob.bstr)
+    torch.cuda.synchronize()
+    out = {"workload": prob.name, "dim": int(sp.dim), "tables_s": time.perf_counter() - t}
+    info = sp.info()
+    out["connections_per_sigma"] = int(info["conn_per_sigma"])
+    c = torch.tensor(I.random_vector(sp.dim, 21), device="cuda:0")
+    s_ = torch.empty_like(c)
+    steps = max(1, min(a.steps, 5))
+    for prec, name in ((sqd.FP64, "fp64"), (sqd.FP32, "fp32")):
+        sp.sigma(c, s_, precision=prec)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            sp.sigma(c, s_, precision=prec)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) / steps * 1e3
+        out[f"sigma_{name}"] = {"ms": ms, "gdet_per_s": sp.dim / ms / 1e6}
+        ctx.profile(True)
+        sp.sigma(c, s_, precision=prec)
+        out[f"sigma_{name}"]["kernels_ms"] = {k: v[1] / v[0] for k, v in ctx.profile_report().items()}
+        ctx.profile(False)
+    log(f"cfg3 sigma {out['sigma_fp64']} {out['sigma_fp32']}")
+    del c, s_
+    noise = torch.tensor(I.guess_noise(sp.dim), device="cuda:0")
+    sols = {}
+    for name, mode, tol in (("fp64", sqd.DAV_FP64, 1e-8), ("mixed", sqd.DAV_MIXED, 1e-8),
+                            ("fp64_ref_1e-10", sqd.DAV_FP64, 1e-10)):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        E, x, rep = sp.davidson(tol=tol, mode=mode, noise=noise, max_iter=400)
+        torch.cuda.synchronize()
+        sols[name] = (x.clone(), {"seconds": time.perf_counter() - t, "energy": E, "tol": tol,
+                                   "iterations": rep["iterations"], "iterations_fp32": rep["iterations_fp32"],
+                                   "converged": rep["converged"], "residual": rep["residual"]})
+        del x
+        log(f"cfg3 davidson {name}: {sols[name][1]}")
+    xr, dr = sols["fp64_ref_1e-10"]
+    for name in ("fp64", "mixed"):
+        x, d = sols[name]
+        d["abs_err_vs_fp64_1e-10_Ha"] = abs(d["energy"] - dr["energy"])
+        d["vector_err_vs_fp64_1e-10"] = float(1.0 - abs(torch.dot(x, xr)))
+        out[f"davidson_{name}"] = d
+    out["davidson_fp64_ref"] = dr
+    out["speedup_mixed_vs_fp64"] = sols["fp64"][1]["seconds"] / sols["mixed"][1]["seconds"]
+    del sols, xr, noise
+    sp.close()
+    ctx.release_workspace()
+    torch.cuda.empty_cache()
+    return out
+
+
+def _secondary_cfg4(a):
+    """64 independent spaces (norb 24, 8+8, 200-3000 strings per spin) in one
+    batched call, FP64 and mixed; the 8 smallest against the oracle's stored
+    energies."""
+    import numpy as np
+    import torch
+    from paper_2601_16169_amd import inputs as I
+    from paper_2601_16169_amd import sqd
+    probs = I.cfg4()
+    ctx = sqd.Context(0)
+    try:
+        ctx.set_hamiltonian(probs[0].ints.h, probs[0].ints.eri, probs[0].ints.ecore)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        spaces = [ctx.build_space(p.nalpha, p.nbeta, p.astr, p.bstr) for p in probs]
+        torch.cuda.synchronize()
+        out = {"workload": "cfg4_64_spaces_norb24_n8", "nspaces": len(spaces),
+               "sum_dim": int(sum(s.dim for s in spaces)), "tables_s": time.perf_counter() - t,
+               "connections_per_sweep": int(sum(s.info()["conn_per_sigma"] for s in spaces))}
+        gold_path = os.path.join(ROOT, "tests", "golden", "cfg4_oracle.json")
+        gold = json.load(open(gold_path)) if os.path.exists(gold_path) else None
+        ctx.davidson_batched(spaces, tol=1e-8, max_iter=3)   # warm-up of every kernel
+        for mode, name in ((sqd.DAV_FP64, "fp64"), (sqd.DAV_MIXED, "mixed")):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            E, vecs, reps, rc = ctx.davidson_batched(spaces, tol=1e-8, max_iter=600, mode=mode)
+            torch.cuda.synchronize()
+            d = {"seconds": time.perf_counter() - t, "all_converged": all(r["converged"] for r in reps),
+                 "iterations_max": max(r["iterations"] for r in reps)}
+            if gold:
+                d["max_abs_err_vs_oracle_8_smallest_Ha"] = max(abs(E[g["index"]] - g["energy"])
+                                                             for g in gold["batches"])
+            out[f"batched_{name}"] = d
+            del vecs
+            log(f"cfg4 batched {name}: {d}")
+        out["speedup_mixed_vs_fp64"] = out["batched_fp64"]["seconds"] / out["batched_mixed"]["seconds"]
+        for s in spaces:
+            s.close()
+    finally:
+        ctx.close()
+    return out
 
 
 def _leg(a, ctx, sp, prob, c, out, info):
@@ -370,95 +509,132 @@ def _leg_batched(a):
 
 
 def _algorithmic(name, info, sp):
-    """(bound, work per launch, unit) of one kernel, from the table counts.
+    """(flops, compulsory HBM bytes) of one launch of a sigma kernel, from
+    the table counts; (None, None) for kernels not accounted here.
 
-    Pair-gather kernels: one multiply-add (2 flops) per Hamiltonian connection
-    they evaluate.  alpha-beta: every (alpha single, beta single) pair.
-    same-spin (called once per spin, the beta call also applying the
-    diagonal): the singles and doubles of that spin times the strings of the
-    other.  Gather, transpose: bytes read + written once.
+    Flops: one multiply-add (2 flops) per Hamiltonian connection the kernel
+    evaluates (alpha-beta: every alpha single x beta single pair; same-spin,
+    called once per spin: that spin's singles and doubles times the strings
+    of the other spin).  Bytes: what the launch must move at least once --
+    its input and output vectors, the intermediate it writes or reads, and
+    the tables it walks (4-byte index + one value per entry) -- not the
+    re-reads its LDS staging serves from the caches.
     """
     es = 8 if "double" in name else 4
     t = info["conn_terms"]  # diag, aa, bb, ab connections per sigma
+    dim, na, nb = sp.dim, info["na"], info["nb"]
+    ns, nd = info["nnz_single"], info["nnz_double"]
     if name.startswith(("k_ab_grouped", "k_ab_direct", "k_ab_kh")):
-        return "alu", 2.0 * t[3], "flop"
+        y = es * ns[0] * nb if name.startswith(("k_ab_grouped", "k_ab_kh")) else 2 * es * dim
+        return 2.0 * t[3], float(es * dim + y + 4 * (ns[0] + ns[1]))
     if name.startswith("k_same_spin"):
-        # [aa]: alpha-alpha launch (on C^T), [bb]: beta-beta launch
-        return "alu", 2.0 * (t[1] if name.endswith("[aa]") else t[2]), "flop"
+        aa = name.endswith("[aa]")
+        k = 0 if aa else 1
+        tables = (4 + es) * (ns[k] + nd[k])
+        vec = 2 * es * dim + (0 if aa else 8 * dim)   # X read, Y written (+ the FP64 diagonal for beta-beta)
+        return 2.0 * (t[1] if aa else t[2]), float(vec + tables)
     if name.startswith("k_ab_gather"):
-        return "hbm", float(es) * (info["nnz_single"][0] * sp.nb + 2 * sp.dim), "byte"
+        return 0.0, float(es * (ns[0] * nb + 2 * dim))
     if name.startswith("k_transpose"):
-        return "hbm", 2.0 * es * sp.dim, "byte"
-    return None, None, None
+        return 0.0, 2.0 * es * dim
+    return None, None
 
 
-def _traffic(name):
-    """HBM bytes per launch from the committed --pmc summary of this kernel,
-    or None when none is there or the kernel source changed since."""
-    import hashlib
-    base = name.split("<")[0]
-    path = os.path.join(PROFILES, f"traffic_{base}_cfg2.md")
-    if not os.path.exists(path):
-        return None
-    vals = {}
-    for line in open(path):
-        if ":" in line and line.startswith("- "):
-            k, v = line[2:].split(":", 1)
-            vals[k.strip()] = v.strip().strip("`")
-    src = vals.get("source")
-    if not src or "bytes_per_launch" not in vals:
-        return None
-    h = hashlib.sha256()
-    for f in src.split():
-        h.update(open(os.path.join(ROOT, f), "rb").read())
-    if h.hexdigest()[:16] != vals.get("source_sha256"):
-        return None
-    return float(vals["bytes_per_launch"])
-
-
-def _lds_util(name, column=3):
-    """LDS busy fraction (rocprofv3 LdsUtil; column 5: VALUBusy) of this
-    kernel from the committed summary, or None when absent or the kernel
-    source changed since."""
+def _counters(workload):
+    """Per-kernel counter figures from the committed summary
+    profiles/counters_sigma_<workload>.md, or {} when it is absent or the
+    kernel sources changed since it was taken.  Keys: the kernel cell of its
+    table; values: dict of the numeric columns (HBM bytes already scaled)."""
     import hashlib
     import re
-    path = os.path.join(PROFILES, "lds_sigma_cfg2.md")
+    path = os.path.join(PROFILES, f"counters_sigma_{workload}.md")
     if not os.path.exists(path):
-        return None
+        return {}
     text = open(path).read()
     m = re.search(r"source: `([^`]*)`", text)
     h = re.search(r"source_sha256: `([0-9a-f]+)`", text)
     if not m or not h:
-        return None
+        return {}
     d = hashlib.sha256()
     for f in m.group(1).split():
         d.update(open(os.path.join(ROOT, f), "rb").read())
     if d.hexdigest()[:16] != h.group(1):
-        return None
-    base, es = name.split("<")[0], ("double" if "double" in name else "float")
+        return {}
+    rows, head = {}, None
     for line in text.splitlines():
-        cells = [c.strip() for c in line.split("|")]
-        if len(cells) > column + 1 and cells[1].startswith(f"`void {base}<{es}"):
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) < 3 or not line.startswith("|"):
+            continue
+        if cells[0] == "kernel":
+            head = cells
+            continue
+        if head is None or set(cells[0]) <= set("-: "):
+            continue
+        vals = {}
+        for k, v in zip(head[1:], cells[1:]):
             try:
-                return float(cells[column]) / 100.0
+                vals[k] = float(v)
             except ValueError:
-                return None
+                pass
+        rows[cells[0].strip("`")] = vals
+    return rows
+
+
+def _counter_row(counters, name):
+    """The summary row of a library kernel name such as k_ab_grouped<double>
+    or k_same_spin<double>[bb] (rows are rocprofv3 names such as
+    `void k_ab_grouped<double, 4>`)."""
+    base, es = name.split("<")[0], ("double" if "double" in name else "float")
+    for k, v in counters.items():
+        if k.startswith(f"void {base}<{es}") or k.startswith(f"{base}<{es}"):
+            return v
     return None
 
 
-def _roofline(kernels, info, sp, prob):
-    """Roofline of the kernel with the largest share of the step."""
+def _kernel_roofline(name, k, info, sp, counters):
+    """t_roof = max(B / HBM peak, F / FP peak, VALU lane-ops / VALU issue
+    peak) against the measured launch time of one kernel."""
+    flops, bytes_ = _algorithmic(name, info, sp)
+    t = k["ms_per_launch"] / 1e3
+    out = {"kernel": name, "ms_per_launch": t * 1e3, "calls_per_step": k["calls_per_step"]}
+    if flops is None:
+        return out
+    peak = (PEAK_FP64_TFLOPS if "double" in name else PEAK_FP32_TFLOPS) * 1e12
+    terms = {"hbm": bytes_ / (PEAK_HBM_GBS * 1e9), "flop": flops / peak}
+    row = _counter_row(counters, name)
+    valu = None
+    if row and "SQ_INSTS_VALU" in row:
+        valu = row["SQ_INSTS_VALU"] * 64.0   # wave instructions x 64 lanes
+        terms["valu"] = valu / PEAK_VALU_OPS
+    bound = max(terms, key=terms.get)
+    out.update({"flops": flops, "bytes_algorithmic": bytes_, "valu_lane_ops": valu,
+                "t_roof_ms": terms[bound] * 1e3, "t_roof_terms_ms": {k_: v * 1e3 for k_, v in terms.items()},
+                "bound": bound, "frac": terms[bound] / t,
+                "hbm_bytes_counters": (row.get("HBM bytes") if row else None)})
+    if out["hbm_bytes_counters"]:
+        out["hbm_gbs_counters"] = out["hbm_bytes_counters"] / t / 1e9
+    return out
+
+
+def _roofline(kernels, info, sp, counters):
+    """Roofline of the kernel with the largest share of the step: the
+    pair-gather kernels against the FP ALU peak (algorithmic flops), the
+    streaming ones against HBM (algorithmic bytes)."""
     name = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
-    bound, work, unit = _algorithmic(name, info, sp)
+    flops, bytes_ = _algorithmic(name, info, sp)
     t = kernels[name]["ms_per_launch"] / 1e3
-    if bound == "hbm":
-        ach, peak, u = work / t / 1e9, PEAK_HBM_GBS, "GB/s"
-    else:
+    if flops:
+        bound = "alu"
         peak = PEAK_FP64_TFLOPS if "double" in name else PEAK_FP32_TFLOPS
-        ach, u = work / t / 1e12, "TFLOP/s"
+        ach, u, work, unit = flops / t / 1e12, "TFLOP/s", flops, "flop"
+    else:
+        bound, peak = "hbm", PEAK_HBM_GBS
+        ach, u, work, unit = bytes_ / t / 1e9, "GB/s", bytes_, "byte"
+    row = _counter_row(counters, name) or {}
     return {"kernel": name, "bound": bound, "achieved": ach, "peak": peak, "unit": u, "frac": ach / peak,
-            "traffic": _traffic(name), "lds_util": _lds_util(name), "valu_busy": _lds_util(name, 5),
-            "algorithmic_per_launch": work, "algorithmic_unit": unit,
+            "traffic": row.get("HBM bytes"), "lds_util": (row["LdsUtil %"] / 100.0 if "LdsUtil %" in row else None),
+            "valu_busy": (row["VALUBusy %"] / 100.0 if "VALUBusy %" in row else None),
+            "algorithmic_per_launch": work, "algorithmic_unit": unit, "bytes_algorithmic": bytes_,
             "launch_ms": t * 1e3, "share_of_step": kernels[name]["ms_per_step"] / sum(
                 v["ms_per_step"] for v in kernels.values())}
 

@@ -73,8 +73,8 @@ extern "C" {
 #define SQD_DAV_FP64 0
 #define SQD_DAV_MIXED 1   /* FP32 sigma until ||r|| < switch_tol, then FP64 refinement */
 
-#define SQD_MMAX 32
-#define SQD_MAXLOCK 8     /* most roots of one sqd_davidson_roots call */       /* largest Davidson subspace                         */
+#define SQD_MMAX 32       /* largest Davidson subspace (m_max)                 */
+#define SQD_MAXLOCK 8     /* most roots of one sqd_davidson_roots call         */
 #define SQD_HIST 512      /* residual history kept in the report               */
 
 /* table kinds for sqd_get_tables */
@@ -149,6 +149,11 @@ typedef struct {
  * `hip_stream` (a hipStream_t, or NULL for the default stream).  The stream
  * must outlive the context. */
 int sqd_create(int device, void* hip_stream, sqd_ctx** out);
+/* Synchronise the stream and free everything the context owns.  Spaces still
+ * open on it lose their device memory and become orphans: any call on an
+ * orphan returns SQD_E_STATE (or SQD_E_INVALID_ARG where a context is passed),
+ * and sqd_space_free on it only frees its small host record.  HIP graphs
+ * captured from calls on the context must not be replayed afterwards. */
 void sqd_destroy(sqd_ctx* ctx);
 /* Message of the last failing call on ctx (never NULL; empty if none). */
 const char* sqd_last_error(const sqd_ctx* ctx);
@@ -162,7 +167,8 @@ int sqd_get_tuning(const sqd_ctx* ctx, int key, int* value);
 /* Free the device workspaces the context keeps between calls (the product
  * and Davidson scratch, and the batched solver's arena, which holds every
  * vector of every space of the last batch); the next call that needs them
- * allocates them again.  Synchronises the context's stream. */
+ * allocates them again.  Synchronises the context's stream.  HIP graphs that
+ * captured sqd_sigma on this context must not be replayed afterwards. */
 int sqd_release_workspace(sqd_ctx* ctx);
 /* Per-kernel timers: while enabled, the single-space calls record HIP events
  * on the context's stream around each kernel they launch (the batched solver,
@@ -180,7 +186,10 @@ int sqd_profile_report(sqd_ctx* ctx, char* buf, int len);
  *   eri : norb^4, (pq|rs) at ((p*norb+q)*norb+r)*norb+s
  * Checks h = h^T and (pq|rs) = (qp|rs) = (pq|sr) = (rs|pq) to
  * 1e-12 * max|value| (else SQD_E_ASYMMETRIC).  Spaces built on ctx pick up
- * new integrals at their next use. */
+ * new integrals at their next use; spaces built for another norb fail every
+ * later call with SQD_E_STATE.  If the copy fails after the checks, the
+ * context holds no integrals (as before the first call) and every space
+ * fails with SQD_E_STATE until a call succeeds. */
 int sqd_set_hamiltonian(sqd_ctx* ctx, int norb, const double* h_host,
                         const double* eri_host, double ecore);
 
@@ -196,7 +205,11 @@ int sqd_set_hamiltonian(sqd_ctx* ctx, int norb, const double* h_host,
 int sqd_build_space(sqd_ctx* ctx, int nalpha, int nbeta,
                     const uint64_t* astr_host, int64_t na,
                     const uint64_t* bstr_host, int64_t nb, sqd_space** out);
+/* Free a space: its device memory (synchronising the context's stream) and
+ * its host record.  On an orphan (its context destroyed) only the host
+ * record is freed.  NULL is a no-op. */
 void sqd_space_free(sqd_space* space);
+/* Sizes and table counts of a space (SQD_E_STATE on an orphan). */
 int sqd_space_info(const sqd_space* space, sqd_space_info_t* out);
 
 /* Copy one table to the host in canonical order: rows by source string,
@@ -213,18 +226,28 @@ int sqd_get_tables(const sqd_space* space, int spin, int kind,
 
 /* ---- products ---------------------------------------------------------- */
 
-/* diag_dev[d] = H_dd for every determinant (dim doubles). */
+/* diag_dev[d] = H_dd for every determinant (dim doubles): the diagonal of
+ * the Hamiltonian restricted to S (Sec. II: every matrix element recomputed
+ * from the integrals; here the zero-difference Slater-Condon case). */
 int sqd_diag(sqd_ctx* ctx, const sqd_space* space, double* diag_dev);
 
-/* sigma_dev = (selected terms of H) c_dev, both dim doubles, distinct buffers.
- * precision SQD_FP64 or SQD_FP32 (off-diagonal terms in FP32 with FP32
- * accumulation; the diagonal term and the result in FP64).  terms_mask is a
- * non-zero OR of SQD_TERM_*.  ab_path selects the alpha-beta algorithm.
+/* sigma_dev = (selected terms of H) c_dev, both dim doubles, distinct buffers:
+ * the matrix-free product of Sec. II (every H_IJ recomputed from the
+ * integrals, nothing stored per determinant), split into the three task types
+ * of Sec. IV (alpha-alpha, beta-beta, one alpha plus one beta excitation)
+ * plus the diagonal.  precision SQD_FP64 or SQD_FP32 (off-diagonal terms in
+ * FP32 with FP32 accumulation; the diagonal term and the result in FP64).
+ * terms_mask is a non-zero OR of SQD_TERM_*.  ab_path selects the alpha-beta
+ * algorithm.
  * The first call for a space and precision may allocate and synchronise (the
  * grouped alpha-beta schedule, the context's scratch); later identical calls
  * only enqueue kernels on the context's stream, so they can be captured in a
- * HIP graph (the scratch is then shared by the graph and eager calls on the
- * same context: do not run them concurrently). */
+ * HIP graph.  Under capture the call allocates nothing: it returns
+ * SQD_E_STATE unless an identical eager call came first.  The scratch is
+ * shared by the graph and eager calls on the same context (do not run them
+ * concurrently); eager calls that need a larger scratch later keep the
+ * captured buffer alive until sqd_release_workspace or sqd_destroy, after
+ * which the graph must not be replayed. */
 int sqd_sigma(sqd_ctx* ctx, const sqd_space* space, const double* c_dev,
               double* sigma_dev, int precision, unsigned terms_mask, int ab_path);
 
@@ -255,7 +278,9 @@ int sqd_davidson_roots(sqd_ctx* ctx, const sqd_space* space, const sqd_davidson_
                        double* energies_host, double* vecs_dev, sqd_report* reps);
 
 /* Many independent spaces built on the same context (same integrals) solved
- * together: one persistent launch per sigma term over a work queue of
+ * together, each for its lowest root (Sec. I: the sampling loop yields many
+ * configuration sets; Sec. II/IV: the same matrix-free product per space;
+ * Sec. VI: load imbalance across uneven task groups): one persistent launch per sigma term over a work queue of
  * (space, tile) units ordered longest-first, and the Davidson iteration of all
  * spaces captured once in a hipGraph and replayed.  energies_host[nspace],
  * vecs_dev[nspace] (each that space's dim), reps[nspace] optional.

@@ -31,11 +31,33 @@ int sqd_alloc(sqd_ctx* ctx, void** p, size_t bytes, int64_t* counter) {
     return SQD_OK;
 }
 
+bool sqd_capturing(sqd_ctx* ctx) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(ctx->stream, &cs) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return cs != hipStreamCaptureStatusNone;
+}
+
+// Context scratch of at least `bytes`.  Under stream capture nothing is
+// allocated or freed: the scratch must already be large enough (else
+// SQD_E_STATE), and it is marked as referenced by a graph.  A later growth
+// then retires the old buffer instead of freeing it.
 void* sqd_ctx_scratch(sqd_ctx* ctx, size_t bytes, int* rc) {
+    if (sqd_capturing(ctx)) {
+        if (ctx->scratch_bytes < bytes) {
+            if (rc) *rc = SQD_E_STATE;
+            return nullptr;
+        }
+        ctx->scratch_captured = true;
+        return ctx->scratch;
+    }
     if (ctx->scratch_bytes >= bytes) return ctx->scratch;
     if (ctx->scratch) {
         (void)hipStreamSynchronize(ctx->stream);
-        (void)hipFree(ctx->scratch);
+        if (ctx->scratch_captured) ctx->scratch_retired.push_back(ctx->scratch);
+        else (void)hipFree(ctx->scratch);
         ctx->scratch = nullptr;
         ctx->scratch_bytes = 0;
     }
@@ -77,6 +99,30 @@ static void free_ham(sqd_ctx* ctx) {
     ctx->eri32 = ctx->jk32 = nullptr;
 }
 
+static void free_scratch(sqd_ctx* ctx) {
+    if (ctx->scratch) (void)hipFree(ctx->scratch);
+    for (void* p : ctx->scratch_retired) (void)hipFree(p);
+    ctx->scratch_retired.clear();
+    ctx->scratch = nullptr;
+    ctx->scratch_bytes = 0;
+    ctx->scratch_captured = false;
+}
+
+// Device memory of a space (the host struct stays).
+static void space_release_device(sqd_space* sp) {
+    sqd_free_spin_tables(&sp->sp[1]);
+    sqd_free_spin_tables(&sp->sp[0]);
+    void* ptrs[] = {sp->diag, sp->ua, sp->ab_grp, sp->ab_chunk_pair, sp->ab_rev, sp->kh_tile_off, sp->kh_pairs,
+                    sp->kh_map, sp->ab_row_order};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    sp->diag = sp->ua = nullptr;
+    sp->ab_grp = sp->ab_chunk_pair = sp->ab_rev = sp->kh_tile_off = sp->kh_pairs = sp->kh_map = nullptr;
+    sp->ab_row_order = nullptr;
+    sp->ab_G = 0;
+    sp->kh_ntiles = 0;
+}
+
 extern "C" {
 
 const char* sqd_version(void) { return SQD_VERSION_STRING; }
@@ -112,8 +158,15 @@ void sqd_destroy(sqd_ctx* ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    // spaces still open: release their device memory and orphan them, so that
+    // a later sqd_space_free only deletes the host struct
+    for (sqd_space* sp : ctx->spaces) {
+        space_release_device(sp);
+        sp->ctx = nullptr;
+    }
+    ctx->spaces.clear();
     free_ham(ctx);
-    if (ctx->scratch) (void)hipFree(ctx->scratch);
+    free_scratch(ctx);
     if (ctx->batch_arena) (void)hipFree(ctx->batch_arena);
     if (ctx->batch_count_host) (void)hipHostFree(ctx->batch_count_host);
     if (ctx->dav_arena) (void)hipFree(ctx->dav_arena);
@@ -151,11 +204,9 @@ int sqd_release_workspace(sqd_ctx* ctx) {
     if (!ctx) return SQD_E_INVALID_ARG;
     SQD_HIP(ctx, hipSetDevice(ctx->device));
     SQD_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    if (ctx->scratch) (void)hipFree(ctx->scratch);
+    free_scratch(ctx);
     if (ctx->batch_arena) (void)hipFree(ctx->batch_arena);
     if (ctx->dav_arena) (void)hipFree(ctx->dav_arena);
-    ctx->scratch = nullptr;
-    ctx->scratch_bytes = 0;
     ctx->batch_arena = nullptr;
     ctx->batch_arena_bytes = 0;
     ctx->dav_arena = nullptr;
@@ -236,7 +287,10 @@ int sqd_set_hamiltonian(sqd_ctx* ctx, int norb, const double* h, const double* e
                 }
     SQD_HIP(ctx, hipSetDevice(ctx->device));
     SQD_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    // from here until success the context holds no usable integrals: norb 0
+    // makes every space fail its norb check (SQD_E_STATE) if a step fails
     if (ctx->norb != norb) free_ham(ctx);
+    ctx->norb = 0;
     int rc;
     if (!ctx->h) {
         if ((rc = sqd_alloc(ctx, (void**)&ctx->h, sizeof(double) * n2, nullptr))) return rc;
@@ -305,7 +359,8 @@ int sqd_build_space(sqd_ctx* ctx, int nalpha, int nbeta, const uint64_t* astr, i
         sqd_space_free(sp);
         return rc;
     }
-    if ((rc = sqd_build_values(ctx, sp))) {
+    ctx->spaces.push_back(sp);
+    if ((rc = sqd_build_values(ctx, sp)) || (rc = sqd_ensure_diag(ctx, sp))) {
         sqd_space_free(sp);
         return rc;
     }
@@ -315,24 +370,20 @@ int sqd_build_space(sqd_ctx* ctx, int nalpha, int nbeta, const uint64_t* astr, i
 
 void sqd_space_free(sqd_space* sp) {
     if (!sp) return;
-    (void)hipSetDevice(sp->ctx->device);
-    (void)hipStreamSynchronize(sp->ctx->stream);
-    sqd_free_spin_tables(&sp->sp[1]);
-    sqd_free_spin_tables(&sp->sp[0]);
-    if (sp->diag) (void)hipFree(sp->diag);
-    if (sp->ua) (void)hipFree(sp->ua);
-    if (sp->ab_grp) (void)hipFree(sp->ab_grp);
-    if (sp->ab_chunk_pair) (void)hipFree(sp->ab_chunk_pair);
-    if (sp->ab_rev) (void)hipFree(sp->ab_rev);
-    if (sp->kh_tile_off) (void)hipFree(sp->kh_tile_off);
-    if (sp->kh_pairs) (void)hipFree(sp->kh_pairs);
-    if (sp->kh_map) (void)hipFree(sp->kh_map);
-    if (sp->ab_row_order) (void)hipFree(sp->ab_row_order);
+    sqd_ctx* ctx = sp->ctx;
+    if (ctx) {   // orphans (context destroyed) hold no device memory
+        (void)hipSetDevice(ctx->device);
+        (void)hipStreamSynchronize(ctx->stream);
+        space_release_device(sp);
+        auto& v = ctx->spaces;
+        v.erase(std::remove(v.begin(), v.end(), sp), v.end());
+    }
     delete sp;
 }
 
 int sqd_space_info(const sqd_space* sp, sqd_space_info_t* out) {
     if (!sp || !out) return SQD_E_INVALID_ARG;
+    if (!sp->ctx) return SQD_E_STATE;
     std::memset(out, 0, sizeof(*out));
     out->norb = sp->norb;
     out->nalpha = sp->nalpha;
@@ -358,6 +409,7 @@ int sqd_space_info(const sqd_space* sp, sqd_space_info_t* out) {
 int sqd_get_tables(const sqd_space* sp, int spin, int kind, int64_t* offsets, uint64_t* entries) {
     if (!sp || !offsets || (spin != 0 && spin != 1) || (kind != SQD_SINGLES && kind != SQD_DOUBLES))
         return SQD_E_INVALID_ARG;
+    if (!sp->ctx) return SQD_E_STATE;
     sqd_ctx* ctx = sp->ctx;
     const spin_tables& t = sp->sp[spin];
     SQD_HIP(ctx, hipSetDevice(ctx->device));
@@ -398,6 +450,9 @@ int sqd_sigma(sqd_ctx* ctx, const sqd_space* spc, const double* c, double* sigma
     if (ab_path < SQD_AB_AUTO || ab_path > SQD_AB_KH) return sqd_fail(ctx, SQD_E_INVALID_ARG, "bad ab_path");
     if (c == sigma) return sqd_fail(ctx, SQD_E_INVALID_ARG, "c and sigma must be distinct buffers");
     SQD_HIP(ctx, hipSetDevice(ctx->device));
+    if (sqd_capturing(ctx) && !sqd_sigma_prepared(ctx, sp, precision, mask, ab_path))
+        return sqd_fail(ctx, SQD_E_STATE,
+                        "sqd_sigma under stream capture needs an earlier identical eager call on this space");
     return sqd_sigma_impl(ctx, sp, c, sigma, precision, mask, ab_path, nullptr, nullptr);
 }
 
@@ -468,6 +523,7 @@ int sqd_rdm(sqd_ctx* ctx, const sqd_space* spc, const double* c, double* rdm1, d
     if (!ctx || !spc || !c || !rdm1) return SQD_E_INVALID_ARG;
     sqd_space* sp = const_cast<sqd_space*>(spc);
     if (sp->ctx != ctx) return sqd_fail(ctx, SQD_E_INVALID_ARG, "space belongs to another context");
+    if (ctx->norb != sp->norb) return sqd_fail(ctx, SQD_E_STATE, "integrals changed norb since the space was built");
     SQD_HIP(ctx, hipSetDevice(ctx->device));
     return sqd_rdm_impl(ctx, sp, c, rdm1, rdm2);
 }

@@ -496,11 +496,31 @@ int sqd_sigma_auto_path(sqd_ctx* ctx, const sqd_space* sp, int precision) {
     return SQD_AB_DIRECT;
 }
 
+// True when a product with these arguments would allocate, copy or
+// synchronise nothing: the space's values and diagonal are current and the
+// alpha-beta path's per-space schedule exists.  (The context scratch is
+// checked separately, by its size.)
+bool sqd_sigma_prepared(sqd_ctx* ctx, const sqd_space* sp, int precision, unsigned mask, int ab_path) {
+    if (sp->values_version != ctx->ham_version || sp->diag_version != ctx->ham_version) return false;
+    if (!(mask & SQD_TERM_AB)) return true;
+    if (ab_path == SQD_AB_AUTO) ab_path = sqd_sigma_auto_path(ctx, sp, precision);
+    if (ab_path == SQD_AB_KH) return sp->kh_map != nullptr && sp->ab_rev != nullptr;
+    const size_t es = precision == SQD_FP64 ? 8 : 4;
+    if (ab_grouped_bytes(ctx, sp, es) == 0) return true;   // row-staged kernel: nothing per space
+    return sp->ab_grp != nullptr && sp->ab_G == ab_group_size(ctx, sp) && sp->ab_row_order != nullptr;
+}
+
 // Context scratch (grown on demand): FP64 path 2*dim doubles, FP32 path 4*dim floats.
 static int space_scratch_get(sqd_ctx* ctx, sqd_space* sp, size_t bytes, void** out) {
     (void)sp;
-    void* p = sqd_ctx_scratch(ctx, bytes, nullptr);
-    if (!p) return sqd_fail(ctx, SQD_E_OOM, "scratch allocation failed (" + std::to_string(bytes) + " bytes)");
+    int rc = SQD_E_OOM;
+    void* p = sqd_ctx_scratch(ctx, bytes, &rc);
+    if (!p) {
+        if (rc == SQD_E_STATE)
+            return sqd_fail(ctx, rc, "product scratch of " + std::to_string(bytes) +
+                                         " bytes not allocated before the stream capture");
+        return sqd_fail(ctx, SQD_E_OOM, "scratch allocation failed (" + std::to_string(bytes) + " bytes)");
+    }
     *out = p;
     return SQD_OK;
 }

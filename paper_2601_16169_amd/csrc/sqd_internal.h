@@ -32,9 +32,16 @@ struct sqd_ctx {
     float* jk32 = nullptr;
     double* jdiag = nullptr;      // J[p*norb+q] = (pp|qq)
     std::vector<double> h_host, eri_host;
-    // scratch shared by products on this context
+    // scratch shared by products on this context; once a call has been
+    // captured into a graph with it (scratch_captured) a grown scratch does
+    // not free the old buffer, which the graph may still use: it is retired
+    // and freed only by sqd_release_workspace / sqd_destroy
     void* scratch = nullptr;
     size_t scratch_bytes = 0;
+    bool scratch_captured = false;
+    std::vector<void*> scratch_retired;
+    // spaces built on this context (sqd_destroy releases their device memory)
+    std::vector<sqd_space*> spaces;
     // workspace of the batched solver (grown on demand, kept across calls)
     void* batch_arena = nullptr;
     size_t batch_arena_bytes = 0;
@@ -117,7 +124,7 @@ struct spin_tables {
 };
 
 struct sqd_space {
-    sqd_ctx* ctx = nullptr;
+    sqd_ctx* ctx = nullptr;       // null once the context was destroyed (orphan)
     int norb = 0;
     int nalpha = 0, nbeta = 0;
     spin_tables sp[2];            // 0 alpha, 1 beta
@@ -151,6 +158,7 @@ int sqd_fail(sqd_ctx* ctx, int code, const std::string& msg);
 int sqd_hip_fail(sqd_ctx* ctx, hipError_t e, const char* what);
 int sqd_alloc(sqd_ctx* ctx, void** p, size_t bytes, int64_t* counter);
 void* sqd_ctx_scratch(sqd_ctx* ctx, size_t bytes, int* rc);
+bool sqd_capturing(sqd_ctx* ctx);
 
 #define SQD_HIP(ctx, call)                                              \
     do {                                                                \
@@ -170,6 +178,7 @@ int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma,
                    int precision, unsigned mask, int ab_path, const float* c32_in,
                    const int* skip_flag);
 int sqd_sigma_auto_path(sqd_ctx* ctx, const sqd_space* sp, int precision);
+bool sqd_sigma_prepared(sqd_ctx* ctx, const sqd_space* sp, int precision, unsigned mask, int ab_path);
 int sqd_ensure_ab_groups(sqd_ctx* ctx, sqd_space* sp, int G);
 
 // ---- kh.hip ----

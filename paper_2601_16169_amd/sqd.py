@@ -268,8 +268,9 @@ class Space:
 
     def close(self):
         if self._h:
-            if self.ctx._h:   # a closed context has freed its spaces already
-                lib().sqd_space_free(self._h)
+            # after the context was destroyed the space is an orphan and this
+            # frees only its host record
+            lib().sqd_space_free(self._h)
             self._h = ctypes.c_void_p()
             self.ctx._spaces.discard(self)
 

@@ -114,3 +114,31 @@ def test_batched_unequal_spins(ctx, mode):
     assert abs(E[2] - w[0]) <= (1e-8 if mode == 0 else 1e-6)
     for s in spaces:
         s.close()
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_cfg4_full_batch_smallest_vs_oracle(ctx, mode):
+    """The full 64-space batched workload (norb 24, 8+8 electrons, 200-3000
+    strings per spin), solved in one batched call with the launch shapes the
+    whole batch picks: the 8 smallest spaces against the oracle's energies
+    (plain Davidson over the memoised H, tol 1e-10; tests/golden/cfg4_oracle.json,
+    written by tests/golden/make_golden.py).  Bars: FP64 <= 1e-8 Ha, mixed
+    <= 1e-6 Ha."""
+    import json
+    import os
+    torch = need_gpu()
+    banner(f"cfg4 full batch vs oracle, mode {mode}")
+    gold = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "cfg4_oracle.json")))
+    probs = I.cfg4()
+    ctx.set_hamiltonian(probs[0].ints.h, probs[0].ints.eri)
+    spaces = [ctx.build_space(p.nalpha, p.nbeta, p.astr, p.bstr) for p in probs]
+    E, vecs, reps, rc = ctx.davidson_batched(spaces, tol=1e-8, max_iter=600, mode=mode)
+    assert rc == 0 and all(r["converged"] for r in reps)
+    bar = 1e-8 if mode == 0 else 1e-6
+    for g in gold["batches"]:
+        b = g["index"]
+        assert probs[b].name == g["name"] and spaces[b].dim == g["dim"]
+        assert abs(E[b] - g["energy"]) <= bar, (g["name"], E[b], g["energy"])
+    del vecs
+    for s in spaces:
+        s.close()

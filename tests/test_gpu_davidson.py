@@ -120,22 +120,29 @@ def _golden(name):
 
 @pytest.mark.parametrize("mode", [0, 1])
 def test_cfg2_against_stored_oracle(ctx, mode):
-    """4.0e6 determinants: the energy against the oracle's Davidson (stored by
-    tests/golden/make_golden.py), the vector on its 256 largest entries, and
-    the residual of the GPU vector under the oracle sigma on sampled rows."""
+    """4.0e6 determinants against the oracle's Davidson over the memoised H
+    (converged to 1e-11; stored by tests/golden/make_golden.py): the energy,
+    and the vector element by element on its 4096 largest entries plus 65,536
+    seeded rows.  FP64 solves to 1e-11 like the oracle: energy <= 1e-8 Ha,
+    vector entries <= 1e-9.  Mixed precision solves to the benchmark's 1e-8:
+    energy <= 1e-6 Ha, vector entries <= 1e-6 (the benchmark spec states the
+    mixed vector error rather than gating it; this bound is a sanity check).
+    Also the residual of the GPU vector under the oracle sigma on sampled
+    rows."""
     torch = need_gpu()
     from paper_2601_16169_amd import sqd
     gold = _golden("cfg2")
+    z = np.load(os.path.join(GOLDEN, gold["vector_file"]))
+    idx, ref = z["index"], z["value"]
     banner(f"davidson cfg2 mode={mode}")
     p = I.cfg2()
     sp = _space(ctx, p)
-    E, x, rep = sp.davidson(tol=1e-8, mode=mode, noise=_noise(torch, sp.dim))
+    tol = 1e-11 if mode == 0 else 1e-8
+    E, x, rep = sp.davidson(tol=tol, mode=mode, noise=_noise(torch, sp.dim), max_iter=1000)
     assert rep["converged"]
     tolE = 1e-8 if mode == 0 else 1e-6
     assert abs(E - gold["energy"]) <= tolE, (E, gold["energy"])
     xv = x.cpu().numpy()
-    idx = np.array(gold["top_index"])
-    ref = np.array(gold["top_value"])
     # Phase: the largest-magnitude entry is positive.  When the two largest
     # magnitudes agree to within the solver tolerance (a flip-odd state puts
     # equal weight on (ia, ib) and (ib, ia)), either choice satisfies the rule,
@@ -143,14 +150,17 @@ def test_cfg2_against_stored_oracle(ctx, mode):
     # checked on the GPU vector itself.
     k = int(np.argmax(np.abs(xv)))
     assert xv[k] > 0
-    mag = np.abs(ref)
+    order = np.argsort(-np.abs(ref))
+    mag = np.abs(ref[order])
     sgn = 1.0
     if mag[0] - mag[1] <= 1e-6 * mag[0]:
         sgn = float(np.sign(xv[idx] @ ref))
-    assert np.abs(sgn * xv[idx] - ref).max() <= (1e-7 if mode == 0 else 1e-5)
-    rows = np.unique(np.concatenate([idx[:64], np.random.default_rng(3).choice(sp.dim, 512, replace=False)]))
+    err = float(np.abs(sgn * xv[idx] - ref).max())
+    print(f"cfg2 mode {mode}: |dE| {abs(E - gold['energy']):.2e}, max vector error on {len(idx)} rows {err:.2e}")
+    assert err <= (1e-9 if mode == 0 else 1e-6), err
+    rows = np.unique(np.concatenate([idx[order[:64]], np.random.default_rng(3).choice(sp.dim, 512, replace=False)]))
     hx = core.Space.from_problem(p).sigma_rows(xv, rows)
-    assert np.abs(hx - E * xv[rows]).max() <= 1e-7
+    assert np.abs(hx - E * xv[rows]).max() <= (1e-9 if mode == 0 else 1e-7)
     sp.close()
 
 

@@ -132,6 +132,8 @@ def test_sigma_graph_capture_replays(precision):
     gctx = sqd.Context(0, stream)
     try:
         p = I.small_problem(10, 4, 3, 70, 97, 4)
+        big_a = I.small_problem(10, 4, 3, 210, 120, 4).astr
+        big_b = I.small_problem(10, 4, 3, 210, 120, 4).bstr
         sp = _space(gctx, p)
         with torch.cuda.stream(stream):
             c = torch.tensor(I.random_vector(sp.dim, 23), device="cuda:0")
@@ -151,12 +153,116 @@ def test_sigma_graph_capture_replays(precision):
             assert torch.equal(out, eager), f"replay {rep} differs"
             with torch.cuda.stream(stream):
                 sp.sigma(c2, other, precision=precision)   # eager work between replays
+                # eager calls that need a larger scratch than the captured one
+                # (FP64 after an FP32 capture, the RDM, a larger space): the
+                # buffer the graph uses must stay alive
+                sp.sigma(c2, other, precision=0)
+                sp.rdm(c2 / torch.linalg.norm(c2))
+                if rep == 1:
+                    big = gctx.build_space(p.nalpha, p.nbeta, big_a, big_b)
+                    big.sigma(torch.ones(big.dim, dtype=torch.float64, device="cuda:0"))
+                    big.close()
             stream.synchronize()
         o = core.Space.from_problem(p).sigma(I.random_vector(sp.dim, 23))
         assert max(rel_err(eager.cpu().numpy(), o)) <= (1e-12 if precision == 0 else 2e-6)
         sp.close()
     finally:
         gctx.close()
+
+
+def test_sigma_capture_without_warmup_is_refused():
+    """Under stream capture sqd_sigma allocates nothing: on a space whose
+    product has never run eagerly it returns SQD_E_STATE."""
+    torch = need_gpu()
+    from paper_2601_16169_amd import sqd
+    banner("sigma capture without warm-up")
+    stream = torch.cuda.Stream()
+    gctx = sqd.Context(0, stream)
+    try:
+        p = I.small_problem(8, 3, 4, 37, 53, 3)
+        sp = _space(gctx, p)
+        with torch.cuda.stream(stream):
+            c = torch.tensor(I.random_vector(sp.dim, 1), device="cuda:0")
+            out = torch.empty_like(c)
+        stream.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        code = None
+        try:
+            with torch.cuda.graph(graph, stream=stream):
+                try:
+                    sp.sigma(c, out)
+                except sqd.SQDError as e:
+                    code = e.code
+        except RuntimeError:
+            pass   # an empty capture may be rejected by torch itself
+        assert code == -8
+        stream.synchronize()
+        with torch.cuda.stream(stream):
+            sp.sigma(c, out)           # eager afterwards: works
+        stream.synchronize()
+        o = core.Space.from_problem(p).sigma(I.random_vector(sp.dim, 1))
+        assert max(rel_err(out.cpu().numpy(), o)) <= 1e-12
+        sp.close()
+    finally:
+        gctx.close()
+
+
+def test_space_outlives_context_abi():
+    """Through the raw C ABI: a space still open when its context is
+    destroyed becomes an orphan; its info call fails with SQD_E_STATE and
+    sqd_space_free on it only frees the host record (no crash)."""
+    torch = need_gpu()
+    import ctypes
+    from paper_2601_16169_amd import sqd
+    banner("space outlives context")
+    L = sqd.lib()
+    p = I.small_problem(6, 3, 2, 13, 11, 2)
+    h = ctypes.c_void_p()
+    assert L.sqd_create(0, ctypes.c_void_p(torch.cuda.current_stream(0).cuda_stream), ctypes.byref(h)) == 0
+    hh = np.ascontiguousarray(p.ints.h)
+    ee = np.ascontiguousarray(p.ints.eri)
+    assert L.sqd_set_hamiltonian(h, p.norb, hh.ctypes.data_as(ctypes.c_void_p), ee.ctypes.data_as(ctypes.c_void_p),
+                                 0.0) == 0
+    a = np.ascontiguousarray(p.astr)
+    b = np.ascontiguousarray(p.bstr)
+    spaces = []
+    for _ in range(2):
+        s_ = ctypes.c_void_p()
+        assert L.sqd_build_space(h, p.nalpha, p.nbeta, a.ctypes.data_as(ctypes.c_void_p), len(a),
+                                 b.ctypes.data_as(ctypes.c_void_p), len(b), ctypes.byref(s_)) == 0
+        spaces.append(s_)
+    L.sqd_space_free(spaces[0])        # freed while the context lives
+    L.sqd_destroy(h)                   # spaces[1] is still open
+    info = sqd.SpaceInfo()
+    assert L.sqd_space_info(spaces[1], ctypes.byref(info)) == -8
+    L.sqd_space_free(spaces[1])        # orphan: host record only
+    L.sqd_space_free(None)
+
+
+def test_rdm_rejects_space_of_other_norb(ctx):
+    """A space built for norb 8 fails every call once the integrals are
+    replaced by norb-6 ones, the RDM call included (it would otherwise index
+    the new integrals and outputs with the old norb)."""
+    torch = need_gpu()
+    from paper_2601_16169_amd import sqd
+    banner("rdm norb guard")
+    p = I.small_problem(8, 3, 4, 37, 53, 3)
+    sp = _space(ctx, p)
+    c = torch.tensor(I.random_vector(sp.dim, 1), device="cuda:0")
+    c /= torch.linalg.norm(c)
+    q = I.small_problem(6, 3, 2, 13, 11, 2)
+    ctx.set_hamiltonian(q.ints.h, q.ints.eri)
+    g1 = torch.empty((8, 8), dtype=torch.float64, device="cuda:0")
+    g2 = torch.empty((8, 8, 8, 8), dtype=torch.float64, device="cuda:0")
+    import ctypes
+    rc = sqd.lib().sqd_rdm(ctx._h, sp._h, ctypes.c_void_p(c.data_ptr()), ctypes.c_void_p(g1.data_ptr()),
+                           ctypes.c_void_p(g2.data_ptr()))
+    assert rc == -8
+    for fn in (lambda: sp.sigma(c), lambda: sp.diag(), lambda: sp.davidson(max_iter=2)):
+        with pytest.raises(sqd.SQDError) as e:
+            fn()
+        assert e.value.code == -8
+    sp.close()
 
 
 def test_sigma_norb64_edge(ctx):

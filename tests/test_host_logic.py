@@ -21,48 +21,58 @@ def test_bench_refuses_more_than_one_gpu():
 
 def test_bench_counter_summaries_are_read_while_sources_match():
     import bench
-    t = bench._traffic("k_ab_grouped<double>")
-    if t is None:
-        pytest.skip("sigma sources changed since the committed counter summaries were taken")
-    assert 1e8 < t < 1e11
-    assert 0.0 < bench._lds_util("k_ab_grouped<double>") <= 1.0
-    assert 0.0 < bench._lds_util("k_ab_grouped<double>", 5) <= 1.0
-    # kernels without a summary
-    assert bench._traffic("k_not_a_kernel<double>") is None
-    assert bench._lds_util("k_residual<24>") is None
+    rows = bench._counters("cfg2")
+    if not rows:
+        pytest.skip("sigma sources changed since the committed counter summary was taken")
+    row = bench._counter_row(rows, "k_ab_grouped<double>")
+    assert row is not None and 1e8 < row["HBM bytes"] < 1e11
+    assert 0.0 < row["LdsUtil %"] <= 100.0
+    assert bench._counter_row(rows, "k_not_a_kernel<double>") is None
+    assert bench._counters("no_such_workload") == {}
 
 
-def test_bench_traffic_is_null_once_a_source_changes(tmp_path, monkeypatch):
+def test_bench_counters_are_dropped_once_a_source_changes(tmp_path, monkeypatch):
+    import hashlib
     import bench
     prof = tmp_path / "profiles"
     prof.mkdir()
     src = tmp_path / "k.hip"
     src.write_text("original")
-    import hashlib
     h = hashlib.sha256(b"original").hexdigest()[:16]
-    (prof / "traffic_k_demo_cfg2.md").write_text(
-        f"- source: `k.hip`\n- source_sha256: `{h}`\n- bytes_per_launch: `1234`\n")
+    (prof / "counters_sigma_demo.md").write_text(
+        "| kernel | dispatches | HBM bytes | SQ_INSTS_VALU |\n|---|---:|---:|---:|\n"
+        "| `void k_demo<double, 4>` | 3 | 1234 | 10 |\n\n"
+        f"- source: `k.hip`\n- source_sha256: `{h}`\n")
     monkeypatch.setattr(bench, "PROFILES", str(prof))
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench._traffic("k_demo<double>") == 1234.0
+    row = bench._counter_row(bench._counters("demo"), "k_demo<double>")
+    assert row == {"dispatches": 3.0, "HBM bytes": 1234.0, "SQ_INSTS_VALU": 10.0}
     src.write_text("edited")
-    assert bench._traffic("k_demo<double>") is None
+    assert bench._counters("demo") == {}
 
 
-def test_bench_algorithmic_work():
+def test_bench_algorithmic_work_and_kernel_roofline():
     import bench
 
     class Sp:
-        nb = 10
         dim = 100
-    info = {"conn_terms": [100, 7, 9, 40], "nnz_single": [3, 4]}
-    assert bench._algorithmic("k_ab_grouped<double>", info, Sp) == ("alu", 80.0, "flop")
-    assert bench._algorithmic("k_same_spin<double>[aa]", info, Sp) == ("alu", 14.0, "flop")
-    assert bench._algorithmic("k_same_spin<float>[bb]", info, Sp) == ("alu", 18.0, "flop")
+    info = {"conn_terms": [100, 7, 9, 40], "nnz_single": [3, 4], "nnz_double": [5, 6], "na": 10, "nb": 10}
+    assert bench._algorithmic("k_ab_grouped<double>", info, Sp) == (80.0, 8.0 * 100 + 8 * 3 * 10 + 4 * 7)
+    assert bench._algorithmic("k_same_spin<double>[aa]", info, Sp) == (14.0, 2 * 8 * 100 + 12 * 8)
+    assert bench._algorithmic("k_same_spin<float>[bb]", info, Sp) == (18.0, 2 * 4 * 100 + 8 * 100 + 8 * 10)
     # gather: Y rows (alpha singles x nb) read once, sigma read and written
-    assert bench._algorithmic("k_ab_gather<double>", info, Sp) == ("hbm", 8.0 * (3 * 10 + 200), "byte")
-    assert bench._algorithmic("k_transpose<float>", info, Sp) == ("hbm", 800.0, "byte")
-    assert bench._algorithmic("k_other", info, Sp) == (None, None, None)
+    assert bench._algorithmic("k_ab_gather<double>", info, Sp) == (0.0, 8.0 * (3 * 10 + 200))
+    assert bench._algorithmic("k_transpose<float>", info, Sp) == (0.0, 800.0)
+    assert bench._algorithmic("k_other", info, Sp) == (None, None)
+    # roofline: the largest of the three times bounds; VALU from the counters
+    k = {"ms_per_launch": 1e-3, "calls_per_step": 1.0}
+    r = bench._kernel_roofline("k_ab_grouped<double>", k, info, Sp,
+                               {"void k_ab_grouped<double, 4>": {"SQ_INSTS_VALU": 1e3, "HBM bytes": 2e3}})
+    assert r["bound"] == "valu"
+    assert r["t_roof_ms"] == pytest.approx(1e3 * 64 / bench.PEAK_VALU_OPS * 1e3)
+    assert r["frac"] == pytest.approx(r["t_roof_ms"] / 1e-3)
+    r = bench._kernel_roofline("k_transpose<double>", k, info, Sp, {})
+    assert r["bound"] == "hbm" and r["valu_lane_ops"] is None
 
 
 class FakeCtx:
