@@ -251,6 +251,27 @@ int sqd_diag(sqd_ctx* ctx, const sqd_space* space, double* diag_dev);
 int sqd_sigma(sqd_ctx* ctx, const sqd_space* space, const double* c_dev,
               double* sigma_dev, int precision, unsigned terms_mask, int ab_path);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid the allocator): the
+ * product of sqd_sigma with no allocation.  Its scratch (the transposed input
+ * and output of the alpha-alpha term, and the FP32 copies of the FP32 path) is
+ * a static device array of SQD_NOALLOC_SCRATCH_BYTES that every GPU the
+ * library runs on holds until the process ends; the alpha-beta term uses the
+ * row-staged kernel, which needs no intermediate.  Arguments as sqd_sigma
+ * (ab_path fixed to that kernel).  Limits: dim <= SQD_NOALLOC_MAX_DIM, and a
+ * source row of C plus one norb^2 integral row must fit in one workgroup's LDS
+ * (as for SQD_TUNE_AB_VARIANT 2); beyond either SQD_E_LIMIT, before anything
+ * is enqueued.  After a Hamiltonian change the first call refreshes the
+ * space's values in place (kernels and a synchronisation; under capture it
+ * returns SQD_E_STATE instead).  All calls on one GPU share the array and it
+ * keeps the last call's contents (every word the product reads is written by
+ * the same call first): calls that overlap in time on one GPU -- on other
+ * streams or contexts -- race, and must be serialised by the caller. */
+#define SQD_NOALLOC_SCRATCH_BYTES (256ull << 20)
+#define SQD_NOALLOC_MAX_DIM 16777152LL   /* (SQD_NOALLOC_SCRATCH_BYTES - 1024) / 16 */
+int sqd_sigma_noalloc(sqd_ctx* ctx, const sqd_space* space, const double* c_dev, double* sigma_dev,
+                      int precision, unsigned terms_mask);
+
 /* ---- eigensolver (Sec. I, Sec. VI: Davidson for the lowest eigenpair) --- */
 
 /* Fill opts with the defaults: tol 1e-8, max_iter 200, m_max 24, FP64,

@@ -150,6 +150,9 @@ int sqd_create(int device, void* hip_stream, sqd_ctx** out) {
         lds_optin > ctx->max_lds)
         ctx->max_lds = lds_optin;
     (void)hipGetLastError();
+    // the no-allocation product's static scratch: its address on this device
+    // (a failure surfaces as SQD_E_STATE from sqd_sigma_noalloc)
+    (void)sqd_noalloc_init(device);
     *out = ctx;
     return SQD_OK;
 }

@@ -526,9 +526,19 @@ static int space_scratch_get(sqd_ctx* ctx, sqd_space* sp, size_t bytes, void** o
 }
 
 int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma, int precision, unsigned mask,
-                   int ab_path, const float* c32_in, const int* skip) {
+                   int ab_path, const float* c32_in, const int* skip, void* ext_scratch, size_t ext_bytes) {
     int rc = sqd_ensure_diag(ctx, sp);
     if (rc) return rc;
+    // a caller-provided scratch: the row-staged alpha-beta kernel (no
+    // intermediate) and nothing taken from the context
+    auto scratch_get = [&](size_t bytes, void** out) -> int {
+        if (!ext_scratch) return space_scratch_get(ctx, sp, bytes, out);
+        if (bytes > ext_bytes)
+            return sqd_fail(ctx, SQD_E_LIMIT, "product needs " + std::to_string(bytes) + " scratch bytes, " +
+                                                  std::to_string(ext_bytes) + " available");
+        *out = ext_scratch;
+        return SQD_OK;
+    };
     const spin_tables& A = sp->sp[0];
     const spin_tables& B = sp->sp[1];
     const int64_t na = A.n, nb = B.n, dim = sp->dim;
@@ -539,9 +549,9 @@ int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma, 
     const dim3 tgrid(nblk(nb, 64), nblk(na, 64)), tgridT(nblk(na, 64), nblk(nb, 64));
     if (precision == SQD_FP64) {
         void* scr = nullptr;
-        const size_t ybytes = !(mask & SQD_TERM_AB) ? 0
+        const size_t ybytes = (!(mask & SQD_TERM_AB) || ext_scratch) ? 0
                               : (ab_path == SQD_AB_KH ? sqd_kh_bytes(sp, 8) : ab_grouped_bytes(ctx, sp, 8));
-        if ((rc = space_scratch_get(ctx, sp, sizeof(double) * 2 * (dim + 64) + ybytes, &scr))) return rc;
+        if ((rc = scratch_get(sizeof(double) * 2 * (dim + 64) + ybytes, &scr))) return rc;
         double* Ct = (double*)scr;
         double* Yt = Ct + dim + 64;
         double* Yab = Yt + dim + 64;
@@ -592,9 +602,9 @@ int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma, 
     }
     // FP32 off-diagonal terms
     void* scr = nullptr;
-    const size_t ybytes = !(mask & SQD_TERM_AB) ? 0
+    const size_t ybytes = (!(mask & SQD_TERM_AB) || ext_scratch) ? 0
                           : (ab_path == SQD_AB_KH ? sqd_kh_bytes(sp, 4) : ab_grouped_bytes(ctx, sp, 4));
-    if ((rc = space_scratch_get(ctx, sp, sizeof(float) * 4 * (dim + 64) + ybytes, &scr))) return rc;
+    if ((rc = scratch_get(sizeof(float) * 4 * (dim + 64) + ybytes, &scr))) return rc;
     float* C32 = (float*)scr;
     float* Ct32 = C32 + dim + 64;
     float* Yt32 = Ct32 + dim + 64;

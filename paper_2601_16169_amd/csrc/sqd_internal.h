@@ -166,6 +166,9 @@ bool sqd_capturing(sqd_ctx* ctx);
         if (_e != hipSuccess) return sqd_hip_fail((ctx), _e, #call);    \
     } while (0)
 
+// ---- noalloc.hip ----
+int sqd_noalloc_init(int device);   // device address of the static product scratch
+
 // ---- tables.hip ----
 int sqd_build_spin_tables(sqd_ctx* ctx, sqd_space* sp, int spin, const uint64_t* host_str,
                           int64_t n, int nel);
@@ -176,7 +179,7 @@ void sqd_free_spin_tables(spin_tables* t);
 int sqd_ensure_diag(sqd_ctx* ctx, sqd_space* sp);
 int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma,
                    int precision, unsigned mask, int ab_path, const float* c32_in,
-                   const int* skip_flag);
+                   const int* skip_flag, void* ext_scratch = nullptr, size_t ext_bytes = 0);
 int sqd_sigma_auto_path(sqd_ctx* ctx, const sqd_space* sp, int precision);
 bool sqd_sigma_prepared(sqd_ctx* ctx, const sqd_space* sp, int precision, unsigned mask, int ab_path);
 int sqd_ensure_ab_groups(sqd_ctx* ctx, sqd_space* sp, int G);

@@ -79,7 +79,7 @@ EXPORTS = [
     "sqd_get_tuning", "sqd_set_hamiltonian", "sqd_build_space", "sqd_space_free", "sqd_space_info",
     "sqd_get_tables", "sqd_diag", "sqd_sigma", "sqd_davidson_default_opts", "sqd_davidson",
     "sqd_davidson_batched", "sqd_rdm", "sqd_profile", "sqd_profile_report", "sqd_release_workspace",
-    "sqd_davidson_roots",
+    "sqd_davidson_roots", "sqd_sigma_noalloc",
 ]
 
 
@@ -109,6 +109,7 @@ def lib():
     L.sqd_get_tables.argtypes = [P, c_int, c_int, P, P]
     L.sqd_diag.argtypes = [P, P, P]
     L.sqd_sigma.argtypes = [P, P, P, P, c_int, u32, c_int]
+    L.sqd_sigma_noalloc.argtypes = [P, P, P, P, c_int, u32]
     L.sqd_davidson_default_opts.argtypes = [ctypes.POINTER(DavidsonOpts)]
     L.sqd_davidson_default_opts.restype = None
     L.sqd_davidson.argtypes = [P, P, ctypes.POINTER(DavidsonOpts), ctypes.POINTER(d), P,
@@ -316,6 +317,14 @@ class Space:
         self.ctx._check(lib().sqd_sigma(self.ctx._h, self._h, _dev_ptr(c, numel=self.dim),
                                         _dev_ptr(out, numel=self.dim), int(precision), int(terms), int(ab_path)),
                         "sqd_sigma")
+        return out
+
+    def sigma_noalloc(self, c, out, precision=FP64, terms=TERM_ALL):
+        """sigma into a caller-allocated `out` through sqd_sigma_noalloc (no
+        device allocation: the library's static scratch)."""
+        self.ctx._check(lib().sqd_sigma_noalloc(self.ctx._h, self._h, _dev_ptr(c, numel=self.dim),
+                                                _dev_ptr(out, numel=self.dim), int(precision), int(terms)),
+                        "sqd_sigma_noalloc")
         return out
 
     def davidson(self, tol=1e-8, max_iter=200, m_max=24, mode=DAV_FP64, switch_tol=1e-4, ab_path=AB_AUTO,
