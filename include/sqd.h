@@ -73,6 +73,11 @@ extern "C" {
 #define SQD_DAV_FP64 0
 #define SQD_DAV_MIXED 1   /* FP32 sigma until ||r|| < switch_tol, then FP64 refinement */
 
+/* Davidson product (Sec. II: the two methods of the CPU code) */
+#define SQD_PRODUCT_MATRIX_FREE 0   /* every H_IJ recomputed in each product (sqd_sigma)  */
+#define SQD_PRODUCT_STORED 1        /* H computed once and reused (sqd_store_hamiltonian,
+                                       sqd_spmv); FP64 only                                */
+
 #define SQD_MMAX 32       /* largest Davidson subspace (m_max)                 */
 #define SQD_MAXLOCK 8     /* most roots of one sqd_davidson_roots call         */
 #define SQD_HIST 512      /* residual history kept in the report               */
@@ -127,6 +132,9 @@ typedef struct {
     int check_every;             /* host polls the device convergence flag every k
                                     iterations (>= 1); iterations past convergence
                                     are skipped on the device                    */
+    int product;                 /* SQD_PRODUCT_*: the stored H needs a current
+                                    sqd_store_hamiltonian on the space and mode
+                                    SQD_DAV_FP64; batched solves take MATRIX_FREE */
 } sqd_davidson_opts;
 
 typedef struct {
@@ -272,10 +280,41 @@ int sqd_sigma(sqd_ctx* ctx, const sqd_space* space, const double* c_dev,
 int sqd_sigma_noalloc(sqd_ctx* ctx, const sqd_space* space, const double* c_dev, double* sigma_dev,
                       int precision, unsigned terms_mask);
 
+/* ---- stored-H mode (Sec. II: the CPU code's second method, the Hamiltonian
+ * matrix computed one time, stored, and reused in every Davidson iteration,
+ * against the matrix-free product that saves memory by recomputing) ------ */
+
+/* Evaluate H restricted to S once into CSR on the device and keep it with the
+ * space (replacing an earlier one).  Row d = ia * nb + ib holds the diagonal
+ * first, then the alpha singles and doubles of ia (columns ia' * nb + ib), the
+ * beta singles and doubles of ib (columns ia * nb + ib'), then the alpha x
+ * beta singles pairs (ia' * nb + ib', alpha-major); every in-set connection
+ * once, values as the matrix-free product uses them.  Storage: 8 (dim + 1) +
+ * 12 nnz bytes (int64 row pointer, int32 column, FP64 value), nnz =
+ * sum over rows of 1 + A(ia) + B(ib) + sa(ia) sb(ib) (A, B: singles plus
+ * doubles of each spin; sa, sb: singles), i.e. conn_per_sigma of
+ * sqd_space_info.  nnz_out (optional host pointer) receives nnz.  Errors:
+ * SQD_E_LIMIT (dim >= 2^31), SQD_E_OOM (does not fit; nothing is kept).
+ * The stored H belongs to the Hamiltonian version it was built for: after
+ * sqd_set_hamiltonian every use returns SQD_E_STATE until it is rebuilt.
+ * Synchronous. */
+int sqd_store_hamiltonian(sqd_ctx* ctx, const sqd_space* space, int64_t* nnz_out);
+/* Free the stored H of a space (no-op if none).  Synchronises the stream. */
+int sqd_release_hamiltonian(sqd_ctx* ctx, const sqd_space* space);
+/* sigma_dev = H c_dev from the stored H (all terms, FP64; dim doubles each,
+ * distinct caller-owned buffers): a sparse product bound by HBM bandwidth,
+ * 12 bytes per stored element.  SQD_E_STATE without a current stored H.
+ * Only enqueues work, so it can be captured in a HIP graph. */
+int sqd_spmv(sqd_ctx* ctx, const sqd_space* space, const double* c_dev, double* sigma_dev);
+/* Host copy of the stored H: rowptr_host (dim + 1), cols_host and vals_host
+ * (nnz each).  Synchronous. */
+int sqd_get_stored_hamiltonian(const sqd_space* space, int64_t* rowptr_host, int32_t* cols_host,
+                               double* vals_host);
+
 /* ---- eigensolver (Sec. I, Sec. VI: Davidson for the lowest eigenpair) --- */
 
 /* Fill opts with the defaults: tol 1e-8, max_iter 200, m_max 24, FP64,
- * switch_tol 1e-4, AUTO path, no guess, check_every 4. */
+ * switch_tol 1e-4, AUTO path, no guess, check_every 4, matrix-free product. */
 void sqd_davidson_default_opts(sqd_davidson_opts* opts);
 
 /* Lowest eigenpair of H restricted to S.  energy_host receives the energy

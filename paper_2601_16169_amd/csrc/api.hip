@@ -110,6 +110,7 @@ static void free_scratch(sqd_ctx* ctx) {
 
 // Device memory of a space (the host struct stays).
 static void space_release_device(sqd_space* sp) {
+    sqd_release_stored_h(sp);
     sqd_free_spin_tables(&sp->sp[1]);
     sqd_free_spin_tables(&sp->sp[0]);
     void* ptrs[] = {sp->diag, sp->ua, sp->ab_grp, sp->ab_chunk_pair, sp->ab_rev, sp->kh_tile_off, sp->kh_pairs,
@@ -469,14 +470,18 @@ void sqd_davidson_default_opts(sqd_davidson_opts* o) {
     o->switch_tol = 1e-4;
     o->ab_path = SQD_AB_AUTO;
     o->check_every = 4;
+    o->product = SQD_PRODUCT_MATRIX_FREE;
 }
 
 static int check_opts(sqd_ctx* ctx, const sqd_davidson_opts* o) {
     if (!o) return sqd_fail(ctx, SQD_E_INVALID_ARG, "null options");
     if (!(o->tol > 0.0) || o->max_iter < 1 || o->m_max < 2 || o->m_max > SQD_MMAX || o->check_every < 1 ||
         (o->mode != SQD_DAV_FP64 && o->mode != SQD_DAV_MIXED) || o->ab_path < 0 || o->ab_path > 2 ||
-        (o->mode == SQD_DAV_MIXED && !(o->switch_tol > 0.0)))
+        (o->mode == SQD_DAV_MIXED && !(o->switch_tol > 0.0)) ||
+        (o->product != SQD_PRODUCT_MATRIX_FREE && o->product != SQD_PRODUCT_STORED))
         return sqd_fail(ctx, SQD_E_INVALID_ARG, "invalid Davidson options");
+    if (o->product == SQD_PRODUCT_STORED && o->mode != SQD_DAV_FP64)
+        return sqd_fail(ctx, SQD_E_INVALID_ARG, "the stored-H product is FP64 only");
     return SQD_OK;
 }
 
@@ -488,6 +493,8 @@ int sqd_davidson(sqd_ctx* ctx, const sqd_space* spc, const sqd_davidson_opts* o,
     sqd_space* sp = const_cast<sqd_space*>(spc);
     if (sp->ctx != ctx) return sqd_fail(ctx, SQD_E_INVALID_ARG, "space belongs to another context");
     if (ctx->norb != sp->norb) return sqd_fail(ctx, SQD_E_STATE, "integrals changed norb since the space was built");
+    if (o->product == SQD_PRODUCT_STORED && (!sp->h_val || sp->h_version != ctx->ham_version))
+        return sqd_fail(ctx, SQD_E_STATE, "no current stored H on this space (call sqd_store_hamiltonian)");
     SQD_HIP(ctx, hipSetDevice(ctx->device));
     return sqd_davidson_impl(ctx, sp, o, energy, vec, rep, 1);
 }
@@ -502,6 +509,8 @@ int sqd_davidson_roots(sqd_ctx* ctx, const sqd_space* spc, const sqd_davidson_op
     if (sp->ctx != ctx) return sqd_fail(ctx, SQD_E_INVALID_ARG, "space belongs to another context");
     if (ctx->norb != sp->norb) return sqd_fail(ctx, SQD_E_STATE, "integrals changed norb since the space was built");
     if ((int64_t)nroots > sp->dim) return sqd_fail(ctx, SQD_E_INVALID_ARG, "more roots than determinants");
+    if (o->product == SQD_PRODUCT_STORED && (!sp->h_val || sp->h_version != ctx->ham_version))
+        return sqd_fail(ctx, SQD_E_STATE, "no current stored H on this space (call sqd_store_hamiltonian)");
     SQD_HIP(ctx, hipSetDevice(ctx->device));
     return sqd_davidson_impl(ctx, sp, o, energies, vecs, reps, nroots);
 }
@@ -511,6 +520,8 @@ int sqd_davidson_batched(sqd_ctx* ctx, int nspace, const sqd_space* const* space
     if (!ctx || nspace < 1 || !spaces || !energies || !vecs) return SQD_E_INVALID_ARG;
     int rc = check_opts(ctx, o);
     if (rc) return rc;
+    if (o->product != SQD_PRODUCT_MATRIX_FREE)
+        return sqd_fail(ctx, SQD_E_INVALID_ARG, "batched solves use the matrix-free product");
     std::vector<sqd_space*> sps(nspace);
     for (int b = 0; b < nspace; ++b) {
         if (!spaces[b] || !vecs[b]) return sqd_fail(ctx, SQD_E_INVALID_ARG, "null space or vector");

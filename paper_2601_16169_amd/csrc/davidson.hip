@@ -217,9 +217,14 @@ static int davidson_run(sqd_ctx* ctx, sqd_space* sp, const sqd_davidson_opts* o,
     }
     const int* skip = &w.st->done;
     int prec = prm.mixed ? SQD_FP32 : SQD_FP64;
-    if ((rc = sqd_sigma_impl(ctx, sp, w.cin, w.sout, prec, SQD_TERM_ALL, o->ab_path, prm.mixed ? w.c32 : nullptr,
-                             skip)))
-        return rc;
+    // the product: matrix-free (FP64, or FP32 off-diagonal terms from the
+    // FP32 copy of the input), or the stored H (FP64)
+    auto product = [&](int p) -> int {
+        if (o->product == SQD_PRODUCT_STORED) return sqd_spmv_impl(ctx, sp, w.cin, w.sout, skip);
+        return sqd_sigma_impl(ctx, sp, w.cin, w.sout, p, SQD_TERM_ALL, o->ab_path,
+                              p == SQD_FP32 ? w.c32 : nullptr, skip);
+    };
+    if ((rc = product(prec))) return rc;
     L::dots(g, s, w.V, w.AV, w.sout, n, w.st, w.partial);
     if (hipGetLastError() != hipSuccess) return sqd_fail(ctx, SQD_E_HIP, "launch failed in Davidson start");
 
@@ -236,9 +241,7 @@ static int davidson_run(sqd_ctx* ctx, sqd_space* sp, const sqd_davidson_opts* o,
             L::orth2(g, s, w.V, n, w.st, w.T, w.cin, prec == SQD_FP32 ? w.c32 : nullptr);
             if (nx > 0)
                 lock_project(g, s, X, nx, w.V, 1, n, w.st, w.cin, prec == SQD_FP32 ? w.c32 : nullptr, w.partial);
-            if ((rc = sqd_sigma_impl(ctx, sp, w.cin, w.sout, prec, SQD_TERM_ALL, o->ab_path,
-                                     prec == SQD_FP32 ? w.c32 : nullptr, skip)))
-                return rc;
+            if ((rc = product(prec))) return rc;
             L::dots(g, s, w.V, w.AV, w.sout, n, w.st, w.partial);
             ++enqueued;
         }
@@ -258,8 +261,7 @@ static int davidson_run(sqd_ctx* ctx, sqd_space* sp, const sqd_davidson_opts* o,
             prec = SQD_FP64;
             L::collapse(g, s, w.V, w.AV, n, w.st, 1, w.cin);
             hipLaunchKernelGGL(k_set_phase, dim3(1), dim3(64), 0, s, w.st, 1, DONE_RUNNING);
-            if ((rc = sqd_sigma_impl(ctx, sp, w.cin, w.sout, SQD_FP64, SQD_TERM_ALL, o->ab_path, nullptr, skip)))
-                return rc;
+            if ((rc = product(SQD_FP64))) return rc;
             L::dots(g, s, w.V, w.AV, w.sout, n, w.st, w.partial);
             continue;
         }

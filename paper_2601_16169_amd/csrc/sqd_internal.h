@@ -151,6 +151,13 @@ struct sqd_space {
     int* kh_map = nullptr;        // tile t: 64 x K_t entries at 64 * kh_tile_off[t]
     int64_t kh_cols = 0;          // sum over tiles of (targets in tile) x K_t
     int kh_kmax = 0;              // largest K_t
+    // stored H (CSR of H restricted to S; built on request, per Hamiltonian version)
+    int64_t* h_rowptr = nullptr;  // dim + 1
+    int* h_col = nullptr;         // nnz column indices
+    double* h_val = nullptr;      // nnz values
+    int64_t h_nnz = 0;
+    int64_t h_bytes = 0;
+    int h_version = -1;
 };
 
 // ---- helpers (api.hip) ----
@@ -188,6 +195,11 @@ int sqd_ensure_ab_groups(sqd_ctx* ctx, sqd_space* sp, int G);
 size_t sqd_kh_bytes(const sqd_space* sp, size_t es);
 int sqd_sigma_ab_kh(sqd_ctx* ctx, sqd_space* sp, const void* c, void* sigma, void* y, int fp32,
                     const int* skip_flag);
+
+// ---- stored.hip ----
+int sqd_store_h_impl(sqd_ctx* ctx, sqd_space* sp, int64_t* nnz_out);
+int sqd_spmv_impl(sqd_ctx* ctx, sqd_space* sp, const double* x, double* y, const int* skip_flag);
+void sqd_release_stored_h(sqd_space* sp);
 
 // ---- davidson.hip ----
 int sqd_davidson_impl(sqd_ctx* ctx, sqd_space* sp, const sqd_davidson_opts* o, double* energy, double* vec,

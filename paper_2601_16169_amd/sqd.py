@@ -23,6 +23,7 @@ TERM_DIAG, TERM_AA, TERM_BB, TERM_AB, TERM_ALL = 1, 2, 4, 8, 15
 FP64, FP32 = 0, 1
 AB_AUTO, AB_DIRECT, AB_KH = 0, 1, 2
 DAV_FP64, DAV_MIXED = 0, 1
+PRODUCT_MATRIX_FREE, PRODUCT_STORED = 0, 1
 SINGLES, DOUBLES = 0, 1
 (TUNE_SS_ROWS, TUNE_AB_CHUNK, TUNE_AB_WAVES, TUNE_SS_WAVES, TUNE_AB_PATH, TUNE_KH_TILE, TUNE_AB_VARIANT,
  TUNE_AB_GROUP) = range(8)
@@ -52,7 +53,7 @@ class DavidsonOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("m_max", ctypes.c_int),
                 ("mode", ctypes.c_int), ("switch_tol", ctypes.c_double), ("ab_path", ctypes.c_int),
                 ("guess_noise_dev", ctypes.c_void_p), ("guess_dev", ctypes.c_void_p),
-                ("check_every", ctypes.c_int)]
+                ("check_every", ctypes.c_int), ("product", ctypes.c_int)]
 
 
 class Report(ctypes.Structure):
@@ -79,7 +80,8 @@ EXPORTS = [
     "sqd_get_tuning", "sqd_set_hamiltonian", "sqd_build_space", "sqd_space_free", "sqd_space_info",
     "sqd_get_tables", "sqd_diag", "sqd_sigma", "sqd_davidson_default_opts", "sqd_davidson",
     "sqd_davidson_batched", "sqd_rdm", "sqd_profile", "sqd_profile_report", "sqd_release_workspace",
-    "sqd_davidson_roots", "sqd_sigma_noalloc",
+    "sqd_davidson_roots", "sqd_sigma_noalloc", "sqd_store_hamiltonian", "sqd_release_hamiltonian", "sqd_spmv",
+    "sqd_get_stored_hamiltonian",
 ]
 
 
@@ -110,6 +112,10 @@ def lib():
     L.sqd_diag.argtypes = [P, P, P]
     L.sqd_sigma.argtypes = [P, P, P, P, c_int, u32, c_int]
     L.sqd_sigma_noalloc.argtypes = [P, P, P, P, c_int, u32]
+    L.sqd_store_hamiltonian.argtypes = [P, P, ctypes.POINTER(i64)]
+    L.sqd_release_hamiltonian.argtypes = [P, P]
+    L.sqd_spmv.argtypes = [P, P, P, P]
+    L.sqd_get_stored_hamiltonian.argtypes = [P, P, P, P]
     L.sqd_davidson_default_opts.argtypes = [ctypes.POINTER(DavidsonOpts)]
     L.sqd_davidson_default_opts.restype = None
     L.sqd_davidson.argtypes = [P, P, ctypes.POINTER(DavidsonOpts), ctypes.POINTER(d), P,
@@ -247,9 +253,11 @@ class Context:
         return [energies[k] for k in range(n)], vecs, [reps[k].as_dict() for k in range(n)], rc
 
 
-def _opts(tol, max_iter, m_max, mode, switch_tol, ab_path, noise_ptr, guess_ptr, check_every):
+def _opts(tol, max_iter, m_max, mode, switch_tol, ab_path, noise_ptr, guess_ptr, check_every,
+          product=PRODUCT_MATRIX_FREE):
     o = DavidsonOpts()
     lib().sqd_davidson_default_opts(ctypes.byref(o))
+    o.product = int(product)
     o.tol, o.max_iter, o.m_max, o.mode = float(tol), int(max_iter), int(m_max), int(mode)
     o.switch_tol, o.ab_path, o.check_every = float(switch_tol), int(ab_path), int(check_every)
     o.guess_noise_dev = noise_ptr
@@ -327,14 +335,44 @@ class Space:
                         "sqd_sigma_noalloc")
         return out
 
+    def store_hamiltonian(self) -> int:
+        """Build the stored H (CSR on the device); returns its element count."""
+        nnz = ctypes.c_int64()
+        self.ctx._check(lib().sqd_store_hamiltonian(self.ctx._h, self._h, ctypes.byref(nnz)),
+                        "sqd_store_hamiltonian")
+        return nnz.value
+
+    def release_hamiltonian(self):
+        self.ctx._check(lib().sqd_release_hamiltonian(self.ctx._h, self._h), "sqd_release_hamiltonian")
+
+    def spmv(self, c, out=None):
+        """sigma = H c from the stored H."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty(self.dim, dtype=torch.float64, device=self._dev)
+        self.ctx._check(lib().sqd_spmv(self.ctx._h, self._h, _dev_ptr(c, numel=self.dim),
+                                       _dev_ptr(out, numel=self.dim)), "sqd_spmv")
+        return out
+
+    def stored_hamiltonian(self, nnz: int):
+        """Host copy (rowptr, cols, vals) of the stored H of nnz elements."""
+        rp = np.zeros(self.dim + 1, dtype=np.int64)
+        cols = np.zeros(max(nnz, 1), dtype=np.int32)
+        vals = np.zeros(max(nnz, 1), dtype=np.float64)
+        self.ctx._check(lib().sqd_get_stored_hamiltonian(self._h, rp.ctypes.data_as(ctypes.c_void_p),
+                                                         cols.ctypes.data_as(ctypes.c_void_p),
+                                                         vals.ctypes.data_as(ctypes.c_void_p)),
+                        "sqd_get_stored_hamiltonian")
+        return rp, cols[:nnz], vals[:nnz]
+
     def davidson(self, tol=1e-8, max_iter=200, m_max=24, mode=DAV_FP64, switch_tol=1e-4, ab_path=AB_AUTO,
-                 noise=None, guess=None, check_every=4, out=None):
+                 noise=None, guess=None, check_every=4, out=None, product=PRODUCT_MATRIX_FREE):
         torch = _torch()
         if out is None:
             out = torch.empty(self.dim, dtype=torch.float64, device=self._dev)
         np_ = _dev_ptr(noise, numel=self.dim) if noise is not None else None
         gp = _dev_ptr(guess, numel=self.dim) if guess is not None else None
-        o = _opts(tol, max_iter, m_max, mode, switch_tol, ab_path, np_, gp, check_every)
+        o = _opts(tol, max_iter, m_max, mode, switch_tol, ab_path, np_, gp, check_every, product)
         e = ctypes.c_double()
         rep = Report()
         rc = self.ctx._check(lib().sqd_davidson(self.ctx._h, self._h, ctypes.byref(o), ctypes.byref(e),
