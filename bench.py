@@ -219,9 +219,15 @@ def main():
             z = np.load(vec_path)
             idx = torch.tensor(z["index"], device=dev)
             ref = z["value"]
+            # a flip-odd ground state has two largest magnitudes that agree
+            # to the solver tolerance; the phase rule (largest entry positive)
+            # may then pick either, so compare up to that one global sign
+            mag = np.sort(np.abs(ref))[::-1]
+            tie = len(mag) > 1 and mag[0] - mag[1] <= 1e-6 * mag[0]
             for name, (d, x) in dav.items():
                 got = x[idx].cpu().numpy()
-                d["vector_max_abs_err_vs_oracle_rows"] = float(np.abs(got - ref).max())
+                sgn = float(np.sign(got @ ref)) if tie else 1.0
+                d["vector_max_abs_err_vs_oracle_rows"] = float(np.abs(sgn * got - ref).max())
                 d["vector_rows_compared"] = int(len(ref))
         result["davidson"] = {"tol": 1e-8, "fp64": d64, "mixed": dmx,
                               "speedup_mixed_vs_fp64": d64["seconds"] / dmx["seconds"],
