@@ -64,7 +64,7 @@ def main():
     ap.add_argument("--no-cfg4", action="store_true", help="skip the 64-space batched secondary keys")
     ap.add_argument("--profile-only", action="store_true",
                     help="only the timed sigma loop (for profilers)")
-    ap.add_argument("--leg", choices=("kh", "rdm", "roots", "batched"), default=None,
+    ap.add_argument("--leg", choices=("kh", "rdm", "roots", "batched", "stored"), default=None,
                     help="instead of the headline: time the Knowles-Handy alpha-beta path against the direct one, "
                          "the RDM backward kernels, the four lowest roots, or the batched solver on 64 uneven "
                          "spaces against solving them one by one (one JSON line each)")
@@ -424,16 +424,64 @@ def _leg(a, ctx, sp, prob, c, out, info):
             print(json.dumps({"leg": "rdm", "workload": prob.name, "two_body": two,
                               "ms": (time.perf_counter() - t) / a.steps * 1e3, "energy": E}), flush=True)
     elif a.leg == "roots":
+        # four lowest roots: locking (one solve per root) against block
+        # Davidson (one subspace), next to the single lowest root
         noise = torch.tensor(I.guess_noise(sp.dim), device="cuda:0")
+        sp.davidson_block(4, tol=1e-8, max_iter=3)   # warm-up of every kernel
         for mode, name in ((sqd.DAV_FP64, "fp64"), (sqd.DAV_MIXED, "mixed")):
             torch.cuda.synchronize()
             t = time.perf_counter()
+            E1, _, r1 = sp.davidson(tol=1e-8, mode=mode, noise=noise)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter() - t
+            t = time.perf_counter()
             E, X, reps = sp.davidson_roots(4, tol=1e-8, mode=mode, noise=noise, max_iter=400)
             torch.cuda.synchronize()
+            tl = time.perf_counter() - t
+            t = time.perf_counter()
+            Eb, Xb, repb = sp.davidson_block(4, tol=1e-8, mode=mode, max_iter=400)
+            torch.cuda.synchronize()
+            tb = time.perf_counter() - t
             print(json.dumps({"leg": "roots", "workload": prob.name, "mode": name,
-                              "seconds": time.perf_counter() - t, "energies": E,
-                              "iterations": [r["iterations"] for r in reps],
-                              "converged": all(r["converged"] for r in reps)}), flush=True)
+                              "one_root_seconds": t1, "one_root_products": r1["iterations"],
+                              "locking_seconds": tl, "locking_products": sum(r["iterations"] for r in reps),
+                              "block_seconds": tb, "block_iterations": repb[0]["iterations"],
+                              "block_products": repb[0]["products"],
+                              "block_vs_one_root": tb / t1, "locking_vs_one_root": tl / t1,
+                              "energies_locking": E, "energies_block": Eb,
+                              "max_abs_diff_Ha": max(abs(x - y) for x, y in zip(E, Eb)),
+                              "converged": all(r["converged"] for r in reps) and all(r["converged"] for r in repb)}),
+                  flush=True)
+    elif a.leg == "stored":
+        # stored H (CSR, 12 bytes per element) against the matrix-free product
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        nnz = sp.store_hamiltonian()
+        torch.cuda.synchronize()
+        t_build = time.perf_counter() - t
+        k = kernels(lambda: sp.spmv(c, out))
+        t_spmv = k["k_spmv"] / 1e3
+        mf = kernels(lambda: sp.sigma(c, out))
+        t_mf = sum(mf.values()) / 1e3
+        noise = torch.tensor(I.guess_noise(sp.dim), device="cuda:0")
+        res = {}
+        for prod, name in ((sqd.PRODUCT_STORED, "stored"), (sqd.PRODUCT_MATRIX_FREE, "matrix_free")):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            E, x, rep = sp.davidson(tol=1e-8, noise=noise, product=prod)
+            torch.cuda.synchronize()
+            res[name] = {"seconds": time.perf_counter() - t, "energy": E, "iterations": rep["iterations"],
+                         "converged": rep["converged"]}
+        stream_bytes = 12.0 * nnz + 8.0 * (sp.dim + 1) + 16.0 * sp.dim
+        print(json.dumps({"leg": "stored", "workload": prob.name, "nnz": nnz, "stored_bytes": 12 * nnz + 8 * (sp.dim + 1),
+                          "build_seconds": t_build, "spmv_ms": t_spmv * 1e3, "matrix_free_sigma_ms": t_mf * 1e3,
+                          "spmv_algorithmic_bytes": stream_bytes,
+                          "spmv_gb_per_s": stream_bytes / t_spmv / 1e9,
+                          "spmv_frac_of_hbm_peak": stream_bytes / t_spmv / (PEAK_HBM_GBS * 1e9),
+                          "davidson": res,
+                          "abs_energy_diff_Ha": abs(res["stored"]["energy"] - res["matrix_free"]["energy"])}),
+              flush=True)
+        sp.release_hamiltonian()
 
 
 def _leg_batched(a):

@@ -17,7 +17,9 @@
  *
  * Conventions shared by every entry point:
  *  - a string is a uint64 with bit p set when orbital p is occupied
- *    (norb <= 64, Sec. V-A / the bit_length discussion of Sec. IV-A);
+ *    (norb <= 64), or, for norb <= 128, two uint64 words, word q holding
+ *    orbitals 64 q .. 64 q + 63 (sqd_build_space_words): the bit_length
+ *    packing of Sec. IV-A, with up to 64 orbitals per word;
  *  - string lists are strictly ascending; the vector index of determinant
  *    (ia, ib) is d = ia * nb + ib (alpha-major, the ia-outer / ib-inner loop
  *    order of Sec. IV-A);
@@ -45,7 +47,8 @@ extern "C" {
 #define SQD_E_INVALID_ARG (-1)  /* null pointer, bad size or option           */
 #define SQD_E_UNSORTED (-2)     /* string list not strictly ascending          */
 #define SQD_E_POPCOUNT (-3)     /* a string has the wrong electron count       */
-#define SQD_E_NORB (-4)         /* norb outside [1, 64] or a bit >= norb       */
+#define SQD_E_NORB (-4)         /* norb outside [1, 128], a bit >= norb, or
+                                   norb > 64 with one-word strings           */
 #define SQD_E_ASYMMETRIC (-5)   /* integrals lack the required symmetry        */
 #define SQD_E_OOM (-6)          /* device allocation failed                    */
 #define SQD_E_HIP (-7)          /* HIP runtime error                           */
@@ -149,6 +152,8 @@ typedef struct {
     double seconds;              /* wall time of the solve, diagonal included     */
     double residual_history[SQD_HIST];
     double energy_history[SQD_HIST];
+    int products;                /* products H v evaluated (the block solver adds
+                                    up to one per unconverged root per iteration) */
 } sqd_report;
 
 /* ---- context ----------------------------------------------------------- */
@@ -207,12 +212,23 @@ int sqd_set_hamiltonian(sqd_ctx* ctx, int norb, const double* h_host,
 /* Validate the strings (strictly ascending, popcount == nalpha / nbeta, no bit
  * >= norb), upload them and build on the device the per-string single and
  * double excitation tables with fermionic signs.  astr_host / bstr_host are
- * host arrays of na / nb strings.  Requires sqd_set_hamiltonian first (for
- * norb).  Limits: na, nb <= 524287; na*nb < 2^40.  The space is owned by the
- * library; free it with sqd_space_free before destroying ctx. */
+ * host arrays of na / nb one-word strings (norb <= 64).  Requires
+ * sqd_set_hamiltonian first (for norb).  Limits: na, nb <= 131071; na*nb <
+ * 2^40.  The space is owned by the library; free it with sqd_space_free
+ * before destroying ctx. */
 int sqd_build_space(sqd_ctx* ctx, int nalpha, int nbeta,
                     const uint64_t* astr_host, int64_t na,
                     const uint64_t* bstr_host, int64_t nb, sqd_space** out);
+/* The same for strings of nwords (1 or 2) uint64 words each, word q holding
+ * orbitals 64 q .. 64 q + 63, string k at astr_host[k * nwords ..]; order is
+ * that of the strings read as integers (word nwords - 1 most significant).
+ * norb > 64 needs nwords = 2 (SQD_E_NORB otherwise).  Every later call works
+ * on the space as on a one-word space; the products stage norb^2 integral
+ * rows in LDS, so for norb near 128 the longest string lists that fit are
+ * shorter (SQD_E_LIMIT names it). */
+int sqd_build_space_words(sqd_ctx* ctx, int nalpha, int nbeta, int nwords,
+                          const uint64_t* astr_host, int64_t na,
+                          const uint64_t* bstr_host, int64_t nb, sqd_space** out);
 /* Free a space: its device memory (synchronising the context's stream) and
  * its host record.  On an orphan (its context destroyed) only the host
  * record is freed.  NULL is a no-op. */
@@ -223,9 +239,9 @@ int sqd_space_info(const sqd_space* space, sqd_space_info_t* out);
 /* Copy one table to the host in canonical order: rows by source string,
  * entries by target index ascending.  spin 0 = alpha, 1 = beta; kind
  * SQD_SINGLES or SQD_DOUBLES.  offsets_host has n+1 int64 slots (CSR),
- * entries_host has nnz uint64 slots packed as
- *   singles: target | i << 32 | a << 38 | negative << 63
- *   doubles: target | i << 32 | j << 38 | a << 44 | b << 50 | negative << 63
+ * entries_host has nnz uint64 slots packed as (7-bit orbital fields)
+ *   singles: target | i << 32 | a << 39 | negative << 63
+ *   doubles: target | i << 32 | j << 39 | a << 46 | b << 53 | negative << 63
  * where i (< j) are annihilated in the source, a (< b) created, and the sign is
  * <target| a+_a a_i |source> or <target| a+_a a+_b a_j a_i |source>.
  * Synchronous. */
@@ -335,6 +351,28 @@ int sqd_davidson(sqd_ctx* ctx, const sqd_space* space, const sqd_davidson_opts* 
  * enter later solves with their residual error.  Synchronous.  Returns
  * SQD_NOT_CONVERGED if any root missed the tolerance. */
 int sqd_davidson_roots(sqd_ctx* ctx, const sqd_space* space, const sqd_davidson_opts* opts, int nroots,
+                       double* energies_host, double* vecs_dev, sqd_report* reps);
+
+/* The nroots lowest eigenpairs (1 <= nroots <= SQD_MAXLOCK) together, by block
+ * Davidson-Liu (Sec. I: the ground and low-lying states of the projected
+ * Hamiltonian; Davidson's method extended to a block of vectors): one
+ * subspace for all roots, one correction per unconverged root per iteration
+ * (two classical Gram-Schmidt passes; kept when over 1e-6 of its norm
+ * survives), restarts on the nroots current Ritz vectors when the next
+ * corrections would exceed m_max (which must be >= 2 nroots).  Start: the
+ * nroots lowest diagonal determinants plus noise of norm about 1e-3
+ * (SplitMix64 counter streams 1..nroots).  Stops when every root's residual
+ * is <= tol.  Mixed mode: FP32 off-diagonal products until the largest
+ * residual drops below switch_tol (or the FP32 floor), then a restart on the
+ * Ritz vectors with FP64 products.  opts->guess_dev and guess_noise_dev are
+ * ignored.  energies_host[nroots] ascending; vecs_dev (nroots x dim doubles,
+ * row j = root j, caller-owned) normalised, largest-magnitude entry
+ * positive; reps[nroots] optional (shared iteration and product counts,
+ * per-root residual and history).  The small projected eigenproblem, the
+ * orthogonalisation and the residuals run on the device; the host reads the
+ * Ritz values and residual norms once per iteration.  Synchronous.  Returns
+ * SQD_NOT_CONVERGED if any root missed the tolerance. */
+int sqd_davidson_block(sqd_ctx* ctx, const sqd_space* space, const sqd_davidson_opts* opts, int nroots,
                        double* energies_host, double* vecs_dev, sqd_report* reps);
 
 /* Many independent spaces built on the same context (same integrals) solved

@@ -33,16 +33,17 @@ def lib():
         P = ctypes.c_void_p
         i64 = ctypes.c_int64
         d = ctypes.c_double
-        L.oracle_sigma.argtypes = [ctypes.c_int, P, i64, P, i64, P, P, d, P, P, ctypes.c_uint]
-        L.oracle_sigma_rows.argtypes = [ctypes.c_int, P, i64, P, i64, P, P, d, P, P, i64, P, ctypes.c_uint]
-        L.oracle_diag.argtypes = [ctypes.c_int, P, i64, P, i64, P, P, d, P]
-        L.oracle_dense.argtypes = [ctypes.c_int, P, i64, P, i64, P, P, d, P]
-        L.oracle_rdm.argtypes = [ctypes.c_int, P, i64, P, i64, P, P, P]
-        L.oracle_h_elem.argtypes = [ctypes.c_int, P, i64, P, i64, P, P, d, i64, i64, i64, i64]
+        ci = ctypes.c_int
+        L.oracle_sigma.argtypes = [ci, ci, P, i64, P, i64, P, P, d, P, P, ctypes.c_uint]
+        L.oracle_sigma_rows.argtypes = [ci, ci, P, i64, P, i64, P, P, d, P, P, i64, P, ctypes.c_uint]
+        L.oracle_diag.argtypes = [ci, ci, P, i64, P, i64, P, P, d, P]
+        L.oracle_dense.argtypes = [ci, ci, P, i64, P, i64, P, P, d, P]
+        L.oracle_rdm.argtypes = [ci, ci, P, i64, P, i64, P, P, P]
+        L.oracle_h_elem.argtypes = [ci, ci, P, i64, P, i64, P, P, d, i64, i64, i64, i64]
         L.oracle_h_elem.restype = d
         L.oracle_num_threads.restype = ctypes.c_int
-        L.oracle_csr_count.argtypes = [ctypes.c_int, P, i64, P, i64, P]
-        L.oracle_csr_fill.argtypes = [ctypes.c_int, P, i64, P, i64, P, P, d, P, P, P]
+        L.oracle_csr_count.argtypes = [ci, ci, P, i64, P, i64, P]
+        L.oracle_csr_fill.argtypes = [ci, ci, P, i64, P, i64, P, P, d, P, P, P]
         L.oracle_csr_matvec.argtypes = [i64, P, P, P, P, P]
         _lib = L
     return _lib
@@ -52,19 +53,31 @@ def _p(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
+def _ascending(words: np.ndarray) -> bool:
+    """Strings (n x nw words, word 0 lowest) strictly ascending as integers."""
+    vals = [sum(int(w) << (64 * q) for q, w in enumerate(row)) for row in words]
+    return all(b > a for a, b in zip(vals, vals[1:]))
+
+
 class Space:
-    """Integrals plus ascending string sets, held as contiguous numpy arrays."""
+    """Integrals plus ascending string sets, held as contiguous numpy arrays.
+
+    A string is one uint64 (norb <= 64; arrays of shape (n,)) or nw words
+    (arrays of shape (n, nw), word q holding orbitals 64 q .. 64 q + 63)."""
 
     def __init__(self, norb, astr, bstr, h, eri, ecore=0.0):
         self.norb = int(norb)
-        self.astr = np.ascontiguousarray(astr, dtype=np.uint64)
-        self.bstr = np.ascontiguousarray(bstr, dtype=np.uint64)
+        a = np.asarray(astr, dtype=np.uint64)
+        b = np.asarray(bstr, dtype=np.uint64)
+        self.nw = 1 if a.ndim == 1 else int(a.shape[1])
+        self.astr = np.ascontiguousarray(a.reshape(len(a), self.nw))
+        self.bstr = np.ascontiguousarray(b.reshape(len(b), self.nw))
         self.h = np.ascontiguousarray(h, dtype=np.float64)
         self.eri = np.ascontiguousarray(eri, dtype=np.float64)
         self.ecore = float(ecore)
-        if len(self.astr) > 1 and not np.all(self.astr[1:] > self.astr[:-1]):
+        if not _ascending(self.astr):
             raise ValueError("alpha strings must be strictly ascending")
-        if len(self.bstr) > 1 and not np.all(self.bstr[1:] > self.bstr[:-1]):
+        if not _ascending(self.bstr):
             raise ValueError("beta strings must be strictly ascending")
 
     @classmethod
@@ -84,7 +97,7 @@ class Space:
         return self.na * self.nb
 
     def _args(self):
-        return (self.norb, _p(self.astr), self.na, _p(self.bstr), self.nb,
+        return (self.norb, self.nw, _p(self.astr), self.na, _p(self.bstr), self.nb,
                 _p(self.h), _p(self.eri), ctypes.c_double(self.ecore))
 
     def sigma(self, c: np.ndarray, mask: int = ALL) -> np.ndarray:
@@ -132,7 +145,7 @@ class Space:
         n = self.norb
         g1 = np.zeros((n, n))
         g2 = np.zeros((n, n, n, n))
-        rc = lib().oracle_rdm(self.norb, _p(self.astr), self.na, _p(self.bstr), self.nb,
+        rc = lib().oracle_rdm(self.norb, self.nw, _p(self.astr), self.na, _p(self.bstr), self.nb,
                               _p(c), _p(g1), _p(g2))
         if rc:
             raise RuntimeError("oracle_rdm failed")
@@ -151,14 +164,14 @@ class MemoisedH:
         dim = space.dim
         self.dim = dim
         self.rowptr = np.zeros(dim + 1, dtype=np.int64)
-        rc = lib().oracle_csr_count(space.norb, _p(space.astr), space.na, _p(space.bstr), space.nb,
+        rc = lib().oracle_csr_count(space.norb, space.nw, _p(space.astr), space.na, _p(space.bstr), space.nb,
                                     _p(self.rowptr))
         if rc:
             raise RuntimeError("oracle_csr_count failed")
         nnz = int(self.rowptr[-1])
         self.cols = np.empty(nnz, dtype=np.int32)
         self.vals = np.empty(nnz, dtype=np.float64)
-        rc = lib().oracle_csr_fill(space.norb, _p(space.astr), space.na, _p(space.bstr), space.nb,
+        rc = lib().oracle_csr_fill(space.norb, space.nw, _p(space.astr), space.na, _p(space.bstr), space.nb,
                                    _p(space.h), _p(space.eri), ctypes.c_double(space.ecore),
                                    _p(self.rowptr), _p(self.cols), _p(self.vals))
         if rc:

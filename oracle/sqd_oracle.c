@@ -18,7 +18,10 @@
  *
  * A determinant |I> is a_{P1}+ a_{P2}+ ... |0> with P1 < P2 < ..., i.e. all
  * alpha creators (ascending) to the left of all beta creators (ascending);
- * its bit pattern is D = Ialpha | (Ibeta << norb).  A matrix element
+ * its bit pattern D has bit p set for occupied alpha orbital p and bit
+ * norb + q for occupied beta orbital q (2 norb <= 256 bits, four 64-bit
+ * words).  A string of norb <= 128 orbitals is given as nw = 1 or 2 64-bit
+ * words, word w holding orbitals 64 w .. 64 w + 63.  A matrix element
  * <I| op |J> is obtained by applying the ladder operators of op to D_J one at
  * a time, right to left, each contributing (-1)^(number of occupied
  * spin-orbitals below it), and comparing the result with D_I.  Every H_IJ is
@@ -47,7 +50,8 @@
 #include <omp.h>
 #endif
 
-typedef unsigned __int128 u128;
+#define NWD 4   /* 64-bit words of a determinant bit pattern (2 norb <= 256) */
+typedef struct { uint64_t w[NWD]; } u256;
 
 #define OR_DIAG 1u
 #define OR_AA 2u
@@ -56,6 +60,7 @@ typedef unsigned __int128 u128;
 
 typedef struct {
     int norb;
+    int nw;               /* 64-bit words per string */
     int64_t na, nb;
     const uint64_t* astr;
     const uint64_t* bstr;
@@ -67,54 +72,71 @@ typedef struct {
     int64_t* boff; int64_t* bidx;
 } prob_t;
 
-static int popc128(u128 x) {
-    return __builtin_popcountll((uint64_t)x) + __builtin_popcountll((uint64_t)(x >> 64));
+static int bit_get(const u256* d, int k) { return (int)((d->w[k >> 6] >> (k & 63)) & 1u); }
+static void bit_flip(u256* d, int k) { d->w[k >> 6] ^= 1ull << (k & 63); }
+static int bits_equal(const u256* a, const u256* b) {
+    for (int q = 0; q < NWD; ++q)
+        if (a->w[q] != b->w[q]) return 0;
+    return 1;
+}
+
+/* number of set bits below position k */
+static int count_below(const u256* d, int k) {
+    int c = 0;
+    for (int q = 0; q < (k >> 6); ++q) c += __builtin_popcountll(d->w[q]);
+    if (k & 63) c += __builtin_popcountll(d->w[k >> 6] & ((1ull << (k & 63)) - 1));
+    return c;
 }
 
 /* apply a_k: returns 0 if the orbital is empty; updates *d and *sign */
-static int op_annihilate(u128* d, int k, int* sign) {
-    u128 bit = ((u128)1) << k;
-    if (!(*d & bit)) return 0;
-    if (popc128(*d & (bit - 1)) & 1) *sign = -*sign;
-    *d &= ~bit;
+static int op_annihilate(u256* d, int k, int* sign) {
+    if (!bit_get(d, k)) return 0;
+    if (count_below(d, k) & 1) *sign = -*sign;
+    bit_flip(d, k);
     return 1;
 }
 
 /* apply a+_k: returns 0 if the orbital is already occupied */
-static int op_create(u128* d, int k, int* sign) {
-    u128 bit = ((u128)1) << k;
-    if (*d & bit) return 0;
-    if (popc128(*d & (bit - 1)) & 1) *sign = -*sign;
-    *d |= bit;
+static int op_create(u256* d, int k, int* sign) {
+    if (bit_get(d, k)) return 0;
+    if (count_below(d, k) & 1) *sign = -*sign;
+    bit_flip(d, k);
     return 1;
 }
 
 /* <I| a+_P a_Q |J> */
-static int me1(u128 I, u128 J, int P, int Q) {
+static int me1(u256 I, u256 J, int P, int Q) {
     int s = 1;
-    u128 d = J;
+    u256 d = J;
     if (!op_annihilate(&d, Q, &s)) return 0;
     if (!op_create(&d, P, &s)) return 0;
-    return d == I ? s : 0;
+    return bits_equal(&d, &I) ? s : 0;
 }
 
 /* <I| a+_P a+_R a_S a_Q |J> : a_Q acts first, then a_S, a+_R, a+_P */
-static int me2(u128 I, u128 J, int P, int Q, int R, int S) {
+static int me2(u256 I, u256 J, int P, int Q, int R, int S) {
     int s = 1;
-    u128 d = J;
+    u256 d = J;
     if (!op_annihilate(&d, Q, &s)) return 0;
     if (!op_annihilate(&d, S, &s)) return 0;
     if (!op_create(&d, R, &s)) return 0;
     if (!op_create(&d, P, &s)) return 0;
-    return d == I ? s : 0;
+    return bits_equal(&d, &I) ? s : 0;
 }
 
-static int bits_of(u128 x, int* out) {
+/* positions of the set bits of x, ascending; returns their count */
+static int bits_of(u256 x, int* out) {
     int n = 0;
-    uint64_t lo = (uint64_t)x, hi = (uint64_t)(x >> 64);
-    while (lo) { out[n++] = __builtin_ctzll(lo); lo &= lo - 1; }
-    while (hi) { out[n++] = 64 + __builtin_ctzll(hi); hi &= hi - 1; }
+    for (int q = 0; q < NWD; ++q)
+        for (uint64_t v = x.w[q]; v; v &= v - 1) out[n++] = 64 * q + __builtin_ctzll(v);
     return n;
+}
+
+/* Hamming distance of two strings of nw words */
+static int str_dist(const uint64_t* a, const uint64_t* b, int nw) {
+    int d = 0;
+    for (int q = 0; q < nw; ++q) d += __builtin_popcountll(a[q] ^ b[q]);
+    return d;
 }
 
 /* Visit every operator string that maps J to I.  For the one-body part the
@@ -124,14 +146,21 @@ static int bits_of(u128 x, int* out) {
  * plus the same spectators; all orderings are visited. */
 typedef void (*visit_fn)(void* ctx, int P, int Q, int R, int S, int sign);
 
-static void for_each_term(u128 I, u128 J, visit_fn fn, void* ctx) {
-    u128 x = I ^ J;
-    int nd2 = popc128(x);
+static void for_each_term(u256 I, u256 J, visit_fn fn, void* ctx) {
+    u256 x, jn, in, both;
+    int nd2 = 0;
+    for (int q = 0; q < NWD; ++q) {
+        x.w[q] = I.w[q] ^ J.w[q];
+        jn.w[q] = J.w[q] & ~I.w[q];
+        in.w[q] = I.w[q] & ~J.w[q];
+        both.w[q] = I.w[q] & J.w[q];
+        nd2 += __builtin_popcountll(x.w[q]);
+    }
     if (nd2 > 4) return;
-    int hole[2], part[2], com[128];
-    int nh = bits_of(J & ~I, hole);   /* in J, not in I: annihilated */
-    int np = bits_of(I & ~J, part);   /* in I, not in J: created */
-    int nc = bits_of(I & J, com);
+    int hole[2], part[2], com[64 * NWD];
+    int nh = bits_of(jn, hole);   /* in J, not in I: annihilated */
+    int np = bits_of(in, part);   /* in I, not in J: created */
+    int nc = bits_of(both, com);
     if (nh != np) return;
     /* one-body */
     if (nh == 0) {
@@ -196,20 +225,29 @@ static void hvisit(void* vctx, int P, int Q, int R, int S, int sign) {
         c->acc += 0.5 * sign * c->pb->eri[((size_t)(p * n + q) * n + r) * n + s];
 }
 
-static u128 det_bits(const prob_t* pb, int64_t ia, int64_t ib) {
-    return (u128)pb->astr[ia] | ((u128)pb->bstr[ib] << pb->norb);
+/* D: bit p for alpha orbital p, bit norb + q for beta orbital q */
+static u256 det_bits(const prob_t* pb, int64_t ia, int64_t ib) {
+    u256 d;
+    memset(&d, 0, sizeof(d));
+    const uint64_t* a = pb->astr + ia * pb->nw;
+    const uint64_t* b = pb->bstr + ib * pb->nw;
+    for (int p = 0; p < pb->norb; ++p) {
+        if ((a[p >> 6] >> (p & 63)) & 1u) bit_flip(&d, p);
+        if ((b[p >> 6] >> (p & 63)) & 1u) bit_flip(&d, pb->norb + p);
+    }
+    return d;
 }
 
 static double h_elem(const prob_t* pb, int64_t ia, int64_t ib, int64_t ja, int64_t jb) {
     hctx_t c = {pb, 0.0};
-    u128 I = det_bits(pb, ia, ib), J = det_bits(pb, ja, jb);
+    u256 I = det_bits(pb, ia, ib), J = det_bits(pb, ja, jb);
     for_each_term(I, J, hvisit, &c);
-    if (I == J) c.acc += pb->ecore;
+    if (bits_equal(&I, &J)) c.acc += pb->ecore;
     return c.acc;
 }
 
 /* brute-force neighbour lists: strings at Hamming distance 2 or 4 */
-static void build_nbrs(const uint64_t* s, int64_t n, int64_t** off_out, int64_t** idx_out) {
+static void build_nbrs(const uint64_t* s, int64_t n, int nw, int64_t** off_out, int64_t** idx_out) {
     int64_t* off = (int64_t*)malloc(sizeof(int64_t) * (n + 1));
     off[0] = 0;
     int64_t* cnt = (int64_t*)calloc(n, sizeof(int64_t));
@@ -217,7 +255,7 @@ static void build_nbrs(const uint64_t* s, int64_t n, int64_t** off_out, int64_t*
     for (int64_t i = 0; i < n; ++i) {
         int64_t c = 0;
         for (int64_t j = 0; j < n; ++j) {
-            int d = __builtin_popcountll(s[i] ^ s[j]);
+            int d = str_dist(s + i * nw, s + j * nw, nw);
             if (d == 2 || d == 4) ++c;
         }
         cnt[i] = c;
@@ -228,7 +266,7 @@ static void build_nbrs(const uint64_t* s, int64_t n, int64_t** off_out, int64_t*
     for (int64_t i = 0; i < n; ++i) {
         int64_t c = off[i];
         for (int64_t j = 0; j < n; ++j) {
-            int d = __builtin_popcountll(s[i] ^ s[j]);
+            int d = str_dist(s + i * nw, s + j * nw, nw);
             if (d == 2 || d == 4) idx[c++] = j;
         }
     }
@@ -236,13 +274,19 @@ static void build_nbrs(const uint64_t* s, int64_t n, int64_t** off_out, int64_t*
     *off_out = off; *idx_out = idx;
 }
 
-static void prob_init(prob_t* pb, int norb, const uint64_t* astr, int64_t na,
+static void prob_init(prob_t* pb, int norb, int nw, const uint64_t* astr, int64_t na,
                       const uint64_t* bstr, int64_t nb, const double* h, const double* eri,
                       double ecore) {
-    pb->norb = norb; pb->na = na; pb->nb = nb; pb->astr = astr; pb->bstr = bstr;
+    pb->norb = norb; pb->nw = nw; pb->na = na; pb->nb = nb; pb->astr = astr; pb->bstr = bstr;
     pb->h = h; pb->eri = eri; pb->ecore = ecore;
-    build_nbrs(astr, na, &pb->aoff, &pb->aidx);
-    build_nbrs(bstr, nb, &pb->boff, &pb->bidx);
+    build_nbrs(astr, na, nw, &pb->aoff, &pb->aidx);
+    build_nbrs(bstr, nb, nw, &pb->boff, &pb->bidx);
+}
+
+/* the string word count norb needs, or 0 when norb is outside [1, 128] */
+static int words_for(int norb, int nw) {
+    if (norb < 1 || norb > 128 || nw < 1 || nw > 2 || norb > 64 * nw) return 0;
+    return nw;
 }
 
 static void prob_free(prob_t* pb) {
@@ -260,10 +304,10 @@ static void for_each_neighbour(const prob_t* pb, int64_t ia, int64_t ib, pair_fn
         fn(ctx, ia, pb->bidx[k], OR_BB);
     for (int64_t k = pb->aoff[ia]; k < pb->aoff[ia + 1]; ++k) {
         int64_t ja = pb->aidx[k];
-        if (__builtin_popcountll(pb->astr[ia] ^ pb->astr[ja]) != 2) continue;
+        if (str_dist(pb->astr + ia * pb->nw, pb->astr + ja * pb->nw, pb->nw) != 2) continue;
         for (int64_t l = pb->boff[ib]; l < pb->boff[ib + 1]; ++l) {
             int64_t jb = pb->bidx[l];
-            if (__builtin_popcountll(pb->bstr[ib] ^ pb->bstr[jb]) != 2) continue;
+            if (str_dist(pb->bstr + ib * pb->nw, pb->bstr + jb * pb->nw, pb->nw) != 2) continue;
             fn(ctx, ja, jb, OR_AB);
         }
     }
@@ -297,12 +341,12 @@ int oracle_num_threads(void) {
 }
 
 /* sigma = (P H P c) restricted to the pair classes in mask; all rows. */
-int oracle_sigma(int norb, const uint64_t* astr, int64_t na, const uint64_t* bstr, int64_t nb,
+int oracle_sigma(int norb, int nw, const uint64_t* astr, int64_t na, const uint64_t* bstr, int64_t nb,
                  const double* h, const double* eri, double ecore,
                  const double* c, double* sigma, unsigned mask) {
-    if (norb < 1 || norb > 64) return -1;
+    if (!words_for(norb, nw)) return -1;
     prob_t pb;
-    prob_init(&pb, norb, astr, na, bstr, nb, h, eri, ecore);
+    prob_init(&pb, norb, nw, astr, na, bstr, nb, h, eri, ecore);
     int64_t dim = na * nb;
     #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t r = 0; r < dim; ++r) sigma[r] = sigma_row(&pb, r, c, mask);
@@ -311,13 +355,13 @@ int oracle_sigma(int norb, const uint64_t* astr, int64_t na, const uint64_t* bst
 }
 
 /* sigma at selected rows only: out[k] = sigma[rows[k]] */
-int oracle_sigma_rows(int norb, const uint64_t* astr, int64_t na, const uint64_t* bstr, int64_t nb,
+int oracle_sigma_rows(int norb, int nw, const uint64_t* astr, int64_t na, const uint64_t* bstr, int64_t nb,
                       const double* h, const double* eri, double ecore,
                       const double* c, const int64_t* rows, int64_t nrows, double* out,
                       unsigned mask) {
-    if (norb < 1 || norb > 64) return -1;
+    if (!words_for(norb, nw)) return -1;
     prob_t pb;
-    prob_init(&pb, norb, astr, na, bstr, nb, h, eri, ecore);
+    prob_init(&pb, norb, nw, astr, na, bstr, nb, h, eri, ecore);
     #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t k = 0; k < nrows; ++k) out[k] = sigma_row(&pb, rows[k], c, mask);
     prob_free(&pb);
@@ -325,11 +369,11 @@ int oracle_sigma_rows(int norb, const uint64_t* astr, int64_t na, const uint64_t
 }
 
 /* diagonal H_II for all rows */
-int oracle_diag(int norb, const uint64_t* astr, int64_t na, const uint64_t* bstr, int64_t nb,
+int oracle_diag(int norb, int nw, const uint64_t* astr, int64_t na, const uint64_t* bstr, int64_t nb,
                 const double* h, const double* eri, double ecore, double* diag) {
-    if (norb < 1 || norb > 64) return -1;
+    if (!words_for(norb, nw)) return -1;
     prob_t pb;
-    pb.norb = norb; pb.na = na; pb.nb = nb; pb.astr = astr; pb.bstr = bstr;
+    pb.norb = norb; pb.nw = nw; pb.na = na; pb.nb = nb; pb.astr = astr; pb.bstr = bstr;
     pb.h = h; pb.eri = eri; pb.ecore = ecore;
     int64_t dim = na * nb;
     #pragma omp parallel for schedule(static)
@@ -347,11 +391,11 @@ static void dense_visit(void* vctx, int64_t ja, int64_t jb, unsigned cls) {
 }
 
 /* dense H_S (dim x dim, row-major); the caller zero-fills H */
-int oracle_dense(int norb, const uint64_t* astr, int64_t na, const uint64_t* bstr, int64_t nb,
+int oracle_dense(int norb, int nw, const uint64_t* astr, int64_t na, const uint64_t* bstr, int64_t nb,
                  const double* h, const double* eri, double ecore, double* H) {
-    if (norb < 1 || norb > 64) return -1;
+    if (!words_for(norb, nw)) return -1;
     prob_t pb;
-    prob_init(&pb, norb, astr, na, bstr, nb, h, eri, ecore);
+    prob_init(&pb, norb, nw, astr, na, bstr, nb, h, eri, ecore);
     int64_t dim = na * nb;
     #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t r = 0; r < dim; ++r) {
@@ -390,17 +434,17 @@ static void rdm_pair_visit(void* vctx, int64_t ja, int64_t jb, unsigned cls) {
     double ci = d->c[d->ia * pb->nb + d->ib], cj = d->c[ja * pb->nb + jb];
     d->r->w = ci * cj;
     if (d->r->w == 0.0) return;
-    u128 I = det_bits(pb, d->ia, d->ib), J = det_bits(pb, ja, jb);
+    u256 I = det_bits(pb, d->ia, d->ib), J = det_bits(pb, ja, jb);
     for_each_term(I, J, rdm_visit, d->r);
 }
 
 /* 1-RDM (norb^2) and 2-RDM (norb^4), spin-summed, for a normalised c:
  * rdm1[p,q] = sum_s <a+_ps a_qs>, rdm2[p,q,r,s] = sum_st <a+_ps a+_rt a_st a_qs>. */
-int oracle_rdm(int norb, const uint64_t* astr, int64_t na, const uint64_t* bstr, int64_t nb,
+int oracle_rdm(int norb, int nw, const uint64_t* astr, int64_t na, const uint64_t* bstr, int64_t nb,
                const double* c, double* rdm1, double* rdm2) {
-    if (norb < 1 || norb > 64) return -1;
+    if (!words_for(norb, nw)) return -1;
     prob_t pb;
-    prob_init(&pb, norb, astr, na, bstr, nb, NULL, NULL, 0.0);
+    prob_init(&pb, norb, nw, astr, na, bstr, nb, NULL, NULL, 0.0);
     int64_t dim = na * nb;
     size_t n2 = (size_t)norb * norb, n4 = n2 * n2;
     memset(rdm1, 0, sizeof(double) * n2);
@@ -427,11 +471,11 @@ int oracle_rdm(int norb, const uint64_t* astr, int64_t na, const uint64_t* bstr,
 }
 
 /* single matrix element, for spot checks */
-double oracle_h_elem(int norb, const uint64_t* astr, int64_t na, const uint64_t* bstr, int64_t nb,
+double oracle_h_elem(int norb, int nw, const uint64_t* astr, int64_t na, const uint64_t* bstr, int64_t nb,
                      const double* h, const double* eri, double ecore,
                      int64_t ia, int64_t ib, int64_t ja, int64_t jb) {
     prob_t pb;
-    pb.norb = norb; pb.na = na; pb.nb = nb; pb.astr = astr; pb.bstr = bstr;
+    pb.norb = norb; pb.nw = nw; pb.na = na; pb.nb = nb; pb.astr = astr; pb.bstr = bstr;
     pb.h = h; pb.eri = eri; pb.ecore = ecore;
     return h_elem(&pb, ia, ib, ja, jb);
 }
@@ -447,11 +491,11 @@ static void count_visit(void* vctx, int64_t ja, int64_t jb, unsigned cls) {
     ((cctx_t*)vctx)->n += 1;
 }
 
-int oracle_csr_count(int norb, const uint64_t* astr, int64_t na, const uint64_t* bstr, int64_t nb,
+int oracle_csr_count(int norb, int nw, const uint64_t* astr, int64_t na, const uint64_t* bstr, int64_t nb,
                      int64_t* rowptr) {
-    if (norb < 1 || norb > 64) return -1;
+    if (!words_for(norb, nw)) return -1;
     prob_t pb;
-    prob_init(&pb, norb, astr, na, bstr, nb, NULL, NULL, 0.0);
+    prob_init(&pb, norb, nw, astr, na, bstr, nb, NULL, NULL, 0.0);
     int64_t dim = na * nb;
     #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t r = 0; r < dim; ++r) {
@@ -474,13 +518,13 @@ static void fill_visit(void* vctx, int64_t ja, int64_t jb, unsigned cls) {
     f->pos += 1;
 }
 
-int oracle_csr_fill(int norb, const uint64_t* astr, int64_t na, const uint64_t* bstr, int64_t nb,
+int oracle_csr_fill(int norb, int nw, const uint64_t* astr, int64_t na, const uint64_t* bstr, int64_t nb,
                     const double* h, const double* eri, double ecore,
                     const int64_t* rowptr, int32_t* cols, double* vals) {
-    if (norb < 1 || norb > 64) return -1;
+    if (!words_for(norb, nw)) return -1;
     if (na * nb >= 2147483647LL) return -2;
     prob_t pb;
-    prob_init(&pb, norb, astr, na, bstr, nb, h, eri, ecore);
+    prob_init(&pb, norb, nw, astr, na, bstr, nb, h, eri, ecore);
     int64_t dim = na * nb;
     #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t r = 0; r < dim; ++r) {

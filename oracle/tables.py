@@ -11,10 +11,14 @@ with the sign s_t = <t| op |s> obtained by applying the ladder operators one
 at a time (each contributes (-1)^(occupied orbitals below it)).
 
 Canonical order: rows by source index; inside a row, entries by target index
-ascending.  Entry packing (uint64):
+ascending.  Entry packing (uint64; orbitals in 7-bit fields, norb <= 128):
 
-  singles: bits 0-31 target | 32-37 i | 38-43 a | bit 63 sign (1 = negative)
-  doubles: bits 0-31 target | 32-37 i | 38-43 j | 44-49 a | 50-55 b | bit 63 sign
+  singles: bits 0-31 target | 32-38 i | 39-45 a | bit 63 sign (1 = negative)
+  doubles: bits 0-31 target | 32-38 i | 39-45 j | 46-52 a | 53-59 b | bit 63 sign
+
+Strings are Python integers (bit p = orbital p); a numpy array of shape
+(n, nw) holds string k as words [k, 0], [k, 1], ... (word q = orbitals
+64 q .. 64 q + 63).
 """
 from __future__ import annotations
 
@@ -47,23 +51,31 @@ def _apply(string: int, ops) -> Tuple[int, int]:
 
 
 def pack_single(target, i, a, sign):
-    v = int(target) | (int(i) << 32) | (int(a) << 38)
+    v = int(target) | (int(i) << 32) | (int(a) << 39)
     if sign < 0:
         v |= 1 << 63
     return v
 
 
 def pack_double(target, i, j, a, b, sign):
-    v = int(target) | (int(i) << 32) | (int(j) << 38) | (int(a) << 44) | (int(b) << 50)
+    v = int(target) | (int(i) << 32) | (int(j) << 39) | (int(a) << 46) | (int(b) << 53)
     if sign < 0:
         v |= 1 << 63
     return v
 
 
+def as_ints(strings) -> list:
+    """Strings as Python integers, from shape (n,) or (n, nw) uint64 arrays."""
+    a = np.asarray(strings, dtype=np.uint64)
+    if a.ndim == 1:
+        return [int(x) for x in a]
+    return [sum(int(w) << (64 * q) for q, w in enumerate(row)) for row in a]
+
+
 def build_tables(strings: np.ndarray, norb: int):
     """Return (s_off, s_ent, d_off, d_ent): CSR offsets (int64) and packed
     uint64 entries for singles and doubles, canonical order."""
-    strs = [int(x) for x in strings]
+    strs = as_ints(strings)
     index = {s: k for k, s in enumerate(strs)}
     s_rows, d_rows = [], []
     for s in strs:
@@ -100,5 +112,5 @@ def unpack(entry: int, kind: str):
     target = e & 0xFFFFFFFF
     sign = -1 if (e >> 63) & 1 else 1
     if kind == "single":
-        return target, (e >> 32) & 63, (e >> 38) & 63, sign
-    return target, (e >> 32) & 63, (e >> 38) & 63, (e >> 44) & 63, (e >> 50) & 63, sign
+        return target, (e >> 32) & 127, (e >> 39) & 127, sign
+    return target, (e >> 32) & 127, (e >> 39) & 127, (e >> 46) & 127, (e >> 53) & 127, sign

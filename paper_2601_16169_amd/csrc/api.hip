@@ -260,7 +260,7 @@ int sqd_get_tuning(const sqd_ctx* ctx, int key, int* value) {
 
 int sqd_set_hamiltonian(sqd_ctx* ctx, int norb, const double* h, const double* eri, double ecore) {
     if (!ctx) return SQD_E_INVALID_ARG;
-    if (norb < 1 || norb > 64) return sqd_fail(ctx, SQD_E_NORB, "norb must be in [1, 64]");
+    if (norb < 1 || norb > SQD_MAXORB) return sqd_fail(ctx, SQD_E_NORB, "norb must be in [1, 128]");
     if (!h || !eri) return sqd_fail(ctx, SQD_E_INVALID_ARG, "null integral pointer");
     if (!std::isfinite(ecore)) return sqd_fail(ctx, SQD_E_INVALID_ARG, "ecore not finite");
     const int64_t n2 = (int64_t)norb * norb, n4 = n2 * n2;
@@ -318,36 +318,56 @@ int sqd_set_hamiltonian(sqd_ctx* ctx, int norb, const double* h, const double* e
     return SQD_OK;
 }
 
-static int validate_strings(sqd_ctx* ctx, const uint64_t* s, int64_t n, int nel, int norb, const char* which) {
-    const uint64_t mask = (norb == 64) ? ~0ull : ((1ull << norb) - 1);
+// strings of nw words (word q: orbitals 64q .. 64q+63): no bit >= norb, nel
+// bits set, strictly ascending as integers (word nw-1 most significant)
+static int validate_strings(sqd_ctx* ctx, const uint64_t* s, int nw, int64_t n, int nel, int norb,
+                            const char* which) {
     for (int64_t k = 0; k < n; ++k) {
-        if (s[k] & ~mask) return sqd_fail(ctx, SQD_E_NORB, std::string(which) + " string has a bit >= norb at " + std::to_string(k));
-        if (__builtin_popcountll(s[k]) != nel)
+        const uint64_t* x = s + k * nw;
+        int pop = 0;
+        for (int q = 0; q < nw; ++q) {
+            const int lo = 64 * q;
+            const uint64_t mask = (norb >= lo + 64) ? ~0ull : (norb <= lo ? 0ull : ((1ull << (norb - lo)) - 1));
+            if (x[q] & ~mask)
+                return sqd_fail(ctx, SQD_E_NORB, std::string(which) + " string has a bit >= norb at " + std::to_string(k));
+            pop += __builtin_popcountll(x[q]);
+        }
+        if (pop != nel)
             return sqd_fail(ctx, SQD_E_POPCOUNT, std::string(which) + " string has the wrong electron count at " + std::to_string(k));
-        if (k > 0 && s[k] <= s[k - 1])
-            return sqd_fail(ctx, SQD_E_UNSORTED, std::string(which) + " strings not strictly ascending at " + std::to_string(k));
+        if (k > 0) {
+            const uint64_t* y = x - nw;
+            int cmp = 0;
+            for (int q = nw - 1; q >= 0 && cmp == 0; --q)
+                if (x[q] != y[q]) cmp = x[q] > y[q] ? 1 : -1;
+            if (cmp <= 0)
+                return sqd_fail(ctx, SQD_E_UNSORTED, std::string(which) + " strings not strictly ascending at " + std::to_string(k));
+        }
     }
     return SQD_OK;
 }
 
-int sqd_build_space(sqd_ctx* ctx, int nalpha, int nbeta, const uint64_t* astr, int64_t na, const uint64_t* bstr,
-                    int64_t nb, sqd_space** out) {
+static int build_space_impl(sqd_ctx* ctx, int nalpha, int nbeta, int nw, const uint64_t* astr, int64_t na,
+                            const uint64_t* bstr, int64_t nb, sqd_space** out) {
     if (!ctx || !out) return SQD_E_INVALID_ARG;
     *out = nullptr;
     if (ctx->norb == 0) return sqd_fail(ctx, SQD_E_STATE, "call sqd_set_hamiltonian before sqd_build_space");
     const int norb = ctx->norb;
+    if (nw < 1 || nw > 2) return sqd_fail(ctx, SQD_E_INVALID_ARG, "strings take 1 or 2 words");
+    if (norb > 64 * nw)
+        return sqd_fail(ctx, SQD_E_NORB, "norb > 64 needs two-word strings (sqd_build_space_words)");
     if (!astr || !bstr || na < 1 || nb < 1) return sqd_fail(ctx, SQD_E_INVALID_ARG, "empty or null string list");
-    if (na > SQD_MAXN || nb > SQD_MAXN) return sqd_fail(ctx, SQD_E_LIMIT, "more than 524287 strings per spin");
+    if (na > SQD_MAXN || nb > SQD_MAXN) return sqd_fail(ctx, SQD_E_LIMIT, "more than 131071 strings per spin");
     if ((double)na * (double)nb >= 1099511627776.0) return sqd_fail(ctx, SQD_E_LIMIT, "dimension >= 2^40");
     if (nalpha < 0 || nalpha > norb || nbeta < 0 || nbeta > norb)
         return sqd_fail(ctx, SQD_E_POPCOUNT, "electron count outside [0, norb]");
     int rc;
-    if ((rc = validate_strings(ctx, astr, na, nalpha, norb, "alpha"))) return rc;
-    if ((rc = validate_strings(ctx, bstr, nb, nbeta, norb, "beta"))) return rc;
+    if ((rc = validate_strings(ctx, astr, nw, na, nalpha, norb, "alpha"))) return rc;
+    if ((rc = validate_strings(ctx, bstr, nw, nb, nbeta, norb, "beta"))) return rc;
     SQD_HIP(ctx, hipSetDevice(ctx->device));
     sqd_space* sp = new sqd_space();
     sp->ctx = ctx;
     sp->norb = norb;
+    sp->nw = nw;
     sp->nalpha = nalpha;
     sp->nbeta = nbeta;
     sp->dim = na * nb;
@@ -355,7 +375,7 @@ int sqd_build_space(sqd_ctx* ctx, int nalpha, int nbeta, const uint64_t* astr, i
         sqd_space_free(sp);
         return rc;
     }
-    const bool same = (na == nb) && (nalpha == nbeta) && std::memcmp(astr, bstr, sizeof(uint64_t) * na) == 0;
+    const bool same = (na == nb) && (nalpha == nbeta) && std::memcmp(astr, bstr, sizeof(uint64_t) * na * nw) == 0;
     if (same) {
         sp->sp[1] = sp->sp[0];
         sp->sp[1].alias = true;
@@ -370,6 +390,16 @@ int sqd_build_space(sqd_ctx* ctx, int nalpha, int nbeta, const uint64_t* astr, i
     }
     *out = sp;
     return SQD_OK;
+}
+
+int sqd_build_space(sqd_ctx* ctx, int nalpha, int nbeta, const uint64_t* astr, int64_t na, const uint64_t* bstr,
+                    int64_t nb, sqd_space** out) {
+    return build_space_impl(ctx, nalpha, nbeta, 1, astr, na, bstr, nb, out);
+}
+
+int sqd_build_space_words(sqd_ctx* ctx, int nalpha, int nbeta, int nwords, const uint64_t* astr, int64_t na,
+                          const uint64_t* bstr, int64_t nb, sqd_space** out) {
+    return build_space_impl(ctx, nalpha, nbeta, nwords, astr, na, bstr, nb, out);
 }
 
 void sqd_space_free(sqd_space* sp) {
@@ -513,6 +543,23 @@ int sqd_davidson_roots(sqd_ctx* ctx, const sqd_space* spc, const sqd_davidson_op
         return sqd_fail(ctx, SQD_E_STATE, "no current stored H on this space (call sqd_store_hamiltonian)");
     SQD_HIP(ctx, hipSetDevice(ctx->device));
     return sqd_davidson_impl(ctx, sp, o, energies, vecs, reps, nroots);
+}
+
+int sqd_davidson_block(sqd_ctx* ctx, const sqd_space* spc, const sqd_davidson_opts* o, int nroots,
+                       double* energies, double* vecs, sqd_report* reps) {
+    if (!ctx || !spc || !energies || !vecs) return SQD_E_INVALID_ARG;
+    if (nroots < 1 || nroots > SQD_MAXLOCK) return sqd_fail(ctx, SQD_E_INVALID_ARG, "nroots must be 1..SQD_MAXLOCK");
+    int rc = check_opts(ctx, o);
+    if (rc) return rc;
+    if (o->m_max < 2 * nroots) return sqd_fail(ctx, SQD_E_INVALID_ARG, "block Davidson needs m_max >= 2 nroots");
+    sqd_space* sp = const_cast<sqd_space*>(spc);
+    if (sp->ctx != ctx) return sqd_fail(ctx, SQD_E_INVALID_ARG, "space belongs to another context");
+    if (ctx->norb != sp->norb) return sqd_fail(ctx, SQD_E_STATE, "integrals changed norb since the space was built");
+    if ((int64_t)nroots > sp->dim) return sqd_fail(ctx, SQD_E_INVALID_ARG, "more roots than determinants");
+    if (o->product == SQD_PRODUCT_STORED && (!sp->h_val || sp->h_version != ctx->ham_version))
+        return sqd_fail(ctx, SQD_E_STATE, "no current stored H on this space (call sqd_store_hamiltonian)");
+    SQD_HIP(ctx, hipSetDevice(ctx->device));
+    return sqd_davidson_block_impl(ctx, sp, o, nroots, energies, vecs, reps);
 }
 
 int sqd_davidson_batched(sqd_ctx* ctx, int nspace, const sqd_space* const* spaces, const sqd_davidson_opts* o,

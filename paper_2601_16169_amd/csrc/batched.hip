@@ -670,13 +670,13 @@ int sqd_davidson_batched_impl(sqd_ctx* ctx, int nspace, sqd_space* const* spaces
         d.st = p.states + b;
         // same-spin: BB on C (rows alpha, columns beta, diagonal fused), AA on C^T
         d.aa64 = ss_args<double>{d.Ct, d.Yt, B.n, A.n, A.perm_ss, A.nslices, A.sl_s_off, A.sl_d_off, A.sell_s_pk,
-                                 A.sell_s_v64, A.sell_d_nbr, A.sell_d_v64, B.str, nullptr, 0};
+                                 A.sell_s_v64, A.sell_d_nbr, A.sell_d_v64, B.str, B.nw, nullptr, 0};
         d.bb64 = ss_args<double>{d.cin, d.sout, A.n, B.n, B.perm_ss, B.nslices, B.sl_s_off, B.sl_d_off, B.sell_s_pk,
-                                 B.sell_s_v64, B.sell_d_nbr, B.sell_d_v64, A.str, sp->diag, 1};
+                                 B.sell_s_v64, B.sell_d_nbr, B.sell_d_v64, A.str, A.nw, sp->diag, 1};
         d.aa32 = ss_args<float>{d.Ct32, d.Yt32, B.n, A.n, A.perm_ss, A.nslices, A.sl_s_off, A.sl_d_off, A.sell_s_pk,
-                                A.sell_s_v32, A.sell_d_nbr, A.sell_d_v32, B.str, nullptr, 0};
+                                A.sell_s_v32, A.sell_d_nbr, A.sell_d_v32, B.str, B.nw, nullptr, 0};
         d.bb32 = ss_args<float>{d.c32, d.S32, A.n, B.n, B.perm_ss, B.nslices, B.sl_s_off, B.sl_d_off, B.sell_s_pk,
-                                B.sell_s_v32, B.sell_d_nbr, B.sell_d_v32, A.str, nullptr, 1};
+                                B.sell_s_v32, B.sell_d_nbr, B.sell_d_v32, A.str, A.nw, nullptr, 1};
         d.ab64 = abg_args<double>{d.cin, d.Y64, B.n, ldy, sp->ab_grp, sp->ab_chunk_pair, A.s_pk, B.perm_ab,
                                   B.nslices, B.sl_ab_off, B.sell_ab_pk};
         d.ab32 = abg_args<float>{d.c32, d.Y32, B.n, ldy, sp->ab_grp, sp->ab_chunk_pair, A.s_pk, B.perm_ab,

@@ -91,7 +91,7 @@ k_gemm_nt(const double* __restrict__ A, const double* __restrict__ B, double* __
 //               Gamma[i][a][j][b] += s w, Gamma[j][b][i][a] += s w,
 //               Gamma[j][a][i][b] -= s w, Gamma[i][b][j][a] -= s w
 __global__ void __launch_bounds__(256)
-k_rdm_same(const uint64_t* __restrict__ str, int64_t n, const int* __restrict__ s_off,
+k_rdm_same(const uint64_t* __restrict__ str, int nw, int64_t n, const int* __restrict__ s_off,
            const uint64_t* __restrict__ s_ent, const int* __restrict__ d_off, const uint64_t* __restrict__ d_ent,
            const double* __restrict__ P, int norb, double* __restrict__ rdm1, double* __restrict__ rdm2) {
     const int64_t I = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -99,41 +99,40 @@ k_rdm_same(const uint64_t* __restrict__ str, int64_t n, const int* __restrict__ 
     if (I >= n) return;
     const int64_t n2 = (int64_t)norb * norb;
     auto G = [&](int p, int q, int r, int s) -> double* { return rdm2 + ((int64_t)p * norb + q) * n2 + r * norb + s; };
-    const uint64_t sI = str[I];
+    const uint64_t* sI = str + I * nw;
     const double wd = P[I * n + I];
     // diagonal
-    if (lane < norb && ((sI >> lane) & 1ull)) {
-        const int k = lane;
+    for (int k = lane; k < norb; k += 64) {
+        if (!str_bit(sI, k)) continue;
         atomicAdd(&rdm1[k * norb + k], wd);
         if (rdm2)
-            for (uint64_t x = sI; x; x &= x - 1) {
-                const int l = __ffsll((unsigned long long)x) - 1;
-                if (l == k) continue;
+            str_for_each(sI, nw, [&](int l) {
+                if (l == k) return;
                 atomicAdd(G(k, k, l, l), wd);
                 atomicAdd(G(l, k, k, l), -wd);
-            }
+            });
     }
     for (int e = s_off[I] + lane; e < s_off[I + 1]; e += 64) {
         const uint64_t x = s_ent[e];
         const int64_t J = (int64_t)(x & 0xFFFFFFFFull);
-        const int i = (int)((x >> 32) & 63), a = (int)((x >> 38) & 63);
+        const int i = SQD_ENT_ORB(x, 0), a = SQD_ENT_ORB(x, 1);
         const double sw = ((x >> 63) ? -1.0 : 1.0) * P[I * n + J];
         atomicAdd(&rdm1[i * norb + a], sw);
         if (rdm2)
-            for (uint64_t y = sI & ~(1ull << i); y; y &= y - 1) {
-                const int k = __ffsll((unsigned long long)y) - 1;
+            str_for_each(sI, nw, [&](int k) {
+                if (k == i) return;
                 atomicAdd(G(i, a, k, k), sw);
                 atomicAdd(G(k, k, i, a), sw);
                 atomicAdd(G(k, a, i, k), -sw);
                 atomicAdd(G(i, k, k, a), -sw);
-            }
+            });
     }
     if (!rdm2) return;
     for (int e = d_off[I] + lane; e < d_off[I + 1]; e += 64) {
         const uint64_t x = d_ent[e];
         const int64_t J = (int64_t)(x & 0xFFFFFFFFull);
-        const int i = (int)((x >> 32) & 63), j = (int)((x >> 38) & 63);
-        const int a = (int)((x >> 44) & 63), b = (int)((x >> 50) & 63);
+        const int i = SQD_ENT_ORB(x, 0), j = SQD_ENT_ORB(x, 1);
+        const int a = SQD_ENT_ORB(x, 2), b = SQD_ENT_ORB(x, 3);
         const double sw = ((x >> 63) ? -1.0 : 1.0) * P[I * n + J];
         atomicAdd(G(i, a, j, b), sw);
         atomicAdd(G(j, b, i, a), sw);
@@ -150,7 +149,7 @@ constexpr int kMaxTiles = 16;  // output tiles per wave: (32/16) x (512/16) / 4 
 // One workgroup per alpha string Ia.  U = alpha factor entries of Ia: its
 // singles (pair a*norb+i, source row Ja, sign) then its diagonal pairs pp.
 __global__ void __launch_bounds__(256)
-k_rdm_ab(const double* __restrict__ C, int64_t na, int64_t nb, const uint64_t* __restrict__ astr,
+k_rdm_ab(const double* __restrict__ C, int64_t na, int64_t nb, const uint64_t* __restrict__ astr, int nw,
          const int* __restrict__ a_off, const uint32_t* __restrict__ a_pk, const uint64_t* __restrict__ bstr,
          const int* __restrict__ b_off, const uint32_t* __restrict__ b_pk, int norb, double* __restrict__ rdm2) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -162,9 +161,10 @@ k_rdm_ab(const double* __restrict__ C, int64_t na, int64_t nb, const uint64_t* _
     int* upq = reinterpret_cast<int*>(As + 32 * (kKC + 1));  // [nu_total]
     const int64_t ia = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const uint64_t sa = astr[ia];
+    const uint64_t* sa = astr + ia * nw;
     const int s0 = a_off[ia], ns = a_off[ia + 1] - s0;
-    const int ndiag = __popcll(sa);
+    int ndiag = 0;
+    for (int q = 0; q < nw; ++q) ndiag += __popcll(sa[q]);
     const int nu = ns + ndiag;
     // pair index of each U entry
     for (int u = tid; u < nu; u += 256) {
@@ -172,9 +172,11 @@ k_rdm_ab(const double* __restrict__ C, int64_t na, int64_t nb, const uint64_t* _
         if (u < ns) {
             pq = (int)((a_pk[s0 + u] >> SQD_PAIR_SHIFT) & SQD_PAIR_MASK);
         } else {
-            uint64_t x = sa;
-            for (int t = 0; t < u - ns; ++t) x &= x - 1;
-            const int p = __ffsll((unsigned long long)x) - 1;
+            // the (u - ns)-th occupied orbital p of Ia
+            int skip = u - ns, p = -1;
+            str_for_each(sa, nw, [&](int k) {
+                if (p < 0 && skip-- == 0) p = k;
+            });
             pq = p * norb + p;
         }
         upq[u] = pq;
@@ -221,8 +223,9 @@ k_rdm_ab(const double* __restrict__ C, int64_t na, int64_t nb, const uint64_t* _
                         if (x >> 31) v = -v;
                         Bs[k * nc_max + (rs - n0)] = v;
                     }
-                    if (j < norb && ((bstr[ib] >> j) & 1ull)) {
-                        const int rs = j * norb + j;
+                    for (int jj = j; jj < norb; jj += 64) {
+                        if (!str_bit(bstr + ib * nw, jj)) continue;
+                        const int rs = jj * norb + jj;
                         if (rs >= n0 && rs < n0 + nc) Bs[k * nc_max + (rs - n0)] = crow[ib];
                     }
                 }
@@ -252,8 +255,9 @@ k_rdm_ab(const double* __restrict__ C, int64_t na, int64_t nb, const uint64_t* _
                         const int rs = (pair % norb) * norb + pair / norb;
                         if (rs >= n0 && rs < n0 + nc) Bs[k * nc_max + (rs - n0)] = 0.0;
                     }
-                    if (j < norb && ((bstr[ib] >> j) & 1ull)) {
-                        const int rs = j * norb + j;
+                    for (int jj = j; jj < norb; jj += 64) {
+                        if (!str_bit(bstr + ib * nw, jj)) continue;
+                        const int rs = jj * norb + jj;
                         if (rs >= n0 && rs < n0 + nc) Bs[k * nc_max + (rs - n0)] = 0.0;
                     }
                 }
@@ -328,10 +332,10 @@ int sqd_rdm_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* rdm1, dou
     hipLaunchKernelGGL(k_gemm_nt, dim3(nblk(na, 64), nblk(na, 64)), dim3(256), 0, s, c, c, Pa, na, na, nb);
     hipLaunchKernelGGL(k_transpose_d, dim3(nblk(nb, 64), nblk(na, 64)), dim3(256), 0, s, c, Ct, na, nb);
     hipLaunchKernelGGL(k_gemm_nt, dim3(nblk(nb, 64), nblk(nb, 64)), dim3(256), 0, s, Ct, Ct, Pb, nb, nb, na);
-    hipLaunchKernelGGL(k_rdm_same, dim3(nblk(na, 4)), dim3(256), 0, s, A.str, na, A.s_off, A.s_ent, A.d_off, A.d_ent,
-                       Pa, norb, rdm1, rdm2);
-    hipLaunchKernelGGL(k_rdm_same, dim3(nblk(nb, 4)), dim3(256), 0, s, B.str, nb, B.s_off, B.s_ent, B.d_off, B.d_ent,
-                       Pb, norb, rdm1, rdm2);
+    hipLaunchKernelGGL(k_rdm_same, dim3(nblk(na, 4)), dim3(256), 0, s, A.str, sp->nw, na, A.s_off, A.s_ent, A.d_off,
+                       A.d_ent, Pa, norb, rdm1, rdm2);
+    hipLaunchKernelGGL(k_rdm_same, dim3(nblk(nb, 4)), dim3(256), 0, s, B.str, sp->nw, nb, B.s_off, B.s_ent, B.d_off,
+                       B.d_ent, Pb, norb, rdm1, rdm2);
     if (rdm2) {
         const int npad = (int)((n2 + 15) & ~15);
         const int nc_max = npad < kMaxNC ? npad : kMaxNC;
@@ -341,8 +345,8 @@ int sqd_rdm_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* rdm1, dou
         if (lds > (size_t)ctx->max_lds) return sqd_fail(ctx, SQD_E_LIMIT, "RDM alpha-beta tile does not fit in LDS");
         hipFuncSetAttribute(reinterpret_cast<const void*>(k_rdm_ab), hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
-        hipLaunchKernelGGL(k_rdm_ab, dim3((unsigned)na), dim3(256), lds, s, c, na, nb, A.str, A.s_off, A.s_pk, B.str,
-                           B.s_off, B.s_pk, norb, rdm2);
+        hipLaunchKernelGGL(k_rdm_ab, dim3((unsigned)na), dim3(256), lds, s, c, na, nb, A.str, sp->nw, A.s_off, A.s_pk,
+                           B.str, B.s_off, B.s_pk, norb, rdm2);
     }
     SQD_HIP(ctx, hipGetLastError());
     return SQD_OK;

@@ -31,27 +31,27 @@ template <> struct vec2<float> { using type = float2; };
 
 // ---------------------------------------------------------------- diagonal
 // ua[ia*norb + q] = sum_{p in Ia} (pp|qq)
-__global__ void k_ua(const uint64_t* __restrict__ astr, int64_t na, int norb, const double* __restrict__ jdiag,
-                     double* __restrict__ ua) {
+__global__ void k_ua(const uint64_t* __restrict__ astr, int nw, int64_t na, int norb,
+                     const double* __restrict__ jdiag, double* __restrict__ ua) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= na * norb) return;
     const int64_t ia = k / norb;
     const int q = (int)(k % norb);
     double acc = 0.0;
-    for (uint64_t x = astr[ia]; x; x &= x - 1) acc += jdiag[(__ffsll((unsigned long long)x) - 1) * norb + q];
+    str_for_each(astr + ia * nw, nw, [&](int p) { acc += jdiag[p * norb + q]; });
     ua[k] = acc;
 }
 
 // H_II = ecore + E_a(Ia) + E_b(Ib) + sum_{p in Ia, q in Ib} (pp|qq)
 __global__ void k_diag(const double* __restrict__ ea, const double* __restrict__ eb, const double* __restrict__ ua,
-                       const uint64_t* __restrict__ bstr, int64_t na, int64_t nb, int norb, double ecore,
+                       const uint64_t* __restrict__ bstr, int nw, int64_t na, int64_t nb, int norb, double ecore,
                        double* __restrict__ diag) {
     const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (d >= na * nb) return;
     const int64_t ia = d / nb, ib = d % nb;
     const double* u = ua + ia * norb;
     double acc = ecore + ea[ia] + eb[ib];
-    for (uint64_t x = bstr[ib]; x; x &= x - 1) acc += u[__ffsll((unsigned long long)x) - 1];
+    str_for_each(bstr + ib * nw, nw, [&](int q) { acc += u[q]; });
     diag[d] = acc;
 }
 
@@ -299,7 +299,7 @@ int launch_same_spin(sqd_ctx* ctx, const T* X, T* Y, int64_t nrows, int64_t ncol
     if constexpr (sizeof(T) == 8) { sv = (const T*)col.sell_s_v64; dv = (const T*)col.sell_d_v64; }
     else { sv = (const T*)col.sell_s_v32; dv = (const T*)col.sell_d_v32; }
     ss_args<T> args{X, Y, nrows, ncols, col.perm_ss, col.nslices, col.sl_s_off, col.sl_d_off, col.sell_s_pk, sv,
-                    col.sell_d_nbr, dv, row.str, diag, accumulate};
+                    col.sell_d_nbr, dv, row.str, row.nw, diag, accumulate};
     prof_scope ps(ctx, timer_name);
 #define SQD_SS_LAUNCH(RR)                                                                                    \
     case RR:                                                                                                 \
@@ -481,10 +481,10 @@ int sqd_ensure_diag(sqd_ctx* ctx, sqd_space* sp) {
         if ((rc = sqd_alloc(ctx, (void**)&sp->diag, sizeof(double) * (sp->dim + 1), &sp->bytes))) return rc;
         if ((rc = sqd_alloc(ctx, (void**)&sp->ua, sizeof(double) * (A.n * sp->norb + 1), &sp->bytes))) return rc;
     }
-    hipLaunchKernelGGL(k_ua, dim3(nblk(A.n * sp->norb, 256)), dim3(256), 0, ctx->stream, A.str, A.n, sp->norb,
-                       ctx->jdiag, sp->ua);
+    hipLaunchKernelGGL(k_ua, dim3(nblk(A.n * sp->norb, 256)), dim3(256), 0, ctx->stream, A.str, sp->nw, A.n,
+                       sp->norb, ctx->jdiag, sp->ua);
     hipLaunchKernelGGL(k_diag, dim3(nblk(sp->dim, 256)), dim3(256), 0, ctx->stream, A.e_same, B.e_same, sp->ua,
-                       B.str, A.n, B.n, sp->norb, ctx->ecore, sp->diag);
+                       B.str, sp->nw, A.n, B.n, sp->norb, ctx->ecore, sp->diag);
     SQD_HIP(ctx, hipGetLastError());
     sp->diag_version = ctx->ham_version;
     return SQD_OK;

@@ -94,7 +94,8 @@ struct ss_args {
     const T* s_val;
     const int* d_nbr;
     const T* d_val;
-    const uint64_t* row_str;   // strings of the row spin (cross-spin term)
+    const uint64_t* row_str;   // strings of the row spin (cross-spin term), nw words each
+    int nw;
     const double* diag;        // fused DIAG term (or null)
     int accumulate;
 };
@@ -123,19 +124,23 @@ __device__ __forceinline__ void ss_block(const ss_args<T>& a, const T* __restric
     for (int idx = tid; idx < R * norb2; idx += nthr) {
         const int r = idx / norb2, pq = idx - r * norb2;
         const int64_t row = row0 + r;
-        const uint64_t x = (row < nrows) ? a.row_str[row] : 0ull;
         T acc = (T)0;
-        int k = 0;
-        for (; k + 4 <= norb; k += 4) {
-            T v[4];
+        for (int q = 0; q < a.nw; ++q) {
+            const uint64_t x = (row < nrows) ? a.row_str[row * a.nw + q] : 0ull;
+            const int kend = min(norb - 64 * q, 64);
+            const T* jq = jk + (int64_t)(64 * q) * norb2 + pq;
+            int k = 0;
+            for (; k + 4 <= kend; k += 4) {
+                T v[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) v[u] = jk[(k + u) * norb2 + pq];
+                for (int u = 0; u < 4; ++u) v[u] = jq[(int64_t)(k + u) * norb2];
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if ((x >> (k + u)) & 1ull) acc += v[u];
+                for (int u = 0; u < 4; ++u)
+                    if ((x >> (k + u)) & 1ull) acc += v[u];
+            }
+            for (; k < kend; ++k)
+                if ((x >> k) & 1ull) acc += jq[(int64_t)k * norb2];
         }
-        for (; k < norb; ++k)
-            if ((x >> k) & 1ull) acc += jk[k * norb2 + pq];
         ws[lds_cols<T, R>::idx(pq, r)] = acc;
     }
     __syncthreads();

@@ -8,11 +8,19 @@
 
 #include "../../include/sqd.h"
 
-#define SQD_MAXN 524287          // strings per spin (19-bit neighbour field)
-#define SQD_NBR_MASK 0x7FFFFu
-#define SQD_PAIR_SHIFT 19
-#define SQD_PAIR_MASK 0xFFFu
+// gather form of a single excitation: neighbour (17 bits) | orbital pair
+// a * norb + i (14 bits, norb <= 128) | negative sign (bit 31)
+#define SQD_MAXN 131071          // strings per spin (17-bit neighbour field)
+#define SQD_NBR_MASK 0x1FFFFu
+#define SQD_PAIR_SHIFT 17
+#define SQD_PAIR_MASK 0x3FFFu
 #define SQD_WAVE 64
+#define SQD_MAXORB 128           // orbitals: strings of one or two 64-bit words
+
+// canonical table entries (sqd_get_tables): target | o0 << 32 | o1 << 39 |
+// o2 << 46 | o3 << 53 | negative << 63, orbitals in 7-bit fields; singles
+// (o0, o1) = (i, a), doubles (o0, o1, o2, o3) = (i, j, a, b)
+#define SQD_ENT_ORB(x, f) ((int)(((x) >> (32 + 7 * (f))) & 127u))
 
 struct sqd_ctx {
     int device = 0;
@@ -89,7 +97,8 @@ struct prof_scope {
 struct spin_tables {
     int64_t n = 0;                // strings
     int nel = 0;
-    uint64_t* str = nullptr;      // ascending strings
+    int nw = 1;                   // 64-bit words per string (word q: orbitals 64q .. 64q+63)
+    uint64_t* str = nullptr;      // ascending strings, nw words each
     // canonical CSR (rows = source strings, entries sorted by target)
     int* s_off = nullptr;         // n+1
     uint64_t* s_ent = nullptr;    // packed canonical singles
@@ -126,6 +135,7 @@ struct spin_tables {
 struct sqd_space {
     sqd_ctx* ctx = nullptr;       // null once the context was destroyed (orphan)
     int norb = 0;
+    int nw = 1;                   // 64-bit words per string
     int nalpha = 0, nbeta = 0;
     spin_tables sp[2];            // 0 alpha, 1 beta
     int values_version = -1;      // ham_version the values were built for
@@ -178,7 +188,7 @@ int sqd_noalloc_init(int device);   // device address of the static product scra
 
 // ---- tables.hip ----
 int sqd_build_spin_tables(sqd_ctx* ctx, sqd_space* sp, int spin, const uint64_t* host_str,
-                          int64_t n, int nel);
+                          int64_t n, int nel);   // host_str: n x sp->nw words
 int sqd_build_values(sqd_ctx* ctx, sqd_space* sp);   // integral-dependent parts
 void sqd_free_spin_tables(spin_tables* t);
 
@@ -205,6 +215,10 @@ void sqd_release_stored_h(sqd_space* sp);
 int sqd_davidson_impl(sqd_ctx* ctx, sqd_space* sp, const sqd_davidson_opts* o, double* energy, double* vec,
                       sqd_report* rep, int nroots);
 
+// ---- block.hip ----
+int sqd_davidson_block_impl(sqd_ctx* ctx, sqd_space* sp, const sqd_davidson_opts* o, int nroots,
+                            double* energies, double* vecs, sqd_report* reps);
+
 // ---- rdm.hip ----
 int sqd_rdm_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* rdm1, double* rdm2);
 
@@ -216,7 +230,12 @@ int sqd_davidson_batched_impl(sqd_ctx* ctx, int nspace, sqd_space* const* spaces
 // ---- device helpers shared by kernels ----
 __device__ __forceinline__ int dev_popc(uint64_t x) { return __popcll(x); }
 
-// sign of applying a_k (or a+_k) to string s: (-1)^(occupied orbitals below k)
-__device__ __forceinline__ int dev_parity_below(uint64_t s, int k) {
-    return __popcll(s & ((k == 0) ? 0ull : ((~0ull) >> (64 - k)))) & 1;
+// bit k of a string of nw words
+__device__ __forceinline__ bool str_bit(const uint64_t* s, int k) { return (s[k >> 6] >> (k & 63)) & 1ull; }
+
+// f(k) for every occupied orbital k of a string of nw words, ascending
+template <typename F>
+__device__ __forceinline__ void str_for_each(const uint64_t* s, int nw, F&& f) {
+    for (int q = 0; q < nw; ++q)
+        for (uint64_t x = s[q]; x; x &= x - 1) f(64 * q + __ffsll((unsigned long long)x) - 1);
 }

@@ -32,6 +32,7 @@ struct store_args {
     const int* bs_off; const uint32_t* bs_pk; const double* bs_val;
     const int* bd_off; const int* bd_nbr; const double* bd_val;
     const uint64_t* astr; const uint64_t* bstr;
+    int nw;                    // words per string
     const double* jk;          // jk[k * norb2 + pq] = (pq|kk)
     const double* V;           // (pq|rs) as a norb2 x norb2 matrix
     int norb;
@@ -41,10 +42,11 @@ struct store_args {
     double* val;
 };
 
-// sum over occupied k of the string, in increasing k, of (pq|kk)
-__device__ __forceinline__ double cross_spin(const double* __restrict__ jk, int norb2, uint64_t s, int pair) {
+// sum over occupied k of the string (nw words), in increasing k, of (pq|kk)
+__device__ __forceinline__ double cross_spin(const double* __restrict__ jk, int norb2, const uint64_t* s, int nw,
+                                             int pair) {
     double w = 0.0;
-    for (uint64_t x = s; x; x &= x - 1) w += jk[(int64_t)(__ffsll((unsigned long long)x) - 1) * norb2 + pair];
+    str_for_each(s, nw, [&](int k) { w += jk[(int64_t)k * norb2 + pair]; });
     return w;
 }
 
@@ -76,7 +78,8 @@ __global__ void __launch_bounds__(256) k_store_fill(store_args a) {
         const int64_t e1 = 1 + nsa, e2 = e1 + nda, e3 = e2 + nsb, e4 = e3 + ndb;
         const int64_t e5 = e4 + (int64_t)nsa * nsb;
         const int64_t base = a.rp[d];
-        const uint64_t sa_str = a.astr[ia], sb_str = a.bstr[ib];
+        const uint64_t* sa_str = a.astr + ia * a.nw;
+        const uint64_t* sb_str = a.bstr + ib * a.nw;
         for (int64_t e = lane; e < e5; e += 64) {
             int64_t c;
             double v;
@@ -87,7 +90,7 @@ __global__ void __launch_bounds__(256) k_store_fill(store_args a) {
                 const int p = sa0 + (int)(e - 1);
                 const uint32_t pk = a.as_pk[p];
                 const int pair = (int)((pk >> SQD_PAIR_SHIFT) & SQD_PAIR_MASK);
-                const double w = cross_spin(a.jk, norb2, sb_str, pair);
+                const double w = cross_spin(a.jk, norb2, sb_str, a.nw, pair);
                 v = a.as_val[p] + ((pk >> 31) ? -w : w);
                 c = (int64_t)(pk & SQD_NBR_MASK) * a.nb + ib;
             } else if (e < e2) {            // alpha double
@@ -98,7 +101,7 @@ __global__ void __launch_bounds__(256) k_store_fill(store_args a) {
                 const int p = sb0 + (int)(e - e2);
                 const uint32_t pk = a.bs_pk[p];
                 const int pair = (int)((pk >> SQD_PAIR_SHIFT) & SQD_PAIR_MASK);
-                const double w = cross_spin(a.jk, norb2, sa_str, pair);
+                const double w = cross_spin(a.jk, norb2, sa_str, a.nw, pair);
                 v = a.bs_val[p] + ((pk >> 31) ? -w : w);
                 c = ia * a.nb + (int64_t)(pk & SQD_NBR_MASK);
             } else if (e < e4) {            // beta double
@@ -227,7 +230,8 @@ int sqd_store_h_impl(sqd_ctx* ctx, sqd_space* sp, int64_t* nnz_out) {
                            dPSB, A.s_off, A.d_off, na, nb, sp->h_rowptr);
         store_args a{na, nb, A.s_off, A.s_pk, A.s_val64, A.d_off, A.d_nbr, A.d_val64,
                      B.s_off, B.s_pk, B.s_val64, B.d_off, B.d_nbr, B.d_val64,
-                     A.str, B.str, ctx->jk64, ctx->eri, sp->norb, sp->diag, sp->h_rowptr, sp->h_col, sp->h_val};
+                     A.str, B.str, sp->nw, ctx->jk64, ctx->eri, sp->norb, sp->diag, sp->h_rowptr, sp->h_col,
+                     sp->h_val};
         hipLaunchKernelGGL(k_store_fill, dim3(fill_grid(dim)), dim3(256), 0, ctx->stream, a);
         e = hipGetLastError();
         if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);

@@ -14,72 +14,126 @@
 
 namespace {
 
-constexpr int kWavesPerBlock = 4;
+// A string of NW 64-bit words (word q: orbitals 64q .. 64q+63) held in registers.
+template <int NW>
+struct wstr {
+    uint64_t w[NW];
+    __device__ __forceinline__ void flip(int k) { w[k >> 6] ^= 1ull << (k & 63); }
+};
 
-__device__ __forceinline__ int64_t find_string(const uint64_t* __restrict__ s, int64_t n, uint64_t key) {
+template <int NW>
+__device__ __forceinline__ wstr<NW> load_str(const uint64_t* __restrict__ s, int64_t r) {
+    wstr<NW> x;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) x.w[q] = s[r * NW + q];
+    return x;
+}
+
+// Binary search of the ascending strings (as NW-word integers, word NW-1 most
+// significant) for key.
+template <int NW>
+__device__ __forceinline__ int64_t find_string(const uint64_t* __restrict__ s, int64_t n, const wstr<NW>& key) {
     int64_t lo = 0, hi = n - 1;
     while (lo <= hi) {
-        int64_t mid = (lo + hi) >> 1;
-        uint64_t v = s[mid];
-        if (v == key) return mid;
-        if (v < key) lo = mid + 1; else hi = mid - 1;
+        const int64_t mid = (lo + hi) >> 1;
+        int c = 0;
+#pragma unroll
+        for (int q = NW - 1; q >= 0; --q) {
+            const uint64_t v = s[mid * NW + q];
+            if (c == 0 && v != key.w[q]) c = v < key.w[q] ? -1 : 1;
+        }
+        if (c == 0) return mid;
+        if (c < 0) lo = mid + 1; else hi = mid - 1;
     }
     return -1;
 }
 
 // Occupied / virtual orbital lists of string s, built by one wavefront (lane =
-// orbital) into LDS, each ascending.
-__device__ __forceinline__ void orbital_lists(uint64_t s, int norb, uint8_t* occ, uint8_t* vir) {
+// orbital within a word) into LDS, each ascending.
+template <int NW>
+__device__ __forceinline__ void orbital_lists(const wstr<NW>& s, int norb, uint8_t* occ, uint8_t* vir) {
     const int lane = threadIdx.x & 63;
-    const bool in = lane < norb;
-    const bool o = in && ((s >> lane) & 1ull);
-    const uint64_t bo = __ballot(o);
-    const uint64_t bv = __ballot(in && !o);
     const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-    if (o) occ[__popcll(bo & below)] = (uint8_t)lane;
-    if (in && !o) vir[__popcll(bv & below)] = (uint8_t)lane;
+    int no = 0, nv = 0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+        const int orb = 64 * q + lane;
+        const bool in = orb < norb;
+        const bool o = in && ((s.w[q] >> lane) & 1ull);
+        const uint64_t bo = __ballot(o);
+        const uint64_t bv = __ballot(in && !o);
+        if (o) occ[no + __popcll(bo & below)] = (uint8_t)orb;
+        if (in && !o) vir[nv + __popcll(bv & below)] = (uint8_t)orb;
+        no += __popcll(bo);
+        nv += __popcll(bv);
+    }
+}
+
+// (-1)^(occupied orbitals below k) as 0 / 1
+template <int NW>
+__device__ __forceinline__ int parity_below(const wstr<NW>& s, int k) {
+    int c = 0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+        const int lo = 64 * q;
+        if (k >= lo + 64) c += __popcll(s.w[q]);
+        else if (k > lo) c += __popcll(s.w[q] & ((~0ull) >> (64 - (k - lo))));
+    }
+    return c & 1;
 }
 
 // Sign of a+_a a_i applied to s (a_i first).
-__device__ __forceinline__ int single_sign(uint64_t s, int i, int a) {
-    int p = dev_parity_below(s, i);
-    uint64_t t = s & ~(1ull << i);
-    p ^= dev_parity_below(t, a);
+template <int NW>
+__device__ __forceinline__ int single_sign(wstr<NW> s, int i, int a) {
+    int p = parity_below(s, i);
+    s.flip(i);
+    p ^= parity_below(s, a);
     return p;  // 1 = negative
 }
 
 // Sign of a+_a a+_b a_j a_i applied to s (a_i, a_j, a+_b, a+_a in that order).
-__device__ __forceinline__ int double_sign(uint64_t s, int i, int j, int a, int b) {
-    int p = dev_parity_below(s, i);
-    uint64_t t = s & ~(1ull << i);
-    p ^= dev_parity_below(t, j);
-    t &= ~(1ull << j);
-    p ^= dev_parity_below(t, b);
-    t |= (1ull << b);
-    p ^= dev_parity_below(t, a);
+template <int NW>
+__device__ __forceinline__ int double_sign(wstr<NW> s, int i, int j, int a, int b) {
+    int p = parity_below(s, i);
+    s.flip(i);
+    p ^= parity_below(s, j);
+    s.flip(j);
+    p ^= parity_below(s, b);
+    s.flip(b);
+    p ^= parity_below(s, a);
     return p;
 }
 
+// Waves per block and LDS slots for the (x < y) orbital pairs of one string:
+// C(64, 2) for one-word strings, C(128, 2) (one wave per block) for two.
+template <int NW> struct enum_shape;
+template <> struct enum_shape<1> { static constexpr int kWaves = 4, kPairs = 2016; };
+template <> struct enum_shape<2> { static constexpr int kWaves = 1, kPairs = 8128; };
+
 // KIND 0: singles, 1: doubles.  MODE 0: count, 1: fill.
-template <int KIND, int MODE>
-__global__ void __launch_bounds__(64 * kWavesPerBlock)
+template <int KIND, int MODE, int NW>
+__global__ void __launch_bounds__(64 * enum_shape<NW>::kWaves)
 k_enum(const uint64_t* __restrict__ str, int64_t n, int norb, int nel,
        int* __restrict__ counts, const int* __restrict__ off,
        uint64_t* __restrict__ keys, uint32_t* __restrict__ payload) {
-    __shared__ uint8_t s_occ[kWavesPerBlock][64];
-    __shared__ uint8_t s_vir[kWavesPerBlock][64];
-    __shared__ uint16_t s_op[kWavesPerBlock][2016];
-    __shared__ uint16_t s_vp[kWavesPerBlock][2016];
+    constexpr int WPB = enum_shape<NW>::kWaves, NP = enum_shape<NW>::kPairs;
+    __shared__ uint8_t s_occ[WPB][64 * NW];
+    __shared__ uint8_t s_vir[WPB][64 * NW];
+    __shared__ uint16_t s_op[WPB][KIND == 1 ? NP : 1];
+    __shared__ uint16_t s_vp[WPB][KIND == 1 ? NP : 1];
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    const int64_t row = (int64_t)blockIdx.x * kWavesPerBlock + w;
+    const int64_t row = (int64_t)blockIdx.x * WPB + w;
     // every wave reaches both barriers; waves past the end do no work
     const bool valid = row < n;
-    const uint64_t s = valid ? str[row] : 0ull;
+    wstr<NW> s;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) s.w[q] = 0ull;
+    if (valid) s = load_str<NW>(str, row);
     const int nvir = norb - nel;
     uint8_t* occ = s_occ[w];
     uint8_t* vir = s_vir[w];
-    if (valid) orbital_lists(s, norb, occ, vir);
+    if (valid) orbital_lists<NW>(s, norb, occ, vir);
     int npo = 0, npv = 0;
     if (KIND == 1) {
         npo = nel * (nel - 1) / 2;
@@ -109,29 +163,33 @@ k_enum(const uint64_t* __restrict__ str, int64_t n, int norb, int nel,
         int64_t tgt = -1;
         int i = 0, j = 0, a = 0, b = 0;
         if (c < ncand) {
-            uint64_t t;
+            wstr<NW> t = s;
             if (KIND == 0) {
                 i = occ[c / nvir];
                 a = vir[c % nvir];
-                t = (s & ~(1ull << i)) | (1ull << a);
+                t.flip(i);
+                t.flip(a);
             } else {
                 const uint16_t op = s_op[w][c / npv];
                 const uint16_t vp = s_vp[w][c % npv];
                 i = op & 0xFF; j = op >> 8; a = vp & 0xFF; b = vp >> 8;
-                t = (s & ~(1ull << i) & ~(1ull << j)) | (1ull << a) | (1ull << b);
+                t.flip(i);
+                t.flip(j);
+                t.flip(a);
+                t.flip(b);
             }
-            tgt = find_string(str, n, t);
+            tgt = find_string<NW>(str, n, t);
         }
         const bool hit = tgt >= 0;
         const uint64_t m = __ballot(hit);
         if (MODE == 1 && hit) {
             const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
             const int pos = base + found + __popcll(m & below);
-            keys[pos] = ((uint64_t)row << 19) | (uint64_t)tgt;
-            uint32_t neg = (KIND == 0) ? (uint32_t)single_sign(s, i, a)
-                                       : (uint32_t)double_sign(s, i, j, a, b);
-            payload[pos] = (uint32_t)i | ((uint32_t)j << 6) | ((uint32_t)a << 12) |
-                           ((uint32_t)b << 18) | (neg << 31);
+            keys[pos] = ((uint64_t)row << 17) | (uint64_t)tgt;
+            uint32_t neg = (KIND == 0) ? (uint32_t)single_sign<NW>(s, i, a)
+                                       : (uint32_t)double_sign<NW>(s, i, j, a, b);
+            payload[pos] = (uint32_t)i | ((uint32_t)j << 7) | ((uint32_t)a << 14) |
+                           ((uint32_t)b << 21) | (neg << 31);
         }
         found += __popcll(m);
     }
@@ -174,14 +232,14 @@ __global__ void k_pack(const uint64_t* __restrict__ keys, const uint32_t* __rest
     if (e >= nnz) return;
     const uint64_t tgt = keys[e] & SQD_NBR_MASK;
     const uint32_t p = payload[e];
-    const uint64_t i = p & 63, j = (p >> 6) & 63, a = (p >> 12) & 63, b = (p >> 18) & 63;
+    const uint64_t i = p & 127, j = (p >> 7) & 127, a = (p >> 14) & 127, b = (p >> 21) & 127;
     const uint64_t neg = p >> 31;
     if (KIND == 0) {
-        ent[e] = tgt | (i << 32) | (a << 38) | (neg << 63);
+        ent[e] = tgt | (i << 32) | (a << 39) | (neg << 63);
         const uint32_t pair = (uint32_t)(a * norb + i);
         pk[e] = (uint32_t)tgt | (pair << SQD_PAIR_SHIFT) | ((uint32_t)neg << 31);
     } else {
-        ent[e] = tgt | (i << 32) | (j << 38) | (a << 44) | (b << 50) | (neg << 63);
+        ent[e] = tgt | (i << 32) | (j << 39) | (a << 46) | (b << 53) | (neg << 63);
         nbr[e] = (int)tgt;
     }
 }
@@ -298,44 +356,41 @@ __global__ void k_sell_fill_nbr(const int* __restrict__ perm, int64_t n, int nsl
 // ---- integral-dependent values ----
 
 // e_same[r] = sum_{i in s} h_ii + 1/2 sum_{i,j in s} [(ii|jj) - (ij|ji)]
-__global__ void k_same_energy(const uint64_t* __restrict__ str, int64_t n, int norb,
+__global__ void k_same_energy(const uint64_t* __restrict__ str, int nw, int64_t n, int norb,
                               const double* __restrict__ h, const double* __restrict__ eri,
                               double* __restrict__ e) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
-    const uint64_t s = str[r];
+    const uint64_t* s = str + r * nw;
     const int64_t n2 = (int64_t)norb * norb;
     double acc = 0.0;
-    for (uint64_t x = s; x; x &= x - 1) {
-        const int i = __ffsll((unsigned long long)x) - 1;
+    str_for_each(s, nw, [&](int i) {
         acc += h[i * norb + i];
-        for (uint64_t y = s; y; y &= y - 1) {
-            const int j = __ffsll((unsigned long long)y) - 1;
+        str_for_each(s, nw, [&](int j) {
             acc += 0.5 * (eri[(int64_t)(i * norb + i) * n2 + j * norb + j] -
                           eri[(int64_t)(i * norb + j) * n2 + j * norb + i]);
-        }
-    }
+        });
+    });
     e[r] = acc;
 }
 
 // single (row string s, i -> a in the neighbour): sign * [h_ai + sum_{k in s}((ai|kk) - (ak|ki))]
-__global__ void k_single_values(const uint64_t* __restrict__ str, const int* __restrict__ off, int64_t n,
+__global__ void k_single_values(const uint64_t* __restrict__ str, int nw, const int* __restrict__ off, int64_t n,
                                 const uint64_t* __restrict__ ent, int norb,
                                 const double* __restrict__ h, const double* __restrict__ eri,
                                 double* __restrict__ v64, float* __restrict__ v32) {
     const int64_t r = (int64_t)blockIdx.x;
     if (r >= n) return;
-    const uint64_t s = str[r];
+    const uint64_t* s = str + r * nw;
     const int64_t n2 = (int64_t)norb * norb;
     for (int e = off[r] + threadIdx.x; e < off[r + 1]; e += blockDim.x) {
         const uint64_t x = ent[e];
-        const int i = (int)((x >> 32) & 63), a = (int)((x >> 38) & 63);
+        const int i = SQD_ENT_ORB(x, 0), a = SQD_ENT_ORB(x, 1);
         double acc = h[a * norb + i];
-        for (uint64_t y = s; y; y &= y - 1) {
-            const int k = __ffsll((unsigned long long)y) - 1;
+        str_for_each(s, nw, [&](int k) {
             acc += eri[(int64_t)(a * norb + i) * n2 + k * norb + k] -
                    eri[(int64_t)(a * norb + k) * n2 + k * norb + i];
-        }
+        });
         if (x >> 63) acc = -acc;
         v64[e] = acc;
         v32[e] = (float)acc;
@@ -349,8 +404,8 @@ __global__ void k_double_values(const uint64_t* __restrict__ ent, int64_t nnz, i
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= nnz) return;
     const uint64_t x = ent[e];
-    const int i = (int)((x >> 32) & 63), j = (int)((x >> 38) & 63);
-    const int a = (int)((x >> 44) & 63), b = (int)((x >> 50) & 63);
+    const int i = SQD_ENT_ORB(x, 0), j = SQD_ENT_ORB(x, 1);
+    const int a = SQD_ENT_ORB(x, 2), b = SQD_ENT_ORB(x, 3);
     const int64_t n2 = (int64_t)norb * norb;
     double v = eri[(int64_t)(a * norb + i) * n2 + b * norb + j] - eri[(int64_t)(a * norb + j) * n2 + b * norb + i];
     if (x >> 63) v = -v;
@@ -398,9 +453,24 @@ int build_kind(sqd_ctx* ctx, sqd_space* sp, spin_tables& t, int** off_out, uint6
     int* off = nullptr;
     int rc = sqd_alloc(ctx, (void**)&off, sizeof(int) * (t.n + 1), &sp->bytes);
     if (rc) return rc;
-    const unsigned grid = nblocks(t.n, kWavesPerBlock);
-    hipLaunchKernelGGL((k_enum<KIND, 0>), dim3(grid), dim3(64 * kWavesPerBlock), 0, ctx->stream,
-                       t.str, t.n, norb, t.nel, counts, nullptr, nullptr, nullptr);
+    uint64_t* keys_ = nullptr;
+    uint32_t* pay_ = nullptr;
+    auto launch_enum = [&](int mode) {
+        const int wpb = t.nw == 1 ? enum_shape<1>::kWaves : enum_shape<2>::kWaves;
+        const dim3 grid(nblocks(t.n, wpb)), block(64 * wpb);
+        int* cnt = mode == 0 ? counts : nullptr;
+        const int* of = mode == 0 ? nullptr : off;
+        uint64_t* ky = mode == 0 ? nullptr : keys_;
+        uint32_t* py = mode == 0 ? nullptr : pay_;
+        if (t.nw == 1) {
+            if (mode == 0) hipLaunchKernelGGL((k_enum<KIND, 0, 1>), grid, block, 0, ctx->stream, t.str, t.n, norb, t.nel, cnt, of, ky, py);
+            else hipLaunchKernelGGL((k_enum<KIND, 1, 1>), grid, block, 0, ctx->stream, t.str, t.n, norb, t.nel, cnt, of, ky, py);
+        } else {
+            if (mode == 0) hipLaunchKernelGGL((k_enum<KIND, 0, 2>), grid, block, 0, ctx->stream, t.str, t.n, norb, t.nel, cnt, of, ky, py);
+            else hipLaunchKernelGGL((k_enum<KIND, 1, 2>), grid, block, 0, ctx->stream, t.str, t.n, norb, t.nel, cnt, of, ky, py);
+        }
+    };
+    launch_enum(0);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, ctx->stream, counts, t.n, off, dtot);
     long long total = 0;
     SQD_HIP(ctx, hipMemcpyAsync(&total, dtot, sizeof(long long), hipMemcpyDeviceToHost, ctx->stream));
@@ -414,10 +484,11 @@ int build_kind(sqd_ctx* ctx, sqd_space* sp, spin_tables& t, int** off_out, uint6
     uint64_t* keys = nullptr; uint32_t* pay = nullptr;
     SQD_HIP(ctx, hipMalloc(&keys, sizeof(uint64_t) * (nnz + 1)));
     SQD_HIP(ctx, hipMalloc(&pay, sizeof(uint32_t) * (nnz + 1)));
-    hipLaunchKernelGGL((k_enum<KIND, 1>), dim3(grid), dim3(64 * kWavesPerBlock), 0, ctx->stream,
-                       t.str, t.n, norb, t.nel, nullptr, off, keys, pay);
+    keys_ = keys;
+    pay_ = pay;
+    launch_enum(1);
     SQD_HIP(ctx, hipGetLastError());
-    rc = radix_sort(ctx, keys, pay, nnz, 38);
+    rc = radix_sort(ctx, keys, pay, nnz, 34);   // (row << 17 | target): rows, then targets
     if (rc) return rc;
     uint64_t* ent = nullptr; uint32_t* pk = nullptr; int* nbr = nullptr;
     if ((rc = sqd_alloc(ctx, (void**)&ent, sizeof(uint64_t) * (nnz + 1), &sp->bytes))) return rc;
@@ -479,9 +550,10 @@ int sqd_build_spin_tables(sqd_ctx* ctx, sqd_space* sp, int spin, const uint64_t*
     spin_tables& t = sp->sp[spin];
     t.n = n;
     t.nel = nel;
-    int rc = sqd_alloc(ctx, (void**)&t.str, sizeof(uint64_t) * (n > 0 ? n : 1), &sp->bytes);
+    t.nw = sp->nw;
+    int rc = sqd_alloc(ctx, (void**)&t.str, sizeof(uint64_t) * (n > 0 ? n : 1) * t.nw, &sp->bytes);
     if (rc) return rc;
-    SQD_HIP(ctx, hipMemcpyAsync(t.str, host_str, sizeof(uint64_t) * n, hipMemcpyHostToDevice, ctx->stream));
+    SQD_HIP(ctx, hipMemcpyAsync(t.str, host_str, sizeof(uint64_t) * n * t.nw, hipMemcpyHostToDevice, ctx->stream));
     int* dummy_nbr = nullptr; uint32_t* dummy_pk = nullptr;
     if ((rc = build_kind<0>(ctx, sp, t, &t.s_off, &t.s_ent, &t.s_pk, &dummy_nbr, &t.nnz_s))) return rc;
     if ((rc = build_kind<1>(ctx, sp, t, &t.d_off, &t.d_ent, &dummy_pk, &t.d_nbr, &t.nnz_d))) return rc;
@@ -555,10 +627,10 @@ int sqd_build_values(sqd_ctx* ctx, sqd_space* sp) {
         spin_tables& t = sp->sp[spin];
         if (t.alias) continue;
         if (t.n > 0) {
-            hipLaunchKernelGGL(k_same_energy, dim3(nblocks(t.n, 128)), dim3(128), 0, ctx->stream, t.str, t.n, norb,
-                               ctx->h, ctx->eri, t.e_same);
-            hipLaunchKernelGGL(k_single_values, dim3((unsigned)t.n), dim3(64), 0, ctx->stream, t.str, t.s_off, t.n,
-                               t.s_ent, norb, ctx->h, ctx->eri, t.s_val64, t.s_val32);
+            hipLaunchKernelGGL(k_same_energy, dim3(nblocks(t.n, 128)), dim3(128), 0, ctx->stream, t.str, t.nw, t.n,
+                               norb, ctx->h, ctx->eri, t.e_same);
+            hipLaunchKernelGGL(k_single_values, dim3((unsigned)t.n), dim3(64), 0, ctx->stream, t.str, t.nw, t.s_off,
+                               t.n, t.s_ent, norb, ctx->h, ctx->eri, t.s_val64, t.s_val32);
         }
         if (t.nnz_d > 0)
             hipLaunchKernelGGL(k_double_values, dim3(nblocks(t.nnz_d, 256)), dim3(256), 0, ctx->stream, t.d_ent,

@@ -56,6 +56,10 @@ class Problem:
     def dim(self) -> int:
         return int(len(self.astr)) * int(len(self.bstr))
 
+    @property
+    def nwords(self) -> int:
+        return 1 if np.asarray(self.astr).ndim == 1 else int(np.asarray(self.astr).shape[1])
+
 
 def make_integrals(norb: int, nchol: int, seed: int,
                    diag_range: Tuple[float, float] = (-2.0, 0.0),
@@ -120,6 +124,87 @@ def sample_strings(norb: int, n: int, count: int, seed: int, p: float = 0.4,
             seen.add(s)
             out.append(s)
     return np.array(sorted(out), dtype=np.uint64)
+
+
+def to_words(strings, nw: int = 2) -> np.ndarray:
+    """Strings (Python ints or a uint64 array) as an (n, nw) uint64 array, word
+    q holding orbitals 64 q .. 64 q + 63."""
+    vals = [int(x) for x in strings]
+    out = np.zeros((len(vals), nw), dtype=np.uint64)
+    for k, v in enumerate(vals):
+        for q in range(nw):
+            out[k, q] = (v >> (64 * q)) & 0xFFFFFFFFFFFFFFFF
+    return out
+
+
+def from_words(words: np.ndarray) -> list:
+    """Inverse of to_words: Python ints."""
+    a = np.asarray(words, dtype=np.uint64)
+    if a.ndim == 1:
+        return [int(x) for x in a]
+    return [sum(int(w) << (64 * q) for q, w in enumerate(row)) for row in a]
+
+
+def sample_strings_words(norb: int, n: int, count: int, seed: int, p: float = 0.4) -> np.ndarray:
+    """HF-biased strings as sample_strings, for norb up to 128: an ascending
+    (count, 2) uint64 array of two-word strings."""
+    from math import comb
+    if count > comb(norb, n):
+        raise ValueError("requested more strings than C(norb, n)")
+    rng = np.random.default_rng(seed)
+    kmax = min(n, norb - n)
+    hf = hf_string(n)
+    seen = {hf}
+    while len(seen) < count:
+        k = min(int(rng.geometric(p)), kmax)
+        occ = rng.choice(n, size=k, replace=False)
+        vir = rng.choice(norb - n, size=k, replace=False) + n
+        s = hf
+        for o in occ:
+            s &= ~(1 << int(o))
+        for v in vir:
+            s |= (1 << int(v))
+        seen.add(s)
+    return to_words(sorted(seen), 2)
+
+
+def embed_problem(prob: "Problem", norb_big: int, orb_map, seed: int) -> "Problem":
+    """The same problem on norb_big orbitals: orbital p becomes orb_map[p]
+    (distinct, below norb_big); the other orbitals are never occupied.  The
+    integrals among mapped orbitals are the original ones; every other
+    integral is random (with the full symmetry), and none of them can enter
+    H restricted to the embedded strings.  Strings are two-word arrays sorted
+    ascending; with an increasing orb_map the order, and every sign, of the
+    original is kept."""
+    m = np.asarray(orb_map, dtype=np.int64)
+    assert len(m) == prob.norb and len(set(m.tolist())) == prob.norb and m.max() < norb_big
+    big = make_integrals(norb_big, 4, seed)
+    h = big.h.copy()
+    eri = big.eri.copy()
+    h[np.ix_(m, m)] = prob.ints.h
+    eri[np.ix_(m, m, m, m)] = prob.ints.eri
+
+    def relabel(strs):
+        out = []
+        for s in from_words(strs):
+            t = 0
+            for q in range(prob.norb):
+                if (s >> q) & 1:
+                    t |= 1 << int(m[q])
+            out.append(t)
+        return to_words(sorted(out), 2)
+
+    ints = Integrals(norb=norb_big, h=np.ascontiguousarray(h), eri=np.ascontiguousarray(eri), ecore=prob.ints.ecore)
+    return Problem(f"{prob.name}_in{norb_big}", ints, prob.nalpha, prob.nbeta, relabel(prob.astr), relabel(prob.bstr))
+
+
+def words_problem(norb: int, nalpha: int, nbeta: int, na: int, nb: int, seed: int) -> "Problem":
+    """A random problem on norb (<= 128) orbitals with two-word strings
+    (HF-biased alpha and beta sets drawn independently)."""
+    ints = make_integrals(norb, 4, seed=seed)
+    a = sample_strings_words(norb, nalpha, na, 1000 + seed)
+    b = sample_strings_words(norb, nbeta, nb, 2000 + seed)
+    return Problem(f"words_{norb}_{nalpha}_{nbeta}_{na}_{nb}_{seed}", ints, nalpha, nbeta, a, b)
 
 
 def all_strings(norb: int, n: int) -> np.ndarray:

@@ -61,7 +61,7 @@ class Report(ctypes.Structure):
                 ("switch_iter", ctypes.c_int), ("converged", ctypes.c_int), ("status", ctypes.c_int),
                 ("nhist", ctypes.c_int), ("energy", ctypes.c_double), ("residual", ctypes.c_double),
                 ("seconds", ctypes.c_double), ("residual_history", ctypes.c_double * HIST),
-                ("energy_history", ctypes.c_double * HIST)]
+                ("energy_history", ctypes.c_double * HIST), ("products", ctypes.c_int)]
 
     def as_dict(self):
         n = min(self.nhist, HIST)
@@ -69,6 +69,7 @@ class Report(ctypes.Structure):
                 "switch_iter": self.switch_iter, "converged": bool(self.converged),
                 "status": self.status, "energy": self.energy, "residual": self.residual,
                 "seconds": self.seconds,
+                "products": self.products,
                 "residual_history": list(self.residual_history[:n]),
                 "energy_history": list(self.energy_history[:n])}
 
@@ -81,7 +82,7 @@ EXPORTS = [
     "sqd_get_tables", "sqd_diag", "sqd_sigma", "sqd_davidson_default_opts", "sqd_davidson",
     "sqd_davidson_batched", "sqd_rdm", "sqd_profile", "sqd_profile_report", "sqd_release_workspace",
     "sqd_davidson_roots", "sqd_sigma_noalloc", "sqd_store_hamiltonian", "sqd_release_hamiltonian", "sqd_spmv",
-    "sqd_get_stored_hamiltonian",
+    "sqd_get_stored_hamiltonian", "sqd_davidson_block", "sqd_build_space_words",
 ]
 
 
@@ -105,6 +106,7 @@ def lib():
     L.sqd_get_tuning.argtypes = [P, c_int, ctypes.POINTER(c_int)]
     L.sqd_set_hamiltonian.argtypes = [P, c_int, P, P, d]
     L.sqd_build_space.argtypes = [P, c_int, c_int, P, i64, P, i64, ctypes.POINTER(P)]
+    L.sqd_build_space_words.argtypes = [P, c_int, c_int, c_int, P, i64, P, i64, ctypes.POINTER(P)]
     L.sqd_space_free.argtypes = [P]
     L.sqd_space_free.restype = None
     L.sqd_space_info.argtypes = [P, ctypes.POINTER(SpaceInfo)]
@@ -126,6 +128,7 @@ def lib():
     L.sqd_profile.argtypes = [P, c_int]
     L.sqd_release_workspace.argtypes = [P]
     L.sqd_davidson_roots.argtypes = [P, P, P, c_int, P, P, P]
+    L.sqd_davidson_block.argtypes = [P, P, P, c_int, P, P, P]
     L.sqd_profile_report.argtypes = [P, ctypes.c_char_p, c_int]
     _lib = L
     return L
@@ -227,12 +230,21 @@ class Context:
         self.norb = norb
 
     def build_space(self, nalpha: int, nbeta: int, astr, bstr) -> "Space":
+        """Strings as uint64 arrays of shape (n,) (one word) or (n, nwords)."""
         a = np.ascontiguousarray(np.asarray(astr, dtype=np.uint64))
         b = np.ascontiguousarray(np.asarray(bstr, dtype=np.uint64))
         h = ctypes.c_void_p()
-        self._check(lib().sqd_build_space(self._h, nalpha, nbeta, a.ctypes.data_as(ctypes.c_void_p), len(a),
-                                          b.ctypes.data_as(ctypes.c_void_p), len(b), ctypes.byref(h)),
-                    "sqd_build_space")
+        if a.ndim == 1 and b.ndim == 1:
+            self._check(lib().sqd_build_space(self._h, nalpha, nbeta, a.ctypes.data_as(ctypes.c_void_p), len(a),
+                                              b.ctypes.data_as(ctypes.c_void_p), len(b), ctypes.byref(h)),
+                        "sqd_build_space")
+        else:
+            if a.ndim != 2 or b.ndim != 2 or a.shape[1] != b.shape[1]:
+                raise ValueError("string arrays must both be (n,) or (n, nwords) with the same nwords")
+            self._check(lib().sqd_build_space_words(self._h, nalpha, nbeta, int(a.shape[1]),
+                                                    a.ctypes.data_as(ctypes.c_void_p), len(a),
+                                                    b.ctypes.data_as(ctypes.c_void_p), len(b), ctypes.byref(h)),
+                        "sqd_build_space_words")
         return Space(self, h, len(a), len(b))
 
     def davidson_batched(self, spaces: Sequence["Space"], tol=1e-8, max_iter=200, m_max=24, mode=DAV_FP64,
@@ -393,6 +405,23 @@ class Space:
         rc = self.ctx._check(lib().sqd_davidson_roots(self.ctx._h, self._h, ctypes.byref(o), nroots, e,
                                                       _dev_ptr(vecs, numel=nroots * self.dim), reps),
                              "sqd_davidson_roots")
+        out = [r.as_dict() for r in reps]
+        for r in out:
+            r["status_code"] = rc
+        return list(e), vecs, out
+
+    def davidson_block(self, nroots, tol=1e-8, max_iter=200, m_max=24, mode=DAV_FP64, switch_tol=1e-4,
+                       ab_path=AB_AUTO, product=PRODUCT_MATRIX_FREE):
+        """The nroots lowest eigenpairs by block Davidson: (energies, vectors
+        (nroots x dim), reports)."""
+        torch = _torch()
+        vecs = torch.empty((nroots, self.dim), dtype=torch.float64, device=self._dev)
+        o = _opts(tol, max_iter, m_max, mode, switch_tol, ab_path, None, None, 1, product)
+        e = (ctypes.c_double * nroots)()
+        reps = (Report * nroots)()
+        rc = self.ctx._check(lib().sqd_davidson_block(self.ctx._h, self._h, ctypes.byref(o), nroots, e,
+                                                      _dev_ptr(vecs, numel=nroots * self.dim), reps),
+                             "sqd_davidson_block")
         out = [r.as_dict() for r in reps]
         for r in out:
             r["status_code"] = rc

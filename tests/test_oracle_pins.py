@@ -412,3 +412,89 @@ def test_generator_properties():
     assert np.all(np.diff(d) >= 0) and d.min() >= -2 and d.max() <= 0
     # reproducible
     assert np.array_equal(I.cfg2().astr, p.astr)
+
+
+# ---------------------------------------------------------------- two-word strings (norb > 64)
+# The two-word path of the oracle (and of its table builder) is pinned to the
+# one-word path, itself pinned to Jordan-Wigner above: a problem on 8 orbitals
+# relabelled onto 72 or 96 orbitals, the other orbitals never occupied, is the
+# same Hamiltonian.  An increasing relabelling keeps the string order and
+# every sign (no empty orbital changes an occupation count below another), so
+# sigma agrees element by element; any relabelling keeps the spectrum and,
+# up to the determinant permutation and signs, the matrix.
+
+MAP72 = [3, 17, 40, 63, 64, 65, 70, 71]          # increasing, across the word boundary
+MAP96 = [90, 5, 64, 33, 71, 2, 95, 60]           # not monotone
+
+
+def _small8():
+    return I.small_problem(8, 3, 4, 37, 53, 3)
+
+
+def test_two_word_embedding_keeps_sigma_elementwise():
+    p = _small8()
+    q = I.embed_problem(p, 72, MAP72, seed=11)
+    sp, sq = _space(p), _space(q)
+    assert sq.nw == 2 and sq.norb == 72
+    c = I.random_vector(sp.dim, 3)
+    for mask in (core.DIAG, core.AA, core.BB, core.AB, core.ALL):
+        a, b = sp.sigma(c, mask), sq.sigma(c, mask)
+        assert np.abs(a - b).max() <= 1e-13 * max(1.0, np.abs(a).max()), mask
+    assert np.abs(sp.diag() - sq.diag()).max() <= 1e-13
+
+
+def test_two_word_embedding_keeps_spectrum_and_matrix_up_to_permutation():
+    p = _small8()
+    q = I.embed_problem(p, 96, MAP96, seed=12)
+    Hp, Hq = _space(p).dense(), _space(q).dense()
+    wp, wq = np.linalg.eigvalsh(Hp), np.linalg.eigvalsh(Hq)
+    assert np.abs(wp - wq).max() <= 1e-10
+    # determinant permutation: where each relabelled string landed
+    def relabel(s):
+        return sum(1 << MAP96[k] for k in range(8) if (int(s) >> k) & 1)
+    ia = {v: k for k, v in enumerate(I.from_words(q.astr))}
+    ib = {v: k for k, v in enumerate(I.from_words(q.bstr))}
+    pa = [ia[relabel(s)] for s in p.astr]
+    pb = [ib[relabel(s)] for s in p.bstr]
+    perm = np.array([pa[i] * len(pb) + pb[j] for i in range(len(pa)) for j in range(len(pb))])
+    Hq_back = Hq[np.ix_(perm, perm)]
+    assert np.abs(np.abs(Hq_back) - np.abs(Hp)).max() <= 1e-13 * np.abs(Hp).max()
+    # and the signs are a diagonal similarity H_q = D H_p D, D_I the parity of
+    # the permutation that sorts the relabelled creators of I (per spin)
+    def parity(s):
+        occ = [MAP96[k] for k in range(8) if (int(s) >> k) & 1]
+        inv = sum(1 for x in range(len(occ)) for y in range(x + 1, len(occ)) if occ[x] > occ[y])
+        return -1.0 if inv % 2 else 1.0
+    da = np.array([parity(s) for s in p.astr])
+    db = np.array([parity(s) for s in p.bstr])
+    d = np.outer(da, db).ravel()
+    assert np.abs(Hq_back - np.outer(d, d) * Hp).max() <= 1e-13 * np.abs(Hp).max()
+
+
+def test_two_word_tables_are_relabelled_one_word_tables():
+    p = _small8()
+    q = I.embed_problem(p, 72, MAP72, seed=11)
+    for s1, s2 in ((p.astr, q.astr), (p.bstr, q.bstr)):
+        so, se, do, de = tables.build_tables(s1, 8)
+        so2, se2, do2, de2 = tables.build_tables(s2, 72)
+        assert np.array_equal(so, so2) and np.array_equal(do, do2)
+        for e, e2 in zip(se, se2):
+            t, i, a, sg = tables.unpack(e, "single")
+            assert tables.unpack(e2, "single") == (t, MAP72[i], MAP72[a], sg)
+        for e, e2 in zip(de, de2):
+            t, i, j, a, b, sg = tables.unpack(e, "double")
+            assert tables.unpack(e2, "double") == (t, MAP72[i], MAP72[j], MAP72[a], MAP72[b], sg)
+
+
+def test_two_word_rdms_are_relabelled():
+    p = _small8()
+    q = I.embed_problem(p, 72, MAP72, seed=11)
+    c = I.random_vector(_space(p).dim, 4)
+    c /= np.linalg.norm(c)
+    g1, g2 = _space(p).rdm(c)
+    h1, h2 = _space(q).rdm(c)
+    m = np.array(MAP72)
+    assert np.abs(h1[np.ix_(m, m)] - g1).max() <= 1e-13
+    assert np.abs(h2[np.ix_(m, m, m, m)] - g2).max() <= 1e-13
+    assert abs(np.abs(h1).sum() - np.abs(g1).sum()) <= 1e-12
+    assert abs(np.abs(h2).sum() - np.abs(g2).sum()) <= 1e-10
