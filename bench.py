@@ -465,7 +465,8 @@ def _leg(a, ctx, sp, prob, c, out, info):
         t_mf = sum(mf.values()) / 1e3
         noise = torch.tensor(I.guess_noise(sp.dim), device="cuda:0")
         res = {}
-        for prod, name in ((sqd.PRODUCT_STORED, "stored"), (sqd.PRODUCT_MATRIX_FREE, "matrix_free")):
+        for prod, name in (() if a.no_davidson else ((sqd.PRODUCT_STORED, "stored"),
+                                                     (sqd.PRODUCT_MATRIX_FREE, "matrix_free"))):
             torch.cuda.synchronize()
             t = time.perf_counter()
             E, x, rep = sp.davidson(tol=1e-8, noise=noise, product=prod)
@@ -479,7 +480,8 @@ def _leg(a, ctx, sp, prob, c, out, info):
                           "spmv_gb_per_s": stream_bytes / t_spmv / 1e9,
                           "spmv_frac_of_hbm_peak": stream_bytes / t_spmv / (PEAK_HBM_GBS * 1e9),
                           "davidson": res,
-                          "abs_energy_diff_Ha": abs(res["stored"]["energy"] - res["matrix_free"]["energy"])}),
+                          "abs_energy_diff_Ha": (abs(res["stored"]["energy"] - res["matrix_free"]["energy"])
+                                                 if res else None)}),
               flush=True)
         sp.release_hamiltonian()
 

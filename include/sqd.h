@@ -100,7 +100,10 @@ extern "C" {
                                   intermediate of nnz_singles_alpha x nb values and a gather),
                                   2 staged per target row (no intermediate); 0 = auto */
 #define SQD_TUNE_AB_GROUP 7    /* alpha singles per grouped alpha-beta unit: 1,2,4,8 (0 = auto) */
-#define SQD_TUNE_COUNT 8
+#define SQD_TUNE_SS_WINDOW 8   /* same-spin term by windows of source strings (rows of C too
+                                  long for two to fit in LDS): 0 auto, 1 never, 2 always,
+                                  or a window width (multiple of 64, <= 65536; always) */
+#define SQD_TUNE_COUNT 9
 
 typedef struct sqd_ctx sqd_ctx;      /* opaque, library-owned */
 typedef struct sqd_space sqd_space;  /* opaque, library-owned */

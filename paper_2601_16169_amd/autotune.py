@@ -32,14 +32,18 @@ CACHE = os.environ.get("SQD_TUNE_CACHE", os.path.join(os.path.dirname(os.path.ab
 
 Setting = Tuple[int, ...]   # key, value, key, value, ...
 
-SS_KNOBS: List[Setting] = [(sqd.TUNE_SS_ROWS, r, sqd.TUNE_SS_WAVES, w) for r in (1, 2, 4, 8) for w in (4, 8, 16)]
+# rows staged x waves (whole rows), or windows of source strings (for rows too
+# long to stage several whole)
+SS_KNOBS: List[Setting] = ([(sqd.TUNE_SS_WINDOW, 1, sqd.TUNE_SS_ROWS, r, sqd.TUNE_SS_WAVES, w)
+                            for r in (1, 2, 4, 8) for w in (4, 8, 16)]
+                           + [(sqd.TUNE_SS_WINDOW, 2, sqd.TUNE_SS_ROWS, 0, sqd.TUNE_SS_WAVES, 0)])
 AB_KNOBS: List[Setting] = (
     [(sqd.TUNE_AB_VARIANT, 1, sqd.TUNE_AB_GROUP, g, sqd.TUNE_AB_WAVES, w) for g in (1, 2, 4, 8) for w in (4, 8, 16)]
     + [(sqd.TUNE_AB_VARIANT, 2, sqd.TUNE_AB_CHUNK, k, sqd.TUNE_AB_WAVES, w) for k in (1, 2, 4, 8) for w in (8, 16)])
 # the batched solver has no row-staged alpha-beta variant
 AB_KNOBS_BATCHED: List[Setting] = [s for s in AB_KNOBS if s[1] == 1]
 ALL_KEYS = (sqd.TUNE_SS_ROWS, sqd.TUNE_SS_WAVES, sqd.TUNE_AB_VARIANT, sqd.TUNE_AB_GROUP, sqd.TUNE_AB_CHUNK,
-            sqd.TUNE_AB_WAVES)
+            sqd.TUNE_AB_WAVES, sqd.TUNE_SS_WINDOW)
 
 
 def signature(space: "sqd.Space", precision: int) -> str:

@@ -114,12 +114,14 @@ static void space_release_device(sqd_space* sp) {
     sqd_free_spin_tables(&sp->sp[1]);
     sqd_free_spin_tables(&sp->sp[0]);
     void* ptrs[] = {sp->diag, sp->ua, sp->ab_grp, sp->ab_chunk_pair, sp->ab_rev, sp->kh_tile_off, sp->kh_pairs,
-                    sp->kh_map, sp->ab_row_order};
+                    sp->kh_map, sp->ab_row_order, sp->win_P};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     sp->diag = sp->ua = nullptr;
     sp->ab_grp = sp->ab_chunk_pair = sp->ab_rev = sp->kh_tile_off = sp->kh_pairs = sp->kh_map = nullptr;
     sp->ab_row_order = nullptr;
+    sp->win_P = nullptr;
+    sp->win_P_bytes = 0;
     sp->ab_G = 0;
     sp->kh_ntiles = 0;
 }
@@ -196,9 +198,11 @@ int sqd_set_tuning(sqd_ctx* ctx, int key, int value) {
     if (key < 0 || key >= SQD_TUNE_COUNT) return sqd_fail(ctx, SQD_E_INVALID_ARG, "unknown tuning key");
     static const int allowed[SQD_TUNE_COUNT][5] = {
         {0, 1, 2, 4, 8}, {0, 1, 2, 4, 8}, {0, 4, 8, 16, -1}, {0, 4, 8, 16, -1}, {0, 1, 2, -1, -1}, {0, 32, 64, -1, -1},
-        {0, 1, 2, -1, -1}, {0, 1, 2, 4, 8}};
+        {0, 1, 2, -1, -1}, {0, 1, 2, 4, 8}, {0, 1, 2, -1, -1}};
     bool ok = false;
     for (int v : allowed[key]) ok |= (v == value);
+    // same-spin windows: also an explicit window width (a multiple of 64)
+    if (key == SQD_TUNE_SS_WINDOW && value >= 64 && value <= 65536 && value % 64 == 0) ok = true;
     if (!ok) return sqd_fail(ctx, SQD_E_INVALID_ARG, "tuning value not allowed for key " + std::to_string(key));
     ctx->tune[key] = value;
     return SQD_OK;

@@ -52,6 +52,8 @@ struct blk_state {
     double theta[KB];
     double rnorm[KB];
     double h[MM];          // Gram-Schmidt coefficients of the vector being orthogonalised
+    double P[MM * KB];     // block projection coefficients P[l * KB + j] = V_l . T_j
+    double tn0[KB];        // squared norms of the corrections before any projection
     double hw;             // its squared norm before the first pass
     double t1sq;           // after the first pass
     double scale;          // 1 / predicted norm after the second pass
@@ -113,12 +115,15 @@ __global__ void __launch_bounds__(kThreads) k_bstart(double* __restrict__ T, int
             T[(int64_t)j * n + i] = (i == st->kmin[j] ? 1.0 : 0.0) + start_noise((uint64_t)j + 1, i, n);
 }
 
-// ---------------------------------------------------------------- Gram-Schmidt of one vector t against V[0..m)
-// pass 1 partials: V^T t (rows < m), |t|^2 (column NR)
+// ---------------------------------------------------------------- Gram-Schmidt of one vector t against V[m_lo..m)
+// (m = st->m; the rows below m_lo were projected out already, as a block)
+// pass 1 partials: V^T t (rows m_lo..m-1), |t|^2 (column NR)
 __global__ void __launch_bounds__(kThreads) k_bo1(const double* __restrict__ V, const double* __restrict__ t,
-                                                  int64_t n, const blk_state* st, double* __restrict__ partial) {
-    const int m = st->m;
-    with_rows<MM>(m, [&](auto nr) {
+                                                  int64_t n, const blk_state* st, int m_lo,
+                                                  double* __restrict__ partial) {
+    const int cnt = st->m - m_lo;
+    const double* Vb = V + (int64_t)m_lo * n;
+    with_rows<MM>(cnt, [&](auto nr) {
         constexpr int NR = decltype(nr)::value;
         double acc[NR + 1];
 #pragma unroll
@@ -127,48 +132,53 @@ __global__ void __launch_bounds__(kThreads) k_bo1(const double* __restrict__ V, 
             const double x = t[i];
             double v[NR];
 #pragma unroll
-            for (int l = 0; l < NR; ++l) v[l] = row_ptr(V, l, m, n)[i];
+            for (int l = 0; l < NR; ++l) v[l] = row_ptr(Vb, l, cnt, n)[i];
 #pragma unroll
-            for (int l = 0; l < NR; ++l) acc[l] += (l < m ? v[l] : 0.0) * x;
+            for (int l = 0; l < NR; ++l) acc[l] += (l < cnt ? v[l] : 0.0) * x;
             acc[NR] += x * x;
         }
         block_to_partial<NR + 1>(acc, partial, blockIdx.x, gridDim.x);
     });
 }
 
-__global__ void __launch_bounds__(kThreads) k_bo1_fin(const double* __restrict__ partial, int nrows, blk_state* st) {
-    const int m = st->m;
-    with_rows<MM>(m, [&](auto nr) {
+// coefficients of pass 1; the reference squared norm for the acceptance test
+// is the vector's own (ref < 0) or st->tn0[ref], its norm before the block
+// projection
+__global__ void __launch_bounds__(kThreads) k_bo1_fin(const double* __restrict__ partial, int nrows, blk_state* st,
+                                                      int m_lo, int ref) {
+    const int cnt = st->m - m_lo;
+    with_rows<MM>(cnt, [&](auto nr) {
         constexpr int NR = decltype(nr)::value;
         __shared__ double out[MM + 1];
         reduce_rows<NR + 1>(partial, nrows, out);
-        for (int l = threadIdx.x; l < MM; l += kThreads) st->h[l] = l < m ? out[l] : 0.0;
-        if (threadIdx.x == 0) st->hw = out[NR];
+        for (int l = threadIdx.x; l < MM; l += kThreads) st->h[l] = l < cnt ? out[l] : 0.0;
+        if (threadIdx.x == 0) st->hw = ref >= 0 ? st->tn0[ref] : out[NR];
     });
 }
 
 // t1 = t - V h (in place); pass 2 partials: V^T t1, |t1|^2
 __global__ void __launch_bounds__(kThreads) k_bo2(const double* __restrict__ V, double* __restrict__ t, int64_t n,
-                                                  const blk_state* st, double* __restrict__ partial) {
-    const int m = st->m;
-    with_rows<MM>(m, [&](auto nr) {
+                                                  const blk_state* st, int m_lo, double* __restrict__ partial) {
+    const int cnt = st->m - m_lo;
+    const double* Vb = V + (int64_t)m_lo * n;
+    with_rows<MM>(cnt, [&](auto nr) {
         constexpr int NR = decltype(nr)::value;
         double h[NR];
 #pragma unroll
-        for (int l = 0; l < NR; ++l) h[l] = st->h[l];   // zero past m
+        for (int l = 0; l < NR; ++l) h[l] = st->h[l];   // zero past cnt
         double acc[NR + 1];
 #pragma unroll
         for (int l = 0; l <= NR; ++l) acc[l] = 0.0;
         for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
             double v[NR];
 #pragma unroll
-            for (int l = 0; l < NR; ++l) v[l] = row_ptr(V, l, m, n)[i];
+            for (int l = 0; l < NR; ++l) v[l] = row_ptr(Vb, l, cnt, n)[i];
             double x = t[i];
 #pragma unroll
-            for (int l = 0; l < NR; ++l) x -= h[l] * (l < m ? v[l] : 0.0);
+            for (int l = 0; l < NR; ++l) x -= h[l] * (l < cnt ? v[l] : 0.0);
             t[i] = x;
 #pragma unroll
-            for (int l = 0; l < NR; ++l) acc[l] += (l < m ? v[l] : 0.0) * x;
+            for (int l = 0; l < NR; ++l) acc[l] += (l < cnt ? v[l] : 0.0) * x;
             acc[NR] += x * x;
         }
         block_to_partial<NR + 1>(acc, partial, blockIdx.x, gridDim.x);
@@ -176,18 +186,18 @@ __global__ void __launch_bounds__(kThreads) k_bo2(const double* __restrict__ V, 
 }
 
 // second-pass coefficients; the vector is kept when its predicted norm after
-// the second pass is above 1e-6 of its norm before the first
+// the second pass is above 1e-6 of the reference norm
 __global__ void __launch_bounds__(kThreads) k_bo2_fin(const double* __restrict__ partial, int nrows, blk_state* st,
-                                                      int m_cap) {
-    const int m = st->m;
-    with_rows<MM>(m, [&](auto nr) {
+                                                      int m_lo, int m_cap) {
+    const int m = st->m, cnt = m - m_lo;
+    with_rows<MM>(cnt, [&](auto nr) {
         constexpr int NR = decltype(nr)::value;
         __shared__ double out[MM + 1];
         reduce_rows<NR + 1>(partial, nrows, out);
-        for (int l = threadIdx.x; l < MM; l += kThreads) st->h[l] = l < m ? out[l] : 0.0;
+        for (int l = threadIdx.x; l < MM; l += kThreads) st->h[l] = l < cnt ? out[l] : 0.0;
         if (threadIdx.x == 0) {
             double hh = 0.0;
-            for (int l = 0; l < m; ++l) hh += out[l] * out[l];
+            for (int l = 0; l < cnt; ++l) hh += out[l] * out[l];
             const double t1sq = out[NR];
             const double t2sq = t1sq - hh;
             const bool ok = (m < m_cap) && t2sq > 1e-12 * st->hw && t2sq > 0.0;
@@ -200,14 +210,15 @@ __global__ void __launch_bounds__(kThreads) k_bo2_fin(const double* __restrict__
     });
 }
 
-// V[slot] = (t1 - V h2) * scale when accepted
+// V[slot] = (t1 - V[m_lo..slot) h2) * scale when accepted
 __global__ void __launch_bounds__(kThreads) k_bo3(double* __restrict__ V, const double* __restrict__ t, int64_t n,
-                                                  const blk_state* st) {
+                                                  const blk_state* st, int m_lo) {
     if (!st->accept) return;
-    const int m = st->slot;
+    const int slot = st->slot, cnt = slot - m_lo;
     const double sc = st->scale;
-    double* out = V + (int64_t)m * n;
-    with_rows<MM>(m, [&](auto nr) {
+    const double* Vb = V + (int64_t)m_lo * n;
+    double* out = V + (int64_t)slot * n;
+    with_rows<MM>(cnt, [&](auto nr) {
         constexpr int NR = decltype(nr)::value;
         double h[NR];
 #pragma unroll
@@ -215,13 +226,47 @@ __global__ void __launch_bounds__(kThreads) k_bo3(double* __restrict__ V, const 
         for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
             double v[NR];
 #pragma unroll
-            for (int l = 0; l < NR; ++l) v[l] = row_ptr(V, l, m, n)[i];
+            for (int l = 0; l < NR; ++l) v[l] = row_ptr(Vb, l, cnt, n)[i];
             double x = t[i];
 #pragma unroll
-            for (int l = 0; l < NR; ++l) x -= h[l] * (l < m ? v[l] : 0.0);
+            for (int l = 0; l < NR; ++l) x -= h[l] * (l < cnt ? v[l] : 0.0);
             out[i] = x * sc;
         }
     });
+}
+
+// Block projection of the k candidate rows of T against V[0..m): P = V^T T
+// (partials by k_bgcols, stored by k_bpfin), then T -= V P.
+template <int NB>
+__global__ void __launch_bounds__(kThreads) k_bpfin(const double* __restrict__ partial, int nrows, blk_state* st,
+                                                    int l0, int nl, int nc) {
+    __shared__ double out[8 * NB];
+    reduce_rows<8 * NB>(partial, nrows, out);
+    for (int q = threadIdx.x; q < 8 * NB; q += kThreads) {
+        const int a = q / NB, b = q % NB;
+        if (a < nl && b < nc) st->P[(l0 + a) * KB + b] = out[q];
+    }
+}
+
+template <int NK>
+__global__ void __launch_bounds__(kThreads) k_bproj(const double* __restrict__ V, double* __restrict__ T, int64_t n,
+                                                    int m, int nk, const blk_state* st) {
+    __shared__ double Ps[MM * NK];
+    for (int q = threadIdx.x; q < MM * NK; q += kThreads) Ps[q] = st->P[(q / NK) * KB + q % NK];
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+        double x[NK];
+#pragma unroll
+        for (int j = 0; j < NK; ++j) x[j] = j < nk ? T[(int64_t)j * n + i] : 0.0;
+        for (int l = 0; l < m; ++l) {
+            const double v = V[(int64_t)l * n + i];
+#pragma unroll
+            for (int j = 0; j < NK; ++j) x[j] -= Ps[l * NK + j] * v;
+        }
+#pragma unroll
+        for (int j = 0; j < NK; ++j)
+            if (j < nk) T[(int64_t)j * n + i] = x[j];
+    }
 }
 
 // ---------------------------------------------------------------- projected matrix
@@ -397,9 +442,9 @@ __global__ void __launch_bounds__(kThreads) k_bresid(const double* __restrict__ 
     for (int q = threadIdx.x; q < MM * K; q += kThreads) Ys[q] = st->Y[(q / K) * KB + q % K];
     if (threadIdx.x < K) th[threadIdx.x] = st->theta[threadIdx.x];
     __syncthreads();
-    double acc[K];
+    double acc[2 * K];
 #pragma unroll
-    for (int j = 0; j < K; ++j) acc[j] = 0.0;
+    for (int j = 0; j < 2 * K; ++j) acc[j] = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
         double x[K], ax[K];
 #pragma unroll
@@ -419,17 +464,22 @@ __global__ void __launch_bounds__(kThreads) k_bresid(const double* __restrict__ 
             acc[j] += r * r;
             double den = th[j] - d;
             if (fabs(den) < 1e-8) den = den < 0.0 ? -1e-8 : 1e-8;
-            T[(int64_t)j * n + i] = r / den;
+            const double tv = r / den;
+            T[(int64_t)j * n + i] = tv;
+            acc[K + j] += tv * tv;
         }
     }
-    block_to_partial<K>(acc, partial, blockIdx.x, gridDim.x);
+    block_to_partial<2 * K>(acc, partial, blockIdx.x, gridDim.x);
 }
 
 template <int K>
 __global__ void __launch_bounds__(kThreads) k_bresid_fin(const double* __restrict__ partial, int nrows, blk_state* st) {
-    __shared__ double out[K];
-    reduce_rows<K>(partial, nrows, out);
-    if (threadIdx.x < K) st->rnorm[threadIdx.x] = sqrt(out[threadIdx.x]);
+    __shared__ double out[2 * K];
+    reduce_rows<2 * K>(partial, nrows, out);
+    if (threadIdx.x < K) {
+        st->rnorm[threadIdx.x] = sqrt(out[threadIdx.x]);
+        st->tn0[threadIdx.x] = out[K + threadIdx.x];
+    }
 }
 
 // Restart coefficients: Z = [Y, Y_prev] orthonormalised column by column
@@ -720,13 +770,31 @@ int sqd_davidson_block_impl(sqd_ctx* ctx, sqd_space* sp, const sqd_davidson_opts
         return hipMemcpyAsync(hs, st, sizeof(blk_state), hipMemcpyDeviceToHost, s) == hipSuccess &&
                hipStreamSynchronize(s) == hipSuccess;
     };
-    // orthogonalise T row j against the basis and append it when accepted
-    auto orth_append = [&](const double* tj) {
-        hipLaunchKernelGGL(k_bo1, dim3(g), dim3(kThreads), 0, s, V, tj, n, st, part);
-        hipLaunchKernelGGL(k_bo1_fin, dim3(1), dim3(kThreads), 0, s, part, g, st);
-        hipLaunchKernelGGL(k_bo2, dim3(g), dim3(kThreads), 0, s, V, const_cast<double*>(tj), n, st, part);
-        hipLaunchKernelGGL(k_bo2_fin, dim3(1), dim3(kThreads), 0, s, part, g, st, mmax);
-        hipLaunchKernelGGL(k_bo3, dim3(g), dim3(kThreads), 0, s, V, tj, n, st);
+    // orthogonalise T row j against the basis rows m_lo.. (the rows below were
+    // projected out as a block) and append it when accepted
+    auto orth_append = [&](const double* tj, int m_lo, int ref) {
+        hipLaunchKernelGGL(k_bo1, dim3(g), dim3(kThreads), 0, s, V, tj, n, st, m_lo, part);
+        hipLaunchKernelGGL(k_bo1_fin, dim3(1), dim3(kThreads), 0, s, part, g, st, m_lo, ref);
+        hipLaunchKernelGGL(k_bo2, dim3(g), dim3(kThreads), 0, s, V, const_cast<double*>(tj), n, st, m_lo, part);
+        hipLaunchKernelGGL(k_bo2_fin, dim3(1), dim3(kThreads), 0, s, part, g, st, m_lo, mmax);
+        hipLaunchKernelGGL(k_bo3, dim3(g), dim3(kThreads), 0, s, V, tj, n, st, m_lo);
+    };
+    // two block Gram-Schmidt passes of the kk rows of T against V[0..m)
+    auto block_project = [&](int m) {
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int l0 = 0; l0 < m; l0 += kGB) {
+                const int nl = std::min(kGB, m - l0);
+                if (kk <= 4) {
+                    hipLaunchKernelGGL((k_bgcols<4>), dim3(g), dim3(kThreads), 0, s, V, T, n, l0, nl, 0, kk, part);
+                    hipLaunchKernelGGL((k_bpfin<4>), dim3(1), dim3(kThreads), 0, s, part, g, st, l0, nl, kk);
+                } else {
+                    hipLaunchKernelGGL((k_bgcols<8>), dim3(g), dim3(kThreads), 0, s, V, T, n, l0, nl, 0, kk, part);
+                    hipLaunchKernelGGL((k_bpfin<8>), dim3(1), dim3(kThreads), 0, s, part, g, st, l0, nl, kk);
+                }
+            }
+            if (kk <= 4) hipLaunchKernelGGL((k_bproj<4>), dim3(g), dim3(kThreads), 0, s, V, T, n, m, kk, st);
+            else hipLaunchKernelGGL((k_bproj<8>), dim3(g), dim3(kThreads), 0, s, V, T, n, m, kk, st);
+        }
     };
     // products of the basis rows [m0, m1) and G's columns m0..m1-1 against rows [0, m1)
     auto products = [&](int m0, int m1, int prec) -> int {
@@ -762,7 +830,7 @@ int sqd_davidson_block_impl(sqd_ctx* ctx, sqd_space* sp, const sqd_davidson_opts
         hipLaunchKernelGGL(k_bargmin_fin, dim3(1), dim3(64), 0, s, part, g, st, j);
     }
     hipLaunchKernelGGL(k_bstart, dim3(g), dim3(kThreads), 0, s, T, n, st, k);
-    for (int j = 0; j < k; ++j) orth_append(T + (int64_t)j * n);
+    for (int j = 0; j < k; ++j) orth_append(T + (int64_t)j * n, 0, -1);
     if (!sync_state()) return fail(SQD_E_HIP, "block Davidson start failed");
     if (hs->m < k) return fail(SQD_E_STATE, "block Davidson start vectors are linearly dependent");
     const bool mixed = o->mode == SQD_DAV_MIXED;
@@ -828,9 +896,11 @@ int sqd_davidson_block_impl(sqd_ctx* ctx, sqd_space* sp, const sqd_davidson_opts
             if (!sync_state()) return fail(SQD_E_HIP, "block Davidson restart failed");
             m = hs->m;
         }
-        // one correction per unconverged root
+        // one correction per unconverged root: projected against the current
+        // basis as a block, then against each other one by one
+        block_project(m);
         for (int j = 0; j < k; ++j)
-            if (!(hs->rnorm[j] <= o->tol) || prec == SQD_FP32) orth_append(T + (int64_t)j * n);
+            if (!(hs->rnorm[j] <= o->tol) || prec == SQD_FP32) orth_append(T + (int64_t)j * n, m, j);
         if (!sync_state()) return fail(SQD_E_HIP, "block Davidson expansion failed");
         const int m1 = hs->m;
         if (m1 == m) { status = DONE_STALLED; break; }

@@ -110,6 +110,9 @@ k_ab_kh(const T* __restrict__ C, T* __restrict__ Y, int64_t na, int64_t nb, cons
                     vv[u] = (pr >= 0 && kk < kn) ? V[(int64_t)pr * n2 + tp[kc + kk]] : (T)0;
                 }
             };
+            // one 16-wide MFMA column block when this pass has at most 16
+            // singles (uniform over the workgroup)
+            const bool two = ne > 16;
             typename M::acc_t acc0 = M::zero(), acc1 = M::zero();
             if (KT > 0) load(0);
             for (int kc = 0; kc < KT; kc += kKC) {
@@ -134,12 +137,20 @@ k_ab_kh(const T* __restrict__ C, T* __restrict__ Y, int64_t na, int64_t nb, cons
                 __syncthreads();
                 if (kc + kKC < KT) load(kc + kKC);
                 const int ks_end = (kn + 3) & ~3;
-                for (int ks = 0; ks < ks_end; ks += 4) {
-                    const T a = Dk[(w * 16 + (lane & 15)) * (kKC + 1) + ks + (lane >> 4)];
-                    const T b0 = Vk[(ks + (lane >> 4)) * (kNE + 1) + (lane & 15)];
-                    const T b1 = Vk[(ks + (lane >> 4)) * (kNE + 1) + 16 + (lane & 15)];
-                    acc0 = M::op(a, b0, acc0);
-                    acc1 = M::op(a, b1, acc1);
+                if (two) {
+                    for (int ks = 0; ks < ks_end; ks += 4) {
+                        const T a = Dk[(w * 16 + (lane & 15)) * (kKC + 1) + ks + (lane >> 4)];
+                        const T b0 = Vk[(ks + (lane >> 4)) * (kNE + 1) + (lane & 15)];
+                        const T b1 = Vk[(ks + (lane >> 4)) * (kNE + 1) + 16 + (lane & 15)];
+                        acc0 = M::op(a, b0, acc0);
+                        acc1 = M::op(a, b1, acc1);
+                    }
+                } else {
+                    for (int ks = 0; ks < ks_end; ks += 4) {
+                        const T a = Dk[(w * 16 + (lane & 15)) * (kKC + 1) + ks + (lane >> 4)];
+                        const T b0 = Vk[(ks + (lane >> 4)) * (kNE + 1) + (lane & 15)];
+                        acc0 = M::op(a, b0, acc0);
+                    }
                 }
             }
             // Y[rev(e)][jb'] = s_e * G[jb'][e]

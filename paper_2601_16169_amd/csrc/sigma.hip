@@ -281,11 +281,34 @@ int pick_chunk(sqd_ctx* ctx, int64_t nb, int norb, size_t es) {
     return 0;
 }
 
+// The spin_tables that own the arrays of t (an alias of the other spin's
+// tables when both spins have the same strings).
+spin_tables& owner(sqd_space* sp, const spin_tables& t) {
+    if (&t == &sp->sp[1] && t.alias) return sp->sp[0];
+    return const_cast<spin_tables&>(t);
+}
+
+// Windowed same-spin kernel: forced on or off by SQD_TUNE_SS_WINDOW, else used
+// when fewer than two rows fit in one workgroup's LDS (measured on MI355X,
+// 2.56e8-determinant workload, beta-beta term: FP64 one row staged 46.2 ms,
+// windowed 30.5 ms; FP32 two rows staged 15.8 ms, windowed 20.8 ms).
+bool use_window(sqd_ctx* ctx, int64_t nrows, int64_t ncols, int norb, size_t es) {
+    const int mode = ctx->tune[SQD_TUNE_SS_WINDOW];
+    if (mode == 1) return false;
+    if (mode >= 2) return true;
+    if (ctx->tune[SQD_TUNE_SS_ROWS]) return false;
+    const size_t lds2 = ((size_t)(ncols + 1) * 2 + (size_t)norb * norb * 2) * es;
+    return lds2 > (size_t)ctx->max_lds && nrows >= 2;
+}
+
 template <typename T>
-int launch_same_spin(sqd_ctx* ctx, const T* X, T* Y, int64_t nrows, int64_t ncols, const spin_tables& col,
-                     const spin_tables& row, const T* jk, int norb, const double* diag, int accumulate,
-                     const int* skip, const char* timer_name) {
+int launch_same_spin(sqd_ctx* ctx, sqd_space* sp, const T* X, T* Y, int64_t nrows, int64_t ncols,
+                     const spin_tables& col, const spin_tables& row, const T* jk, int norb, const double* diag,
+                     int accumulate, const int* skip, const char* timer_name) {
     const size_t es = sizeof(T);
+    if (!accumulate && use_window(ctx, nrows, ncols, norb, es))
+        return sqd_same_spin_windowed(ctx, sp, owner(sp, col), owner(sp, row), X, Y, nrows, ncols, diag,
+                                      sizeof(T) == 4, skip, timer_name);
     const int R = pick_rows(ctx, nrows, ncols, norb, es);
     if (R == 0) return sqd_fail(ctx, SQD_E_LIMIT, "same-spin row does not fit in LDS (too many strings)");
     const size_t lds = ((size_t)(ncols + 1) * R + (size_t)norb * norb * R) * es;
@@ -502,6 +525,18 @@ int sqd_sigma_auto_path(sqd_ctx* ctx, const sqd_space* sp, int precision) {
 // checked separately, by its size.)
 bool sqd_sigma_prepared(sqd_ctx* ctx, const sqd_space* sp, int precision, unsigned mask, int ab_path) {
     if (sp->values_version != ctx->ham_version || sp->diag_version != ctx->ham_version) return false;
+    const size_t es0 = precision == SQD_FP64 ? 8 : 4;
+    for (int spin = 0; spin < 2; ++spin) {   // windowed same-spin tables of either spin
+        if (!(mask & (spin == 0 ? SQD_TERM_AA : SQD_TERM_BB))) continue;
+        const spin_tables& col = sp->sp[spin].alias ? sp->sp[0] : sp->sp[spin];
+        const spin_tables& row = sp->sp[1 - spin].alias ? sp->sp[0] : sp->sp[1 - spin];
+        if (use_window(ctx, sp->sp[1 - spin].n, sp->sp[spin].n, sp->norb, es0)) {
+            const int W = sqd_window_count(ctx, sp->sp[spin].n);
+            if (W == 0 || col.win_W != W || col.win_values_version != ctx->ham_version || !row.wg64 ||
+                row.wg_version != ctx->ham_version || (W > 1 && sp->win_P_bytes < sqd_window_scratch_bytes(sp)))
+                return false;
+        }
+    }
     if (!(mask & SQD_TERM_AB)) return true;
     if (ab_path == SQD_AB_AUTO) ab_path = sqd_sigma_auto_path(ctx, sp, precision);
     if (ab_path == SQD_AB_KH) return sp->kh_map != nullptr && sp->ab_rev != nullptr;
@@ -560,7 +595,7 @@ int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma, 
         // back through a coalesced transpose that adds
         bool written = false;
         if (mask & SQD_TERM_BB) {
-            if ((rc = launch_same_spin<double>(ctx, c, sigma, na, nb, B, A, ctx->jk64, norb, diag, 0, skip,
+            if ((rc = launch_same_spin<double>(ctx, sp, c, sigma, na, nb, B, A, ctx->jk64, norb, diag, 0, skip,
                                                "k_same_spin<double>[bb]")))
                 return rc;
             written = true;
@@ -574,7 +609,7 @@ int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma, 
                 hipLaunchKernelGGL((k_transpose<double, double, false>), tgrid, dim3(256), 0, ctx->stream, c, Ct, na,
                                    nb, skip);
             }
-            if ((rc = launch_same_spin<double>(ctx, Ct, Yt, nb, na, A, B, ctx->jk64, norb, nullptr, 0, skip,
+            if ((rc = launch_same_spin<double>(ctx, sp, Ct, Yt, nb, na, A, B, ctx->jk64, norb, nullptr, 0, skip,
                                                "k_same_spin<double>[aa]"))) return rc;
             {
                 prof_scope pt(ctx, "k_transpose<double>");
@@ -617,7 +652,7 @@ int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma, 
     }
     bool written = false;
     if (mask & SQD_TERM_BB) {
-        if ((rc = launch_same_spin<float>(ctx, Cin, S32, na, nb, B, A, ctx->jk32, norb, nullptr, 0, skip,
+        if ((rc = launch_same_spin<float>(ctx, sp, Cin, S32, na, nb, B, A, ctx->jk32, norb, nullptr, 0, skip,
                                           "k_same_spin<float>[bb]")))
             return rc;
         written = true;
@@ -628,7 +663,7 @@ int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma, 
             hipLaunchKernelGGL((k_transpose<float, float, false>), tgrid, dim3(256), 0, ctx->stream, Cin, Ct32, na, nb,
                                skip);
         }
-        if ((rc = launch_same_spin<float>(ctx, Ct32, Yt32, nb, na, A, B, ctx->jk32, norb, nullptr, 0, skip,
+        if ((rc = launch_same_spin<float>(ctx, sp, Ct32, Yt32, nb, na, A, B, ctx->jk32, norb, nullptr, 0, skip,
                                               "k_same_spin<float>[aa]"))) return rc;
         {
             prof_scope pt(ctx, "k_transpose<float>");

@@ -26,7 +26,7 @@ struct sqd_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     std::string err;
-    int tune[SQD_TUNE_COUNT] = {0, 0, 0, 0, 0, 0, 0};
+    int tune[SQD_TUNE_COUNT] = {};
     int max_lds = 65536;          // bytes of LDS a workgroup may allocate
     int num_cu = 256;
     // Hamiltonian
@@ -130,6 +130,24 @@ struct spin_tables {
     int64_t sell_ss_entries = 0, sell_ab_entries = 0;
     int max_singles = 0, max_doubles = 0;
     bool alias = false;           // arrays owned by the other spin
+    // windowed sliced tables for rows too long to stage whole (window.hip):
+    // the source strings are dealt into win_W interleaved windows (source j in
+    // window j mod W, local index j / W, at most win_width per window); part w
+    // lists, per target in the perm_ss order, the entries of window w
+    int win_W = 0, win_width = 0, win_values_version = -1;
+    int* win_s_off = nullptr;     // win_W * (nslices + 1) slot-column offsets (units of 64)
+    int* win_d_off = nullptr;
+    uint32_t* win_s_pk = nullptr; // local source | pair << 17 | negative << 31
+    int* win_d_nbr = nullptr;     // local source
+    int* win_s_csr = nullptr;     // CSR index of each slot (-1: padding)
+    int* win_d_csr = nullptr;
+    double* win_s_v64 = nullptr; float* win_s_v32 = nullptr;
+    double* win_d_v64 = nullptr; float* win_d_v32 = nullptr;
+    int64_t win_bytes = 0;
+    // cross-spin table of these strings as the row spin: wg[s * norb^2 + pq] =
+    // sum_{k in s} (pq|kk) (FP64 and FP32), per Hamiltonian version
+    double* wg64 = nullptr; float* wg32 = nullptr;
+    int wg_version = -1;
 };
 
 struct sqd_space {
@@ -168,6 +186,9 @@ struct sqd_space {
     int64_t h_nnz = 0;
     int64_t h_bytes = 0;
     int h_version = -1;
+    // partial sums of the windowed same-spin kernel (rows x slots, FP64-sized)
+    void* win_P = nullptr;
+    size_t win_P_bytes = 0;
 };
 
 // ---- helpers (api.hip) ----
@@ -205,6 +226,17 @@ int sqd_ensure_ab_groups(sqd_ctx* ctx, sqd_space* sp, int G);
 size_t sqd_kh_bytes(const sqd_space* sp, size_t es);
 int sqd_sigma_ab_kh(sqd_ctx* ctx, sqd_space* sp, const void* c, void* sigma, void* y, int fp32,
                     const int* skip_flag);
+
+// ---- window.hip ----
+// Same-spin term for rows too long to stage whole: X (nrows x ncols) times the
+// column spin's tables, by windows of source strings; Y written (no
+// accumulation).  col / row: the owning spin_tables of the column and row spins.
+int sqd_same_spin_windowed(sqd_ctx* ctx, sqd_space* sp, spin_tables& col, spin_tables& row, const void* X, void* Y,
+                           int64_t nrows, int64_t ncols, const double* diag, int fp32, const int* skip,
+                           const char* timer);
+void sqd_free_window_tables(spin_tables* t);
+int sqd_window_count(sqd_ctx* ctx, int64_t ncols);    // 0: a window does not fit
+size_t sqd_window_scratch_bytes(const sqd_space* sp);
 
 // ---- stored.hip ----
 int sqd_store_h_impl(sqd_ctx* ctx, sqd_space* sp, int64_t* nnz_out);

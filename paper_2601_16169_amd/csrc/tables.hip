@@ -660,6 +660,7 @@ int sqd_build_values(sqd_ctx* ctx, sqd_space* sp) {
 
 void sqd_free_spin_tables(spin_tables* t) {
     if (t->alias) { *t = spin_tables(); return; }
+    sqd_free_window_tables(t);
     void* ptrs[] = {t->str, t->s_off, t->s_ent, t->d_off, t->d_ent, t->s_pk, t->d_nbr, t->s_val64, t->s_val32,
                     t->d_val64, t->d_val32, t->e_same, t->perm_ss, t->sl_s_off, t->sl_d_off, t->sell_s_pk,
                     t->sell_s_v64, t->sell_s_v32, t->sell_d_nbr, t->sell_d_v64, t->sell_d_v32, t->perm_ab,

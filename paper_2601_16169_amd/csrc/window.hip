@@ -1,0 +1,418 @@
+// Same-spin term (Sec. IV: the alpha-alpha and beta-beta task types) for rows
+// too long to stage several whole in LDS.
+//
+// The row-staged kernel (sigma_body.h) keeps R rows of C in LDS and walks the
+// column spin's whole sliced table once per row block; when a row alone fills
+// the LDS (R = 1), every row streams the whole table through the caches.
+// Here the source strings of the column spin are dealt into W interleaved
+// windows (window w: the sources j with j mod W = w, local index j / W): a
+// workgroup stages R rows x one window of C and walks that window's part of
+// the table, for all windows in turn, so the table is streamed once per R
+// rows.  Every window's part keeps the targets in the order of the whole
+// sliced table (rows sorted by total length), so a lane owns the same targets
+// in every window; interleaving spreads each target's sources evenly over the
+// windows, which keeps the 64-lane slices of every part nearly as tight as
+// the whole table's.  A lane's partial sums go to a scratch row in slot order
+// (coalesced, read back by the same lane in the next window) and the last
+// window adds the diagonal and writes the target.  The cross-spin part of the
+// singles comes from a per-string table wg[s][pq] = sum_{k in s} (pq|kk) of
+// the row spin (global memory) instead of an LDS copy per row.
+#include <algorithm>
+#include <numeric>
+
+#include "sqd_internal.h"
+
+#include "sigma_body.h"
+
+namespace {
+
+inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+// wg[s * norb2 + pq] = sum over occupied k of s (ascending) of jk[k * norb2 + pq]
+__global__ void k_wtable(const uint64_t* __restrict__ str, int nw, int64_t n, int norb, const double* __restrict__ jk,
+                         double* __restrict__ w64, float* __restrict__ w32) {
+    const int norb2 = norb * norb;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n * norb2) return;
+    const int64_t s = idx / norb2;
+    const int pq = (int)(idx - s * norb2);
+    double acc = 0.0;
+    str_for_each(str + s * nw, nw, [&](int k) { acc += jk[(int64_t)k * norb2 + pq]; });
+    w64[idx] = acc;
+    w32[idx] = (float)acc;
+}
+
+template <typename T>
+__global__ void k_win_values(const int* __restrict__ csr, int64_t m, const T* __restrict__ v, T* __restrict__ out) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m) return;
+    const int src = csr[k];
+    out[k] = (src >= 0) ? v[src] : (T)0;
+}
+
+template <typename T>
+struct win_args {
+    const T* X;                 // nrows x ncols
+    T* Y;
+    T* P;                       // partial sums: nrows x (nslices * 64), slot order
+    int64_t nrows, ncols;
+    int W, width, nslices;
+    const int* perm;            // nslices * 64: target of each slot (n = padding)
+    const int* s_off;           // W x (nslices + 1)
+    const int* d_off;
+    const uint32_t* s_pk;
+    const T* s_val;
+    const int* d_nbr;
+    const T* d_val;
+    const T* wg;                // row spin: nrows x norb2
+    const double* diag;         // fused DIAG term (or null)
+    int norb;
+};
+
+// One workgroup per block of R rows; windows in turn.  LDS: xs[(width + 1) * R]
+// in the lds_cols<T, R> layout (column width is the zero slot).
+template <typename T, int R>
+__global__ void __launch_bounds__(1024) k_same_spin_win(win_args<T> a, const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    T* xs = reinterpret_cast<T*>(lds_raw);
+    using L = lds_cols<T, R>;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int wave = tid >> 6, lane = tid & 63, nw = nthr >> 6;
+    const int64_t row0 = (int64_t)blockIdx.x * R;
+    const int norb2 = a.norb * a.norb;
+    const int64_t ldp = (int64_t)a.nslices * 64;
+    for (int w = 0; w < a.W; ++w) {
+        // sources w, w + W, w + 2W, ... as local columns 0, 1, 2, ...
+        const int len = (int)((a.ncols - w + a.W - 1) / a.W);
+        __syncthreads();   // the previous window is done with xs
+        for (int c = tid; c <= a.width; c += nthr) {
+            T v[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int64_t row = row0 + r;
+                v[r] = (c < len && row < a.nrows) ? a.X[row * a.ncols + w + (int64_t)c * a.W] : (T)0;
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) xs[L::idx(c, r)] = v[r];
+        }
+        __syncthreads();
+        const int* so = a.s_off + (int64_t)w * (a.nslices + 1);
+        const int* dof = a.d_off + (int64_t)w * (a.nslices + 1);
+        for (int sl = wave; sl < a.nslices; sl += nw) {
+            T acc[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r] = (T)0;
+            const int s0 = so[sl], s1 = so[sl + 1];
+            for (int k = s0; k < s1; ++k) {
+                const uint32_t e = a.s_pk[(int64_t)k * 64 + lane];
+                const T v = a.s_val[(int64_t)k * 64 + lane];
+                const int nbr = (int)(e & SQD_NBR_MASK);
+                const int pair = (int)((e >> SQD_PAIR_SHIFT) & SQD_PAIR_MASK);
+                const bool neg = (e >> 31) != 0;
+                T xr[R];
+                L::load(xs, nbr, xr);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int64_t row = row0 + r < a.nrows ? row0 + r : a.nrows - 1;
+                    const T wv = a.wg[row * norb2 + pair];
+                    acc[r] += (v + (neg ? -wv : wv)) * xr[r];
+                }
+            }
+            const int d0 = dof[sl], d1 = dof[sl + 1];
+            int k = d0;
+            constexpr int kD = 8;
+            for (; k + kD <= d1; k += kD) {   // eight table entries in flight
+                int nb8[kD];
+                T v8[kD];
+#pragma unroll
+                for (int u = 0; u < kD; ++u) {
+                    nb8[u] = a.d_nbr[(int64_t)(k + u) * 64 + lane];
+                    v8[u] = a.d_val[(int64_t)(k + u) * 64 + lane];
+                }
+#pragma unroll
+                for (int u = 0; u < kD; ++u) {
+                    T xr[R];
+                    L::load(xs, nb8[u], xr);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) acc[r] += v8[u] * xr[r];
+                }
+            }
+            for (; k < d1; ++k) {
+                const int nb1 = a.d_nbr[(int64_t)k * 64 + lane];
+                const T v1 = a.d_val[(int64_t)k * 64 + lane];
+                T xr[R];
+                L::load(xs, nb1, xr);
+#pragma unroll
+                for (int r = 0; r < R; ++r) acc[r] += v1 * xr[r];
+            }
+            // the lane keeps its slot in every window: partial sums in slot
+            // order (its own earlier writes, read back in program order);
+            // the last window writes the target with the diagonal
+            const int64_t slot = (int64_t)sl * 64 + lane;
+            const int t = a.perm[slot];
+            const bool last = (w == a.W - 1);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int64_t row = row0 + r;
+                if (row >= a.nrows) continue;
+                T val = acc[r];
+                if (w > 0) val += a.P[row * ldp + slot];
+                if (!last) {
+                    a.P[row * ldp + slot] = val;
+                } else if (t < a.ncols) {
+                    const int64_t o = row * a.ncols + t;
+                    if (a.diag) val += (T)(a.diag[o] * (double)a.X[o]);
+                    a.Y[o] = val;
+                }
+            }
+        }
+    }
+}
+
+// Build the windowed tables of spin t for W interleaved windows (host pass
+// over the canonical CSR, which lists for every string its in-set
+// neighbours); targets in the order of the whole sliced table (perm_ss).
+int build_window_tables(sqd_ctx* ctx, sqd_space* sp, spin_tables& t, int W) {
+    sqd_free_window_tables(&t);
+    const int64_t n = t.n;
+    const int ns = t.nslices;
+    const int width = (int)((n + W - 1) / W);
+    std::vector<int> soff(n + 1), doff(n + 1), dnbr(t.nnz_d > 0 ? t.nnz_d : 1), perm((size_t)ns * 64);
+    std::vector<uint32_t> spk(t.nnz_s > 0 ? t.nnz_s : 1);
+    SQD_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    SQD_HIP(ctx, hipMemcpy(soff.data(), t.s_off, sizeof(int) * (n + 1), hipMemcpyDeviceToHost));
+    SQD_HIP(ctx, hipMemcpy(doff.data(), t.d_off, sizeof(int) * (n + 1), hipMemcpyDeviceToHost));
+    SQD_HIP(ctx, hipMemcpy(perm.data(), t.perm_ss, sizeof(int) * perm.size(), hipMemcpyDeviceToHost));
+    if (t.nnz_s > 0) SQD_HIP(ctx, hipMemcpy(spk.data(), t.s_pk, sizeof(uint32_t) * t.nnz_s, hipMemcpyDeviceToHost));
+    if (t.nnz_d > 0) SQD_HIP(ctx, hipMemcpy(dnbr.data(), t.d_nbr, sizeof(int) * t.nnz_d, hipMemcpyDeviceToHost));
+    // per (window, target) entry counts, then slice widths per window
+    std::vector<int> cs((size_t)W * n, 0), cd((size_t)W * n, 0);
+    for (int64_t r = 0; r < n; ++r) {
+        for (int e = soff[r]; e < soff[r + 1]; ++e) cs[(size_t)((spk[e] & SQD_NBR_MASK) % W) * n + r] += 1;
+        for (int e = doff[r]; e < doff[r + 1]; ++e) cd[(size_t)(dnbr[e] % W) * n + r] += 1;
+    }
+    std::vector<int> so((size_t)W * (ns + 1)), dof((size_t)W * (ns + 1));
+    int64_t tot_s = 0, tot_d = 0;
+    for (int w = 0; w < W; ++w) {
+        so[(size_t)w * (ns + 1)] = (int)tot_s;
+        dof[(size_t)w * (ns + 1)] = (int)tot_d;
+        for (int sl = 0; sl < ns; ++sl) {
+            int ms = 0, md = 0;
+            for (int l = 0; l < 64; ++l) {
+                const int tg = perm[(size_t)sl * 64 + l];
+                if (tg < n) {
+                    ms = std::max(ms, cs[(size_t)w * n + tg]);
+                    md = std::max(md, cd[(size_t)w * n + tg]);
+                }
+            }
+            tot_s += ms;
+            tot_d += md;
+            so[(size_t)w * (ns + 1) + sl + 1] = (int)tot_s;
+            dof[(size_t)w * (ns + 1) + sl + 1] = (int)tot_d;
+        }
+    }
+    if ((tot_s + tot_d) * 64 >= (1LL << 31)) return sqd_fail(ctx, SQD_E_LIMIT, "windowed table exceeds 2^31 slots");
+    // slots: a target's entries of window w in CSR order; padding points at
+    // the zero column (local index width)
+    std::vector<uint32_t> hs_pk((size_t)tot_s * 64 + 1);
+    std::vector<int> hs_csr((size_t)tot_s * 64 + 1, -1), hd_nbr((size_t)tot_d * 64 + 1), hd_csr((size_t)tot_d * 64 + 1, -1);
+    for (int w = 0; w < W; ++w)
+        for (int sl = 0; sl < ns; ++sl) {
+            const int sb = so[(size_t)w * (ns + 1) + sl], se = so[(size_t)w * (ns + 1) + sl + 1];
+            const int db = dof[(size_t)w * (ns + 1) + sl], de = dof[(size_t)w * (ns + 1) + sl + 1];
+            for (int l = 0; l < 64; ++l) {
+                const int tg = perm[(size_t)sl * 64 + l];
+                int col = sb;
+                if (tg < n)
+                    for (int e = soff[tg]; e < soff[tg + 1]; ++e) {
+                        const uint32_t src = spk[e] & SQD_NBR_MASK;
+                        if ((int)(src % W) != w) continue;
+                        hs_pk[(size_t)col * 64 + l] = (src / W) | (spk[e] & ~SQD_NBR_MASK);
+                        hs_csr[(size_t)col * 64 + l] = e;
+                        ++col;
+                    }
+                for (; col < se; ++col) hs_pk[(size_t)col * 64 + l] = (uint32_t)width;
+                col = db;
+                if (tg < n)
+                    for (int e = doff[tg]; e < doff[tg + 1]; ++e) {
+                        const int src = dnbr[e];
+                        if (src % W != w) continue;
+                        hd_nbr[(size_t)col * 64 + l] = src / W;
+                        hd_csr[(size_t)col * 64 + l] = e;
+                        ++col;
+                    }
+                for (; col < de; ++col) hd_nbr[(size_t)col * 64 + l] = width;
+            }
+        }
+    int rc;
+    int64_t bytes = 0;
+    const size_t S = (size_t)tot_s * 64 + 1, D = (size_t)tot_d * 64 + 1;
+    if ((rc = sqd_alloc(ctx, (void**)&t.win_s_off, sizeof(int) * so.size(), &bytes)) ||
+        (rc = sqd_alloc(ctx, (void**)&t.win_d_off, sizeof(int) * dof.size(), &bytes)) ||
+        (rc = sqd_alloc(ctx, (void**)&t.win_s_pk, sizeof(uint32_t) * S, &bytes)) ||
+        (rc = sqd_alloc(ctx, (void**)&t.win_s_csr, sizeof(int) * S, &bytes)) ||
+        (rc = sqd_alloc(ctx, (void**)&t.win_d_nbr, sizeof(int) * D, &bytes)) ||
+        (rc = sqd_alloc(ctx, (void**)&t.win_d_csr, sizeof(int) * D, &bytes)) ||
+        (rc = sqd_alloc(ctx, (void**)&t.win_s_v64, sizeof(double) * S, &bytes)) ||
+        (rc = sqd_alloc(ctx, (void**)&t.win_s_v32, sizeof(float) * S, &bytes)) ||
+        (rc = sqd_alloc(ctx, (void**)&t.win_d_v64, sizeof(double) * D, &bytes)) ||
+        (rc = sqd_alloc(ctx, (void**)&t.win_d_v32, sizeof(float) * D, &bytes))) {
+        sqd_free_window_tables(&t);
+        return rc;
+    }
+    SQD_HIP(ctx, hipMemcpy(t.win_s_off, so.data(), sizeof(int) * so.size(), hipMemcpyHostToDevice));
+    SQD_HIP(ctx, hipMemcpy(t.win_d_off, dof.data(), sizeof(int) * dof.size(), hipMemcpyHostToDevice));
+    SQD_HIP(ctx, hipMemcpy(t.win_s_pk, hs_pk.data(), sizeof(uint32_t) * S, hipMemcpyHostToDevice));
+    SQD_HIP(ctx, hipMemcpy(t.win_s_csr, hs_csr.data(), sizeof(int) * S, hipMemcpyHostToDevice));
+    SQD_HIP(ctx, hipMemcpy(t.win_d_nbr, hd_nbr.data(), sizeof(int) * D, hipMemcpyHostToDevice));
+    SQD_HIP(ctx, hipMemcpy(t.win_d_csr, hd_csr.data(), sizeof(int) * D, hipMemcpyHostToDevice));
+    t.win_W = W;
+    t.win_width = width;
+    t.win_values_version = -1;
+    t.win_bytes = bytes;
+    sp->bytes += bytes;
+    return SQD_OK;
+}
+
+// values of the windowed slots from the canonical CSR values (per Hamiltonian)
+int window_values(sqd_ctx* ctx, spin_tables& t) {
+    if (t.win_values_version == ctx->ham_version) return SQD_OK;
+    int s_cols = 0, d_cols = 0;
+    SQD_HIP(ctx, hipMemcpy(&s_cols, t.win_s_off + (size_t)t.win_W * (t.nslices + 1) - 1, sizeof(int),
+                           hipMemcpyDeviceToHost));
+    SQD_HIP(ctx, hipMemcpy(&d_cols, t.win_d_off + (size_t)t.win_W * (t.nslices + 1) - 1, sizeof(int),
+                           hipMemcpyDeviceToHost));
+    const int64_t S = (int64_t)s_cols * 64, D = (int64_t)d_cols * 64;
+    hipStream_t s = ctx->stream;
+    if (S > 0) {
+        hipLaunchKernelGGL(k_win_values<double>, dim3(nblk(S, 256)), dim3(256), 0, s, t.win_s_csr, S, t.s_val64,
+                           t.win_s_v64);
+        hipLaunchKernelGGL(k_win_values<float>, dim3(nblk(S, 256)), dim3(256), 0, s, t.win_s_csr, S, t.s_val32,
+                           t.win_s_v32);
+    }
+    if (D > 0) {
+        hipLaunchKernelGGL(k_win_values<double>, dim3(nblk(D, 256)), dim3(256), 0, s, t.win_d_csr, D, t.d_val64,
+                           t.win_d_v64);
+        hipLaunchKernelGGL(k_win_values<float>, dim3(nblk(D, 256)), dim3(256), 0, s, t.win_d_csr, D, t.d_val32,
+                           t.win_d_v32);
+    }
+    SQD_HIP(ctx, hipGetLastError());
+    SQD_HIP(ctx, hipStreamSynchronize(s));
+    t.win_values_version = ctx->ham_version;
+    return SQD_OK;
+}
+
+int window_wtable(sqd_ctx* ctx, sqd_space* sp, spin_tables& t) {
+    if (t.wg64 && t.wg_version == ctx->ham_version) return SQD_OK;
+    const int64_t m = t.n * (int64_t)sp->norb * sp->norb;
+    int rc;
+    if (!t.wg64) {
+        int64_t bytes = 0;
+        if ((rc = sqd_alloc(ctx, (void**)&t.wg64, sizeof(double) * (m + 1), &bytes)) ||
+            (rc = sqd_alloc(ctx, (void**)&t.wg32, sizeof(float) * (m + 1), &bytes)))
+            return rc;
+        t.win_bytes += bytes;
+        sp->bytes += bytes;
+    }
+    hipLaunchKernelGGL(k_wtable, dim3(nblk(m, 256)), dim3(256), 0, ctx->stream, t.str, t.nw, t.n, sp->norb,
+                       ctx->jk64, t.wg64, t.wg32);
+    SQD_HIP(ctx, hipGetLastError());
+    t.wg_version = ctx->ham_version;
+    return SQD_OK;
+}
+
+template <typename F>
+void set_lds_attr(F f, int bytes) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(f), hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+template <typename T, int R>
+int launch_win(sqd_ctx* ctx, sqd_space* sp, spin_tables& col, spin_tables& row, const T* X, T* Y, int64_t nrows,
+               int64_t ncols, const double* diag, const int* skip) {
+    const T* sv;
+    const T* dv;
+    const T* wg;
+    if constexpr (sizeof(T) == 8) { sv = (const T*)col.win_s_v64; dv = (const T*)col.win_d_v64; wg = (const T*)row.wg64; }
+    else { sv = (const T*)col.win_s_v32; dv = (const T*)col.win_d_v32; wg = (const T*)row.wg32; }
+    win_args<T> a{X, Y, (T*)sp->win_P, nrows, ncols, col.win_W, col.win_width, col.nslices, col.perm_ss,
+                  col.win_s_off, col.win_d_off, col.win_s_pk, sv, col.win_d_nbr, dv, wg, diag, sp->norb};
+    const size_t lds = (size_t)(col.win_width + 1) * R * sizeof(T);
+    set_lds_attr(k_same_spin_win<T, R>, (int)lds);
+    hipLaunchKernelGGL((k_same_spin_win<T, R>), dim3(nblk(nrows, R)), dim3(1024), lds, ctx->stream, a, skip);
+    SQD_HIP(ctx, hipGetLastError());
+    return SQD_OK;
+}
+
+}  // namespace
+
+// rows staged per windowed workgroup
+constexpr int kWinRows = 8;
+
+void sqd_free_window_tables(spin_tables* t) {
+    void* ptrs[] = {t->win_s_off, t->win_d_off, t->win_s_pk, t->win_d_nbr, t->win_s_csr,
+                    t->win_d_csr, t->win_s_v64, t->win_s_v32, t->win_d_v64, t->win_d_v32, t->wg64, t->wg32};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    t->win_s_off = t->win_d_off = t->win_d_nbr = t->win_s_csr = t->win_d_csr = nullptr;
+    t->win_s_pk = nullptr;
+    t->win_s_v64 = t->win_d_v64 = t->wg64 = nullptr;
+    t->win_s_v32 = t->win_d_v32 = t->wg32 = nullptr;
+    t->win_W = t->win_width = 0;
+    t->win_values_version = t->wg_version = -1;
+    t->win_bytes = 0;
+}
+
+// Windows for rows of ncols strings: the fewest whose R staged FP64 rows fit
+// the LDS of one workgroup (or of the width set by SQD_TUNE_SS_WINDOW).  FP32
+// products use the same windows, so both precisions share one set of tables.
+int sqd_window_count(sqd_ctx* ctx, int64_t ncols) {
+    int64_t wmax = (int64_t)(ctx->max_lds / (sizeof(double) * kWinRows)) - 1;
+    if (ctx->tune[SQD_TUNE_SS_WINDOW] >= 64) wmax = std::min<int64_t>(wmax, ctx->tune[SQD_TUNE_SS_WINDOW]);
+    if (wmax < 64) return 0;
+    return (int)std::max<int64_t>(1, (ncols + wmax - 1) / wmax);
+}
+
+size_t sqd_window_scratch_bytes(const sqd_space* sp) {
+    size_t b = 0;
+    for (int spin = 0; spin < 2; ++spin) {   // rows of one spin x slots of the other
+        const spin_tables& col = sp->sp[spin].alias ? sp->sp[0] : sp->sp[spin];
+        b = std::max(b, (size_t)sp->sp[1 - spin].n * (size_t)col.nslices * 64 * sizeof(double));
+    }
+    return b;
+}
+
+int sqd_same_spin_windowed(sqd_ctx* ctx, sqd_space* sp, spin_tables& col, spin_tables& row, const void* X, void* Y,
+                           int64_t nrows, int64_t ncols, const double* diag, int fp32, const int* skip,
+                           const char* timer) {
+    const int W = sqd_window_count(ctx, ncols);
+    if (W == 0) return sqd_fail(ctx, SQD_E_LIMIT, "same-spin window does not fit in LDS");
+    const bool cap = sqd_capturing(ctx);
+    int rc;
+    if (col.win_W != W) {
+        if (cap) return sqd_fail(ctx, SQD_E_STATE, "windowed tables not built before the capture");
+        if ((rc = build_window_tables(ctx, sp, col, W))) return rc;
+    }
+    if (col.win_values_version != ctx->ham_version || !row.wg64 || row.wg_version != ctx->ham_version) {
+        if (cap) return sqd_fail(ctx, SQD_E_STATE, "windowed values not built before the capture");
+        if ((rc = window_values(ctx, col)) || (rc = window_wtable(ctx, sp, row))) return rc;
+    }
+    // partial sums between windows: one scratch per space, kept
+    const size_t pb = sqd_window_scratch_bytes(sp);
+    if (W > 1 && sp->win_P_bytes < pb) {
+        if (cap) return sqd_fail(ctx, SQD_E_STATE, "windowed scratch not allocated before the capture");
+        SQD_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        if (sp->win_P) {
+            (void)hipFree(sp->win_P);
+            sp->bytes -= (int64_t)sp->win_P_bytes;
+            sp->win_P = nullptr;
+            sp->win_P_bytes = 0;
+        }
+        if ((rc = sqd_alloc(ctx, &sp->win_P, pb, &sp->bytes))) return rc;
+        sp->win_P_bytes = pb;
+    }
+    prof_scope ps(ctx, timer);
+    if (fp32)
+        return launch_win<float, kWinRows>(ctx, sp, col, row, (const float*)X, (float*)Y, nrows, ncols, diag, skip);
+    return launch_win<double, kWinRows>(ctx, sp, col, row, (const double*)X, (double*)Y, nrows, ncols, diag, skip);
+}

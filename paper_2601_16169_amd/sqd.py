@@ -26,7 +26,7 @@ DAV_FP64, DAV_MIXED = 0, 1
 PRODUCT_MATRIX_FREE, PRODUCT_STORED = 0, 1
 SINGLES, DOUBLES = 0, 1
 (TUNE_SS_ROWS, TUNE_AB_CHUNK, TUNE_AB_WAVES, TUNE_SS_WAVES, TUNE_AB_PATH, TUNE_KH_TILE, TUNE_AB_VARIANT,
- TUNE_AB_GROUP) = range(8)
+ TUNE_AB_GROUP, TUNE_SS_WINDOW) = range(9)
 MMAX, HIST = 32, 512
 
 ERRORS = {

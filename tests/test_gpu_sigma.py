@@ -485,3 +485,54 @@ def test_autotune_keeps_results(ctx, tmp_path, monkeypatch):
     assert autotune.tune(sp, precision=sqd.FP64) == json.loads(json.dumps(r))
     autotune.reset(ctx)
     sp.close()
+
+
+@pytest.mark.parametrize("name,make,width", [
+    ("sab_neq_10_4_3", lambda: I.small_problem(10, 4, 3, 70, 97, 4), 64),      # 2 windows each way, ragged
+    ("ragged_8_3_4", lambda: I.small_problem(8, 3, 4, 37, 53, 3), 64),         # one short window
+    ("one_beta_string", lambda: I.small_problem(6, 2, 3, 15, 1, 6), 64),       # fewer rows than staged
+])
+def test_sigma_windowed_same_spin(ctx, name, make, width):
+    """The same-spin term by windows of source strings (the path taken for
+    rows too long to stage whole), forced on small spaces with a narrow
+    window, against the oracle per term: FP64 <= 1e-12, FP32 <= 2e-6."""
+    torch = need_gpu()
+    from paper_2601_16169_amd import sqd
+    banner(f"windowed same-spin {name} width {width}")
+    p = make()
+    sp = _space(ctx, p)
+    osp = core.Space.from_problem(p)
+    c = I.random_vector(sp.dim, 17)
+    ct = torch.tensor(c, device="cuda:0")
+    ctx.set_tuning(sqd.TUNE_SS_WINDOW, width)
+    try:
+        for mask in (TERMS["AA"], TERMS["BB"], TERMS["BB"] | TERMS["DIAG"], TERMS["ALL"]):
+            ref = osp.sigma(c, mask)
+            for prec, bar in ((sqd.FP64, 1e-12), (sqd.FP32, 2e-6)):
+                got = sp.sigma(ct, precision=prec, terms=mask).cpu().numpy()
+                e_inf, e_2 = rel_err(got, ref)
+                assert e_inf <= bar and e_2 <= bar, (mask, prec, e_inf, e_2)
+    finally:
+        ctx.set_tuning(sqd.TUNE_SS_WINDOW, 0)
+    sp.close()
+
+
+def test_sigma_windowed_cfg2_matches_row_staged(ctx):
+    """4.0e6 determinants: windows of 256 source strings (8 windows per row)
+    against the row-staged kernels, FP64 and FP32, all terms."""
+    torch = need_gpu()
+    from paper_2601_16169_amd import sqd
+    banner("windowed same-spin cfg2, width 256")
+    p = I.cfg2()
+    sp = _space(ctx, p)
+    c = torch.tensor(I.random_vector(sp.dim, 23), device="cuda:0")
+    for prec, bar in ((sqd.FP64, 1e-12), (sqd.FP32, 2e-6)):
+        ref = sp.sigma(c, precision=prec).cpu().numpy()
+        ctx.set_tuning(sqd.TUNE_SS_WINDOW, 256)
+        try:
+            got = sp.sigma(c, precision=prec).cpu().numpy()
+        finally:
+            ctx.set_tuning(sqd.TUNE_SS_WINDOW, 0)
+        e_inf, e_2 = rel_err(got, ref)
+        assert e_inf <= bar and e_2 <= bar, (prec, e_inf, e_2)
+    sp.close()

@@ -91,13 +91,16 @@ class FakeCtx:
 def test_autotune_search_keeps_the_fastest_valid_setting():
     from paper_2601_16169_amd import autotune, sqd
     ctx = FakeCtx()
-    # time = rows + waves / 100 (smallest rows first), except rows 2 which is fastest
+    # time = rows + waves / 100 (smallest rows first), except rows 2 which is
+    # fastest; the windowed setting is slower than all of them
     def measure():
+        if ctx.tune.get(sqd.TUNE_SS_WINDOW, 0) == 2:
+            return 99.0
         r, w = ctx.tune.get(sqd.TUNE_SS_ROWS, 0), ctx.tune.get(sqd.TUNE_SS_WAVES, 0)
         return (0.5 if r == 2 else float(r)) + w / 100.0
     res = autotune._search(ctx, (("ss", autotune.SS_KNOBS),), measure, None)
     setting, ms = res["ss"]
-    assert setting == [sqd.TUNE_SS_ROWS, 2, sqd.TUNE_SS_WAVES, 4]
+    assert setting == [sqd.TUNE_SS_WINDOW, 1, sqd.TUNE_SS_ROWS, 2, sqd.TUNE_SS_WAVES, 4]
     assert ms == pytest.approx(0.54)
     # the winner stays applied; reset restores every knob to automatic
     assert ctx.tune[sqd.TUNE_SS_ROWS] == 2 and ctx.tune[sqd.TUNE_SS_WAVES] == 4
