@@ -70,75 +70,119 @@ struct win_args {
 };
 
 // One workgroup per block of R rows; windows in turn.  LDS: xs[(width + 1) * R]
-// in the lds_cols<T, R> layout (column width is the zero slot).
+// in the lds_cols<T, R> layout (column width is the zero slot).  The loop
+// over a slice's entries waits on the table, which streams from beyond the
+// L2, so the partial sums of the earlier windows and the first batch of
+// doubles are loaded before the singles, and each single's successor loads
+// while its cross-spin terms are read (measured on MI355X, 2.56e8-determinant
+// workload, beta-beta FP64: 30.7 -> 27.9 ms; double-buffering the doubles
+// batches as well needs more than the 128 VGPRs of 16 waves per CU).
 template <typename T, int R>
 __global__ void __launch_bounds__(1024) k_same_spin_win(win_args<T> a, const int* __restrict__ skip) {
     if (skip && *skip) return;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T* xs = reinterpret_cast<T*>(lds_raw);
     using L = lds_cols<T, R>;
+    constexpr int kD = 8;   // doubles per batch
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int wave = tid >> 6, lane = tid & 63, nw = nthr >> 6;
     const int64_t row0 = (int64_t)blockIdx.x * R;
     const int norb2 = a.norb * a.norb;
     const int64_t ldp = (int64_t)a.nslices * 64;
+    // rows past the end read the last row (their results are not stored)
+    auto rowc = [&](int r) -> int64_t { return row0 + r < a.nrows ? row0 + r : a.nrows - 1; };
     for (int w = 0; w < a.W; ++w) {
         // sources w, w + W, w + 2W, ... as local columns 0, 1, 2, ...
         const int len = (int)((a.ncols - w + a.W - 1) / a.W);
         __syncthreads();   // the previous window is done with xs
-        for (int c = tid; c <= a.width; c += nthr) {
-            T v[R];
+        for (int c0 = tid; c0 <= a.width; c0 += 2 * nthr) {
+            T v[2][R];
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int64_t row = row0 + r;
-                v[r] = (c < len && row < a.nrows) ? a.X[row * a.ncols + w + (int64_t)c * a.W] : (T)0;
+            for (int u = 0; u < 2; ++u) {
+                const int c = c0 + u * nthr;
+                const int cc = c < len ? c : 0;
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[u][r] = a.X[rowc(r) * a.ncols + w + (int64_t)cc * a.W];
             }
 #pragma unroll
-            for (int r = 0; r < R; ++r) xs[L::idx(c, r)] = v[r];
+            for (int u = 0; u < 2; ++u) {
+                const int c = c0 + u * nthr;
+                if (c > a.width) continue;
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    xs[L::idx(c, r)] = (c < len && row0 + r < a.nrows) ? v[u][r] : (T)0;
+            }
         }
         __syncthreads();
         const int* so = a.s_off + (int64_t)w * (a.nslices + 1);
         const int* dof = a.d_off + (int64_t)w * (a.nslices + 1);
+        const bool first = (w == 0), last = (w == a.W - 1);
         for (int sl = wave; sl < a.nslices; sl += nw) {
-            T acc[R];
+            const int64_t slot = (int64_t)sl * 64 + lane;
+            T acc[R], prev[R];
 #pragma unroll
-            for (int r = 0; r < R; ++r) acc[r] = (T)0;
-            const int s0 = so[sl], s1 = so[sl + 1];
-            for (int k = s0; k < s1; ++k) {
-                const uint32_t e = a.s_pk[(int64_t)k * 64 + lane];
-                const T v = a.s_val[(int64_t)k * 64 + lane];
-                const int nbr = (int)(e & SQD_NBR_MASK);
-                const int pair = (int)((e >> SQD_PAIR_SHIFT) & SQD_PAIR_MASK);
-                const bool neg = (e >> 31) != 0;
-                T xr[R];
-                L::load(xs, nbr, xr);
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const int64_t row = row0 + r < a.nrows ? row0 + r : a.nrows - 1;
-                    const T wv = a.wg[row * norb2 + pair];
-                    acc[r] += (v + (neg ? -wv : wv)) * xr[r];
-                }
+            for (int r = 0; r < R; ++r) {
+                acc[r] = (T)0;
+                prev[r] = first ? (T)0 : a.P[rowc(r) * ldp + slot];
             }
             const int d0 = dof[sl], d1 = dof[sl + 1];
-            int k = d0;
-            constexpr int kD = 8;
-            for (; k + kD <= d1; k += kD) {   // eight table entries in flight
-                int nb8[kD];
-                T v8[kD];
+            const int nfull = (d1 - d0) / kD;
+            int nA[kD];
+            T vA[kD];
+            auto load = [&](int k, int (&nb)[kD], T (&v)[kD]) {
+                const int* pn = a.d_nbr + (int64_t)k * 64 + lane;
+                const T* pv = a.d_val + (int64_t)k * 64 + lane;
 #pragma unroll
                 for (int u = 0; u < kD; ++u) {
-                    nb8[u] = a.d_nbr[(int64_t)(k + u) * 64 + lane];
-                    v8[u] = a.d_val[(int64_t)(k + u) * 64 + lane];
+                    nb[u] = pn[u * 64];
+                    v[u] = pv[u * 64];
                 }
+            };
+            auto use = [&](const int (&nb)[kD], const T (&v)[kD]) {
 #pragma unroll
-                for (int u = 0; u < kD; ++u) {
-                    T xr[R];
-                    L::load(xs, nb8[u], xr);
+                for (int u = 0; u < kD; u += 2) {
+                    T x0[R], x1[R];
+                    L::load(xs, nb[u], x0);
+                    L::load(xs, nb[u + 1], x1);
 #pragma unroll
-                    for (int r = 0; r < R; ++r) acc[r] += v8[u] * xr[r];
+                    for (int r = 0; r < R; ++r) acc[r] += v[u] * x0[r];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) acc[r] += v[u + 1] * x1[r];
+                    __builtin_amdgcn_sched_barrier(0);   // two entries' LDS reads at a time
                 }
+            };
+            if (nfull > 0) load(d0, nA, vA);
+            // singles: the next entry loads while the cross-spin terms of
+            // the current one are read
+            const int s0 = so[sl], s1 = so[sl + 1];
+            uint32_t en = 0;
+            T vn = (T)0;
+            if (s0 < s1) {
+                en = a.s_pk[(int64_t)s0 * 64 + lane];
+                vn = a.s_val[(int64_t)s0 * 64 + lane];
             }
-            for (; k < d1; ++k) {
+            for (int k = s0; k < s1; ++k) {
+                const uint32_t e = en;
+                const T v = vn;
+                if (k + 1 < s1) {
+                    en = a.s_pk[(int64_t)(k + 1) * 64 + lane];
+                    vn = a.s_val[(int64_t)(k + 1) * 64 + lane];
+                }
+                const int pair = (int)((e >> SQD_PAIR_SHIFT) & SQD_PAIR_MASK);
+                T wv[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) wv[r] = a.wg[rowc(r) * norb2 + pair];
+                T xr[R];
+                L::load(xs, (int)(e & SQD_NBR_MASK), xr);
+                const bool neg = (e >> 31) != 0;
+#pragma unroll
+                for (int r = 0; r < R; ++r) acc[r] += (v + (neg ? -wv[r] : wv[r])) * xr[r];
+            }
+            for (int b = 0; b < nfull; ++b) {
+                if (b > 0) load(d0 + b * kD, nA, vA);
+                use(nA, vA);
+            }
+            for (int k = d0 + nfull * kD; k < d1; ++k) {
                 const int nb1 = a.d_nbr[(int64_t)k * 64 + lane];
                 const T v1 = a.d_val[(int64_t)k * 64 + lane];
                 T xr[R];
@@ -149,21 +193,17 @@ __global__ void __launch_bounds__(1024) k_same_spin_win(win_args<T> a, const int
             // the lane keeps its slot in every window: partial sums in slot
             // order (its own earlier writes, read back in program order);
             // the last window writes the target with the diagonal
-            const int64_t slot = (int64_t)sl * 64 + lane;
             const int t = a.perm[slot];
-            const bool last = (w == a.W - 1);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int64_t row = row0 + r;
                 if (row >= a.nrows) continue;
-                T val = acc[r];
-                if (w > 0) val += a.P[row * ldp + slot];
+                const T val = acc[r] + prev[r];
                 if (!last) {
                     a.P[row * ldp + slot] = val;
                 } else if (t < a.ncols) {
                     const int64_t o = row * a.ncols + t;
-                    if (a.diag) val += (T)(a.diag[o] * (double)a.X[o]);
-                    a.Y[o] = val;
+                    a.Y[o] = a.diag ? val + (T)(a.diag[o] * (double)a.X[o]) : val;
                 }
             }
         }
