@@ -161,6 +161,8 @@ def main():
                for k, (n, ms) in kern.items()}
     log(f"kernels {kernels}")
     counters = _counters(a.workload)
+    # the alpha-alpha term comes back through transposes only when windowed
+    info["aa_in_place"] = not any(k.startswith("k_transpose") for k in kernels)
     roofline = _roofline(kernels, info, sp, counters)
     kernel_roofs = [_kernel_roofline(k, v, info, sp, counters) for k, v in kernels.items()]
     conn = info["conn_per_sigma"]
@@ -587,7 +589,9 @@ def _algorithmic(name, info, sp):
         aa = name.endswith("[aa]")
         k = 0 if aa else 1
         tables = (4 + es) * (ns[k] + nd[k])
-        vec = 2 * es * dim + (0 if aa else 8 * dim)   # X read, Y written (+ the FP64 diagonal for beta-beta)
+        # X read, Y written (+ the FP64 diagonal for beta-beta; + sigma read
+        # when the row-staged alpha-alpha kernel adds into sigma in place)
+        vec = 2 * es * dim + (es * dim if aa and info.get("aa_in_place") else 0) + (0 if aa else 8 * dim)
         return 2.0 * (t[1] if aa else t[2]), float(vec + tables)
     if name.startswith("k_ab_gather"):
         return 0.0, float(es * (ns[0] * nb + 2 * dim))

@@ -59,6 +59,10 @@ extern "C" int sqd_sigma_noalloc(sqd_ctx* ctx, const sqd_space* spc, const doubl
     }
     if (!buf) return sqd_fail(ctx, SQD_E_STATE, "static product scratch has no device address on this device");
     SQD_HIP(ctx, hipSetDevice(ctx->device));
+    // windowed tables for long same-spin rows are built (allocated) by the
+    // space's first allocating product with that term
+    if (!sqd_space_built_for(ctx, sp, precision, mask))
+        return sqd_fail(ctx, SQD_E_STATE, "windowed same-spin tables not built: call sqd_sigma on this space first");
     // values and diagonal are refreshed in place after a Hamiltonian change
     // (kernels and a synchronisation, no allocation); under capture they must
     // already be current

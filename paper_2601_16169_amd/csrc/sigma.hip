@@ -301,12 +301,14 @@ bool use_window(sqd_ctx* ctx, int64_t nrows, int64_t ncols, int norb, size_t es)
     return lds2 > (size_t)ctx->max_lds && nrows >= 2;
 }
 
+// colmajor: X and Y hold the transposes (the alpha-alpha term read from C and
+// added into sigma directly); only for the row-staged kernel.
 template <typename T>
 int launch_same_spin(sqd_ctx* ctx, sqd_space* sp, const T* X, T* Y, int64_t nrows, int64_t ncols,
                      const spin_tables& col, const spin_tables& row, const T* jk, int norb, const double* diag,
-                     int accumulate, const int* skip, const char* timer_name) {
+                     int accumulate, const int* skip, const char* timer_name, int colmajor = 0) {
     const size_t es = sizeof(T);
-    if (!accumulate && use_window(ctx, nrows, ncols, norb, es))
+    if (!accumulate && !colmajor && use_window(ctx, nrows, ncols, norb, es))
         return sqd_same_spin_windowed(ctx, sp, owner(sp, col), owner(sp, row), X, Y, nrows, ncols, diag,
                                       sizeof(T) == 4, skip, timer_name);
     const int R = pick_rows(ctx, nrows, ncols, norb, es);
@@ -322,7 +324,7 @@ int launch_same_spin(sqd_ctx* ctx, sqd_space* sp, const T* X, T* Y, int64_t nrow
     if constexpr (sizeof(T) == 8) { sv = (const T*)col.sell_s_v64; dv = (const T*)col.sell_d_v64; }
     else { sv = (const T*)col.sell_s_v32; dv = (const T*)col.sell_d_v32; }
     ss_args<T> args{X, Y, nrows, ncols, col.perm_ss, col.nslices, col.sl_s_off, col.sl_d_off, col.sell_s_pk, sv,
-                    col.sell_d_nbr, dv, row.str, row.nw, diag, accumulate};
+                    col.sell_d_nbr, dv, row.str, row.nw, diag, accumulate, colmajor};
     prof_scope ps(ctx, timer_name);
 #define SQD_SS_LAUNCH(RR)                                                                                    \
     case RR:                                                                                                 \
@@ -545,6 +547,27 @@ bool sqd_sigma_prepared(sqd_ctx* ctx, const sqd_space* sp, int precision, unsign
     return sp->ab_grp != nullptr && sp->ab_G == ab_group_size(ctx, sp) && sp->ab_row_order != nullptr;
 }
 
+// True when the arrays that a space's first product builds exist for a
+// product with these arguments: the diagonal, and for same-spin rows too long
+// to stage two whole the windowed tables of the column spin, the cross-spin
+// table of the row spin and the partial-sum scratch.  (Their values may still
+// be stale: those are refreshed in place.)
+bool sqd_space_built_for(sqd_ctx* ctx, const sqd_space* sp, int precision, unsigned mask) {
+    if (!sp->diag || !sp->ua) return false;
+    const size_t es = precision == SQD_FP64 ? 8 : 4;
+    for (int spin = 0; spin < 2; ++spin) {
+        if (!(mask & (spin == 0 ? SQD_TERM_AA : SQD_TERM_BB))) continue;
+        const spin_tables& col = sp->sp[spin].alias ? sp->sp[0] : sp->sp[spin];
+        const spin_tables& row = sp->sp[1 - spin].alias ? sp->sp[0] : sp->sp[1 - spin];
+        if (use_window(ctx, sp->sp[1 - spin].n, sp->sp[spin].n, sp->norb, es)) {
+            const int W = sqd_window_count(ctx, sp->sp[spin].n);
+            if (W == 0 || col.win_W != W || !row.wg64 || (W > 1 && sp->win_P_bytes < sqd_window_scratch_bytes(sp)))
+                return false;
+        }
+    }
+    return true;
+}
+
 // Context scratch (grown on demand): FP64 path 2*dim doubles, FP32 path 4*dim floats.
 static int space_scratch_get(sqd_ctx* ctx, sqd_space* sp, size_t bytes, void** out) {
     (void)sp;
@@ -591,8 +614,9 @@ int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma, 
         double* Yt = Ct + dim + 64;
         double* Yab = Yt + dim + 64;
         // beta-beta (with the diagonal) writes sigma first, so that its
-        // scattered stores need no read of sigma; the alpha-alpha term comes
-        // back through a coalesced transpose that adds
+        // scattered stores need no read of sigma; the alpha-alpha term reads
+        // the columns of C and adds into sigma (row-staged kernel), or comes
+        // back through a coalesced transpose that adds (windowed kernel)
         bool written = false;
         if (mask & SQD_TERM_BB) {
             if ((rc = launch_same_spin<double>(ctx, sp, c, sigma, na, nb, B, A, ctx->jk64, norb, diag, 0, skip,
@@ -603,7 +627,13 @@ int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma, 
             hipLaunchKernelGGL(k_diag_apply, dim3(g), dim3(256), 0, ctx->stream, diag, c, sigma, dim, 0, skip);
             written = true;
         }
-        if (mask & SQD_TERM_AA) {
+        if ((mask & SQD_TERM_AA) && !use_window(ctx, nb, na, norb, 8)) {
+            // row-staged: beta rows read from the columns of C, added into sigma
+            if ((rc = launch_same_spin<double>(ctx, sp, c, sigma, nb, na, A, B, ctx->jk64, norb, nullptr,
+                                               written ? 1 : 0, skip, "k_same_spin<double>[aa]", 1)))
+                return rc;
+            written = true;
+        } else if (mask & SQD_TERM_AA) {
             {
                 prof_scope pt(ctx, "k_transpose<double>");
                 hipLaunchKernelGGL((k_transpose<double, double, false>), tgrid, dim3(256), 0, ctx->stream, c, Ct, na,
@@ -657,7 +687,12 @@ int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma, 
             return rc;
         written = true;
     }
-    if (mask & SQD_TERM_AA) {
+    if ((mask & SQD_TERM_AA) && !use_window(ctx, nb, na, norb, 4)) {
+        if ((rc = launch_same_spin<float>(ctx, sp, Cin, S32, nb, na, A, B, ctx->jk32, norb, nullptr, written ? 1 : 0,
+                                          skip, "k_same_spin<float>[aa]", 1)))
+            return rc;
+        written = true;
+    } else if (mask & SQD_TERM_AA) {
         {
             prof_scope pt(ctx, "k_transpose<float>");
             hipLaunchKernelGGL((k_transpose<float, float, false>), tgrid, dim3(256), 0, ctx->stream, Cin, Ct32, na, nb,

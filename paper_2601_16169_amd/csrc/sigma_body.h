@@ -80,6 +80,42 @@ __device__ __forceinline__ void stage_rows(T* __restrict__ xs, const T* const (&
     if (tid < R) xs[(int64_t)ncols * R + tid] = (T)0;
 }
 
+// Stage rows row0 .. row0+R-1 of X held column-major (element (row, col) at
+// col * nrows + row) into LDS in the lds_cols<T, R> layout; column ncols is
+// zero.  A thread reads the R consecutive values of a column (one or two
+// cache lines), two columns per pass with all loads before any store.
+template <typename T, int R>
+__device__ __forceinline__ void stage_cols(T* __restrict__ xs, const T* __restrict__ X, int64_t nrows, int64_t row0,
+                                           int64_t ncols) {
+    using L = lds_cols<T, R>;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const bool full = row0 + R <= nrows;   // uniform over the workgroup
+    for (int64_t c0 = tid; c0 < ncols; c0 += 2 * nthr) {
+        T v[2][R];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int64_t c = c0 + u * nthr < ncols ? c0 + u * nthr : ncols - 1;
+            const T* src = X + c * nrows + row0;
+            if (full) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[u][r] = src[r];
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[u][r] = (row0 + r < nrows) ? src[r] : (T)0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int64_t c = c0 + u * nthr;
+            if (c < ncols) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) xs[L::idx(c, r)] = v[u][r];
+            }
+        }
+    }
+    if (tid < R) xs[ncols * R + tid] = (T)0;
+}
+
 // ---------------------------------------------------------------- same spin
 template <typename T>
 struct ss_args {
@@ -98,6 +134,7 @@ struct ss_args {
     int nw;
     const double* diag;        // fused DIAG term (or null)
     int accumulate;
+    int colmajor;              // X, Y (and diag) hold the transposes: (row, col) at col * nrows + row
 };
 
 // Rows blk*R .. blk*R+R-1: Y (=|+=) same-spin singles and doubles of the column
@@ -112,7 +149,9 @@ __device__ __forceinline__ void ss_block(const ss_args<T>& a, const T* __restric
     const int64_t row0 = blk * R;
     const int nthr = blockDim.x;
     const int tid = threadIdx.x;
-    {
+    if (a.colmajor) {
+        stage_cols<T, R>(xs, a.X, nrows, row0, ncols);
+    } else {
         const T* rows[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) rows[r] = (row0 + r < nrows) ? a.X + (row0 + r) * ncols : nullptr;
@@ -228,7 +267,7 @@ __device__ __forceinline__ void ss_block(const ss_args<T>& a, const T* __restric
             for (int r = 0; r < R; ++r) {
                 const int64_t row = row0 + r;
                 if (row < nrows) {
-                    const int64_t o = row * ncols + t;
+                    const int64_t o = a.colmajor ? (int64_t)t * nrows + row : row * ncols + t;
                     T val = acc[r];
                     if (a.diag) val += (T)(a.diag[o] * (double)xs[lds_cols<T, R>::idx(t, r)]);
                     if (a.accumulate) val += a.Y[o];

@@ -235,6 +235,7 @@ int sqd_same_spin_windowed(sqd_ctx* ctx, sqd_space* sp, spin_tables& col, spin_t
                            int64_t nrows, int64_t ncols, const double* diag, int fp32, const int* skip,
                            const char* timer);
 void sqd_free_window_tables(spin_tables* t);
+bool sqd_space_built_for(sqd_ctx* ctx, const sqd_space* sp, int precision, unsigned mask);
 int sqd_window_count(sqd_ctx* ctx, int64_t ncols);    // 0: a window does not fit
 size_t sqd_window_scratch_bytes(const sqd_space* sp);
 

@@ -386,8 +386,12 @@ int launch_win(sqd_ctx* ctx, sqd_space* sp, spin_tables& col, spin_tables& row, 
 
 }  // namespace
 
-// rows staged per windowed workgroup
+// rows staged per windowed workgroup: the window width is set by 8 FP64 rows;
+// FP32 stages 16 rows of the same width in the same LDS, which halves its
+// table stream per row (2.56e8-determinant workload, beta-beta FP32 windowed:
+// 18.4 -> 16.9 ms)
 constexpr int kWinRows = 8;
+constexpr int kWinRows32 = 16;
 
 void sqd_free_window_tables(spin_tables* t) {
     void* ptrs[] = {t->win_s_off, t->win_d_off, t->win_s_pk, t->win_d_nbr, t->win_s_csr,
@@ -405,7 +409,8 @@ void sqd_free_window_tables(spin_tables* t) {
 
 // Windows for rows of ncols strings: the fewest whose R staged FP64 rows fit
 // the LDS of one workgroup (or of the width set by SQD_TUNE_SS_WINDOW).  FP32
-// products use the same windows, so both precisions share one set of tables.
+// products use the same windows (with twice the rows), so both precisions
+// share one set of tables.
 int sqd_window_count(sqd_ctx* ctx, int64_t ncols) {
     int64_t wmax = (int64_t)(ctx->max_lds / (sizeof(double) * kWinRows)) - 1;
     if (ctx->tune[SQD_TUNE_SS_WINDOW] >= 64) wmax = std::min<int64_t>(wmax, ctx->tune[SQD_TUNE_SS_WINDOW]);
@@ -453,6 +458,6 @@ int sqd_same_spin_windowed(sqd_ctx* ctx, sqd_space* sp, spin_tables& col, spin_t
     }
     prof_scope ps(ctx, timer);
     if (fp32)
-        return launch_win<float, kWinRows>(ctx, sp, col, row, (const float*)X, (float*)Y, nrows, ncols, diag, skip);
+        return launch_win<float, kWinRows32>(ctx, sp, col, row, (const float*)X, (float*)Y, nrows, ncols, diag, skip);
     return launch_win<double, kWinRows>(ctx, sp, col, row, (const double*)X, (double*)Y, nrows, ncols, diag, skip);
 }

@@ -59,6 +59,7 @@ def test_bench_algorithmic_work_and_kernel_roofline():
     info = {"conn_terms": [100, 7, 9, 40], "nnz_single": [3, 4], "nnz_double": [5, 6], "na": 10, "nb": 10}
     assert bench._algorithmic("k_ab_grouped<double>", info, Sp) == (80.0, 8.0 * 100 + 8 * 3 * 10 + 4 * 7)
     assert bench._algorithmic("k_same_spin<double>[aa]", info, Sp) == (14.0, 2 * 8 * 100 + 12 * 8)
+    assert bench._algorithmic("k_same_spin<double>[aa]", dict(info, aa_in_place=True), Sp) == (14.0, 3 * 8 * 100 + 12 * 8)
     assert bench._algorithmic("k_same_spin<float>[bb]", info, Sp) == (18.0, 2 * 4 * 100 + 8 * 100 + 8 * 10)
     # gather: Y rows (alpha singles x nb) read once, sigma read and written
     assert bench._algorithmic("k_ab_gather<double>", info, Sp) == (0.0, 8.0 * (3 * 10 + 200))

@@ -6,7 +6,10 @@ allocating entry point on the same input: FP64 max-norm and 2-norm relative
 difference <= 1e-12 (the sigma bar; the two entry points run different
 alpha-beta kernels, so the summation order differs), FP32 <= 2e-6.  The smaller
 space is also checked against the oracle.  Sizes above the documented maximum
-are rejected with SQD_E_LIMIT before anything is enqueued.
+are rejected with SQD_E_LIMIT before anything is enqueued.  A fresh space
+needs no allocating product first; one whose beta rows take the windowed
+same-spin kernel (12,000 strings) answers SQD_E_STATE until an allocating
+product has built its windowed tables, and is then compared the same way.
 """
 import numpy as np
 import pytest
@@ -87,3 +90,37 @@ def test_noalloc_rejects_sizes_beyond_the_limit(ctx):
         sp.sigma_noalloc(c, out)
     assert ei.value.code == -9
     sp.close()
+
+
+def test_noalloc_fresh_space_and_windowed_rows(ctx):
+    torch = need_gpu()
+    from paper_2601_16169_amd import sqd
+    banner("sigma_noalloc: fresh space, then a space with windowed beta rows")
+    # a space straight from build_space (diagonal built there) needs no
+    # allocating product first
+    q = I.small_problem(10, 4, 3, 70, 97, 4)
+    sq = _space(ctx, q)
+    c = torch.tensor(I.random_vector(sq.dim, 13), device="cuda:0")
+    out = torch.full_like(c, float("nan"))
+    sq.sigma_noalloc(c, out)
+    torch.cuda.synchronize()
+    e_inf, e_2 = rel_err(out.cpu().numpy(), core.Space.from_problem(q).sigma(c.cpu().numpy()))
+    assert e_inf <= 1e-12 and e_2 <= 1e-12, (e_inf, e_2)
+    sq.close()
+    # 40 alpha strings x 12,000 beta strings of norb 16: two staged FP64 beta
+    # rows exceed one workgroup's LDS, so the beta-beta term is windowed, and
+    # its tables come with the first allocating product
+    allb = I.all_strings(16, 8)
+    bstr = np.sort(I.random_subset(allb, 12000, 41))
+    astr = np.sort(I.random_subset(allb, 40, 42))
+    ints = I.make_integrals(16, 8, 43)
+    ctx.set_hamiltonian(ints.h, ints.eri, ints.ecore)
+    sw = ctx.build_space(8, 8, astr, bstr)
+    c = torch.tensor(I.random_vector(sw.dim, 14), device="cuda:0")
+    out = torch.empty_like(c)
+    with pytest.raises(sqd.SQDError) as ei:
+        sw.sigma_noalloc(c, out, terms=sqd.TERM_BB)
+    assert ei.value.code == -8
+    for prec, bar in ((sqd.FP64, 1e-12), (sqd.FP32, 2e-6)):
+        _compare(sw, c, prec, sqd.TERM_ALL, bar)
+    sw.close()
