@@ -119,14 +119,7 @@ def main():
     t64 = timed(lambda: sp.sigma(c, out, precision=sqd.FP64), a.steps, a.warmup)
     log(f"sigma fp64 {t64 * 1e3:.3f} ms")
     if a.profile_only:
-        # a plain elementwise kernel of known size (reads COPY_BYTES, writes
-        # COPY_BYTES), for checking the scale of the HBM byte counters
-        src = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            torch.mul(src, 2.0, out=dst)
-        torch.cuda.synchronize()
-        log(f"copy calibration: {COPY_BYTES} bytes read + written per elementwise kernel")
+        _calibration_kernel(dev)
         return
     t32 = timed(lambda: sp.sigma(c, out, precision=sqd.FP32), a.steps, a.warmup)
     log(f"sigma fp32 {t32 * 1e3:.3f} ms")
@@ -463,6 +456,10 @@ def _leg(a, ctx, sp, prob, c, out, info):
         t_build = time.perf_counter() - t
         k = kernels(lambda: sp.spmv(c, out))
         t_spmv = k["k_spmv"] / 1e3
+        if a.profile_only:
+            _calibration_kernel("cuda:0")
+            sp.release_hamiltonian()
+            return
         mf = kernels(lambda: sp.sigma(c, out))
         t_mf = sum(mf.values()) / 1e3
         noise = torch.tensor(I.guess_noise(sp.dim), device="cuda:0")
@@ -476,11 +473,18 @@ def _leg(a, ctx, sp, prob, c, out, info):
             res[name] = {"seconds": time.perf_counter() - t, "energy": E, "iterations": rep["iterations"],
                          "converged": rep["converged"]}
         stream_bytes = 12.0 * nnz + 8.0 * (sp.dim + 1) + 16.0 * sp.dim
+        # bytes the counters saw leave the L2 (FETCH + WRITE, scaled), from
+        # the committed summary while the product's source is unchanged
+        crow = _counters(a.workload, "counters_stored").get("k_spmv", {})
+        cbytes = crow.get("HBM bytes")
         print(json.dumps({"leg": "stored", "workload": prob.name, "nnz": nnz, "stored_bytes": 12 * nnz + 8 * (sp.dim + 1),
                           "build_seconds": t_build, "spmv_ms": t_spmv * 1e3, "matrix_free_sigma_ms": t_mf * 1e3,
                           "spmv_algorithmic_bytes": stream_bytes,
                           "spmv_gb_per_s": stream_bytes / t_spmv / 1e9,
                           "spmv_frac_of_hbm_peak": stream_bytes / t_spmv / (PEAK_HBM_GBS * 1e9),
+                          "spmv_counter_bytes": cbytes,
+                          "spmv_counter_gb_per_s": cbytes / t_spmv / 1e9 if cbytes else None,
+                          "spmv_counter_frac_of_hbm_peak": cbytes / t_spmv / (PEAK_HBM_GBS * 1e9) if cbytes else None,
                           "davidson": res,
                           "abs_energy_diff_Ha": (abs(res["stored"]["energy"] - res["matrix_free"]["energy"])
                                                  if res else None)}),
@@ -566,6 +570,18 @@ def _leg_batched(a):
     print(json.dumps(res), flush=True)
 
 
+def _calibration_kernel(dev):
+    """A plain elementwise kernel of known size (reads COPY_BYTES, writes
+    COPY_BYTES), for checking the scale of the HBM byte counters."""
+    import torch
+    src = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.mul(src, 2.0, out=dst)
+    torch.cuda.synchronize()
+    log(f"copy calibration: {COPY_BYTES} bytes read + written per elementwise kernel")
+
+
 def _algorithmic(name, info, sp):
     """(flops, compulsory HBM bytes) of one launch of a sigma kernel, from
     the table counts; (None, None) for kernels not accounted here.
@@ -600,14 +616,14 @@ def _algorithmic(name, info, sp):
     return None, None
 
 
-def _counters(workload):
+def _counters(workload, prefix="counters_sigma"):
     """Per-kernel counter figures from the committed summary
-    profiles/counters_sigma_<workload>.md, or {} when it is absent or the
-    kernel sources changed since it was taken.  Keys: the kernel cell of its
-    table; values: dict of the numeric columns (HBM bytes already scaled)."""
+    profiles/<prefix>_<workload>.md, or {} when it is absent or the kernel
+    sources changed since it was taken.  Keys: the kernel cell of its table;
+    values: dict of the numeric columns (HBM bytes already scaled)."""
     import hashlib
     import re
-    path = os.path.join(PROFILES, f"counters_sigma_{workload}.md")
+    path = os.path.join(PROFILES, f"{prefix}_{workload}.md")
     if not os.path.exists(path):
         return {}
     text = open(path).read()

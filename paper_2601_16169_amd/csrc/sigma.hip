@@ -235,8 +235,8 @@ k_ab_gather(const T* __restrict__ Y, T* __restrict__ S, int64_t na, int64_t nb, 
 }
 
 // Longest alpha-beta output row assembled in LDS by the gather (larger rows are
-// added in place).
-constexpr int64_t kGatherStageBytes = 64 * 1024;
+// added in place, with scattered read-modify-writes of sigma).
+constexpr int64_t kGatherStageBytes = 128 * 1024;
 
 constexpr int kAbMaxJ = 8;
 
@@ -303,14 +303,38 @@ bool use_window(sqd_ctx* ctx, int64_t nrows, int64_t ncols, int norb, size_t es)
 
 // colmajor: X and Y hold the transposes (the alpha-alpha term read from C and
 // added into sigma directly); only for the row-staged kernel.
+// The alpha-alpha term runs the row-staged kernel column-major on C (no
+// transposes) when a staged column of C is a whole 64-byte piece (measured on
+// MI355X: FP64 with 8 rows, 4.0e6 workload, sigma 0.878 -> 0.867 ms; FP32
+// with 8 rows, 32-byte pieces: no change; FP32 with 2 rows of the 2.56e8
+// workload, 8-byte pieces: alpha-alpha with its transposes 17.1 ms, in place
+// 20.8 ms), else the transposes around the row-major kernel.
+bool aa_in_place(sqd_ctx* ctx, int64_t nb, int64_t na, int norb, size_t es) {
+    if (use_window(ctx, nb, na, norb, es)) return false;
+    return (size_t)pick_rows(ctx, nb, na, norb, es) * es >= 64;
+}
+
 template <typename T>
 int launch_same_spin(sqd_ctx* ctx, sqd_space* sp, const T* X, T* Y, int64_t nrows, int64_t ncols,
                      const spin_tables& col, const spin_tables& row, const T* jk, int norb, const double* diag,
                      int accumulate, const int* skip, const char* timer_name, int colmajor = 0) {
     const size_t es = sizeof(T);
-    if (!accumulate && !colmajor && use_window(ctx, nrows, ncols, norb, es))
-        return sqd_same_spin_windowed(ctx, sp, owner(sp, col), owner(sp, row), X, Y, nrows, ncols, diag,
-                                      sizeof(T) == 4, skip, timer_name);
+    if (!accumulate && !colmajor && use_window(ctx, nrows, ncols, norb, es)) {
+        // the windowed kernel writes its targets in scattered order, so the
+        // diagonal (scattered reads of diag and X there) goes in a coalesced
+        // pass after it (2.56e8 workload: beta-beta with the fused diagonal
+        // 35.5 ms, without 28.1 ms)
+        int rc = sqd_same_spin_windowed(ctx, sp, owner(sp, col), owner(sp, row), X, Y, nrows, ncols, sizeof(T) == 4,
+                                        skip, timer_name);
+        if (rc || !diag) return rc;
+        if constexpr (sizeof(T) == 8) {
+            prof_scope pd(ctx, "k_diag_apply");
+            const int64_t n = nrows * ncols;
+            hipLaunchKernelGGL(k_diag_apply, dim3(nblk(n, 256)), dim3(256), 0, ctx->stream, diag, X, Y, n, 1, skip);
+            SQD_HIP(ctx, hipGetLastError());
+        }
+        return SQD_OK;
+    }
     const int R = pick_rows(ctx, nrows, ncols, norb, es);
     if (R == 0) return sqd_fail(ctx, SQD_E_LIMIT, "same-spin row does not fit in LDS (too many strings)");
     const size_t lds = ((size_t)(ncols + 1) * R + (size_t)norb * norb * R) * es;
@@ -482,12 +506,14 @@ int launch_ab_grouped(sqd_ctx* ctx, sqd_space* sp, const T* C, T* S, T* Y, const
     // measured on MI355X (4.0e6-determinant workload): 1024 threads per row
     // for FP64, 512 for FP32
     const dim3 gblock(sizeof(T) == 8 ? 1024 : 512);
-    if (row_bytes <= kGatherStageBytes)
+    if (row_bytes <= std::min<int64_t>(kGatherStageBytes, (int64_t)ctx->max_lds)) {
+        set_lds(k_ab_gather<T, true>, (int)row_bytes);
         hipLaunchKernelGGL((k_ab_gather<T, true>), dim3(gx), gblock, (size_t)row_bytes, ctx->stream, Y, S, A.n,
                            B.n, ldy, B.perm_ab, A.s_off, sp->ab_row_order, skip);
-    else
+    } else {
         hipLaunchKernelGGL((k_ab_gather<T, false>), dim3(gx), gblock, 0, ctx->stream, Y, S, A.n, B.n, ldy,
                            B.perm_ab, A.s_off, sp->ab_row_order, skip);
+    }
     SQD_HIP(ctx, hipGetLastError());
     return SQD_OK;
 }
@@ -627,7 +653,7 @@ int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma, 
             hipLaunchKernelGGL(k_diag_apply, dim3(g), dim3(256), 0, ctx->stream, diag, c, sigma, dim, 0, skip);
             written = true;
         }
-        if ((mask & SQD_TERM_AA) && !use_window(ctx, nb, na, norb, 8)) {
+        if ((mask & SQD_TERM_AA) && aa_in_place(ctx, nb, na, norb, 8)) {
             // row-staged: beta rows read from the columns of C, added into sigma
             if ((rc = launch_same_spin<double>(ctx, sp, c, sigma, nb, na, A, B, ctx->jk64, norb, nullptr,
                                                written ? 1 : 0, skip, "k_same_spin<double>[aa]", 1)))
@@ -687,7 +713,7 @@ int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma, 
             return rc;
         written = true;
     }
-    if ((mask & SQD_TERM_AA) && !use_window(ctx, nb, na, norb, 4)) {
+    if ((mask & SQD_TERM_AA) && aa_in_place(ctx, nb, na, norb, 4)) {
         if ((rc = launch_same_spin<float>(ctx, sp, Cin, S32, nb, na, A, B, ctx->jk32, norb, nullptr, written ? 1 : 0,
                                           skip, "k_same_spin<float>[aa]", 1)))
             return rc;

@@ -97,6 +97,20 @@ __device__ __forceinline__ void stage_cols(T* __restrict__ xs, const T* __restri
             const int64_t c = c0 + u * nthr < ncols ? c0 + u * nthr : ncols - 1;
             const T* src = X + c * nrows + row0;
             if (full) {
+                if constexpr (R * sizeof(T) % 16 == 0) {
+                    if ((reinterpret_cast<uintptr_t>(src) & 15) == 0) {   // 16-byte pieces
+                        using V4 = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
+                        constexpr int kP = (int)(16 / sizeof(T));
+#pragma unroll
+                        for (int q = 0; q < R / kP; ++q) {
+                            const V4 x = reinterpret_cast<const V4*>(src)[q];
+                            const T* xv = reinterpret_cast<const T*>(&x);
+#pragma unroll
+                            for (int i = 0; i < kP; ++i) v[u][q * kP + i] = xv[i];
+                        }
+                        continue;
+                    }
+                }
 #pragma unroll
                 for (int r = 0; r < R; ++r) v[u][r] = src[r];
             } else {
@@ -262,6 +276,31 @@ __device__ __forceinline__ void ss_block(const ss_args<T>& a, const T* __restric
         }
         for (; k < d1; ++k) dbl(a.d_nbr[(int64_t)k * 64 + lane], a.d_val[(int64_t)k * 64 + lane]);
         const int t = a.perm[sl * 64 + lane];
+        if constexpr (R * sizeof(T) % 16 == 0) {
+            // column-major output of a whole row block: R consecutive values
+            // of the target's column in 16-byte pieces
+            T* yp = a.Y + (int64_t)t * nrows + row0;
+            if (a.colmajor && !a.diag && t < ncols && row0 + R <= nrows &&
+                (reinterpret_cast<uintptr_t>(yp) & 15) == 0) {
+                using V4 = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
+                constexpr int kP = (int)(16 / sizeof(T));
+                V4 old[R / kP];
+                if (a.accumulate) {
+#pragma unroll
+                    for (int q = 0; q < R / kP; ++q) old[q] = reinterpret_cast<const V4*>(yp)[q];
+                }
+#pragma unroll
+                for (int q = 0; q < R / kP; ++q) {
+                    V4 y;
+                    T* yv = reinterpret_cast<T*>(&y);
+                    const T* ov = reinterpret_cast<const T*>(&old[q]);
+#pragma unroll
+                    for (int i = 0; i < kP; ++i) yv[i] = acc[q * kP + i] + (a.accumulate ? ov[i] : (T)0);
+                    reinterpret_cast<V4*>(yp)[q] = y;
+                }
+                continue;
+            }
+        }
         if (t < ncols) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {

@@ -232,8 +232,7 @@ int sqd_sigma_ab_kh(sqd_ctx* ctx, sqd_space* sp, const void* c, void* sigma, voi
 // column spin's tables, by windows of source strings; Y written (no
 // accumulation).  col / row: the owning spin_tables of the column and row spins.
 int sqd_same_spin_windowed(sqd_ctx* ctx, sqd_space* sp, spin_tables& col, spin_tables& row, const void* X, void* Y,
-                           int64_t nrows, int64_t ncols, const double* diag, int fp32, const int* skip,
-                           const char* timer);
+                           int64_t nrows, int64_t ncols, int fp32, const int* skip, const char* timer);
 void sqd_free_window_tables(spin_tables* t);
 bool sqd_space_built_for(sqd_ctx* ctx, const sqd_space* sp, int precision, unsigned mask);
 int sqd_window_count(sqd_ctx* ctx, int64_t ncols);    // 0: a window does not fit

@@ -14,7 +14,8 @@
 // windows, which keeps the 64-lane slices of every part nearly as tight as
 // the whole table's.  A lane's partial sums go to a scratch row in slot order
 // (coalesced, read back by the same lane in the next window) and the last
-// window adds the diagonal and writes the target.  The cross-spin part of the
+// window writes the target (the caller adds the diagonal in a coalesced
+// pass).  The cross-spin part of the
 // singles comes from a per-string table wg[s][pq] = sum_{k in s} (pq|kk) of
 // the row spin (global memory) instead of an LDS copy per row.
 #include <algorithm>
@@ -65,7 +66,6 @@ struct win_args {
     const int* d_nbr;
     const T* d_val;
     const T* wg;                // row spin: nrows x norb2
-    const double* diag;         // fused DIAG term (or null)
     int norb;
 };
 
@@ -192,7 +192,7 @@ __global__ void __launch_bounds__(1024) k_same_spin_win(win_args<T> a, const int
             }
             // the lane keeps its slot in every window: partial sums in slot
             // order (its own earlier writes, read back in program order);
-            // the last window writes the target with the diagonal
+            // the last window writes the target
             const int t = a.perm[slot];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -203,7 +203,7 @@ __global__ void __launch_bounds__(1024) k_same_spin_win(win_args<T> a, const int
                     a.P[row * ldp + slot] = val;
                 } else if (t < a.ncols) {
                     const int64_t o = row * a.ncols + t;
-                    a.Y[o] = a.diag ? val + (T)(a.diag[o] * (double)a.X[o]) : val;
+                    a.Y[o] = val;
                 }
             }
         }
@@ -369,14 +369,14 @@ void set_lds_attr(F f, int bytes) {
 
 template <typename T, int R>
 int launch_win(sqd_ctx* ctx, sqd_space* sp, spin_tables& col, spin_tables& row, const T* X, T* Y, int64_t nrows,
-               int64_t ncols, const double* diag, const int* skip) {
+               int64_t ncols, const int* skip) {
     const T* sv;
     const T* dv;
     const T* wg;
     if constexpr (sizeof(T) == 8) { sv = (const T*)col.win_s_v64; dv = (const T*)col.win_d_v64; wg = (const T*)row.wg64; }
     else { sv = (const T*)col.win_s_v32; dv = (const T*)col.win_d_v32; wg = (const T*)row.wg32; }
     win_args<T> a{X, Y, (T*)sp->win_P, nrows, ncols, col.win_W, col.win_width, col.nslices, col.perm_ss,
-                  col.win_s_off, col.win_d_off, col.win_s_pk, sv, col.win_d_nbr, dv, wg, diag, sp->norb};
+                  col.win_s_off, col.win_d_off, col.win_s_pk, sv, col.win_d_nbr, dv, wg, sp->norb};
     const size_t lds = (size_t)(col.win_width + 1) * R * sizeof(T);
     set_lds_attr(k_same_spin_win<T, R>, (int)lds);
     hipLaunchKernelGGL((k_same_spin_win<T, R>), dim3(nblk(nrows, R)), dim3(1024), lds, ctx->stream, a, skip);
@@ -428,7 +428,7 @@ size_t sqd_window_scratch_bytes(const sqd_space* sp) {
 }
 
 int sqd_same_spin_windowed(sqd_ctx* ctx, sqd_space* sp, spin_tables& col, spin_tables& row, const void* X, void* Y,
-                           int64_t nrows, int64_t ncols, const double* diag, int fp32, const int* skip,
+                           int64_t nrows, int64_t ncols, int fp32, const int* skip,
                            const char* timer) {
     const int W = sqd_window_count(ctx, ncols);
     if (W == 0) return sqd_fail(ctx, SQD_E_LIMIT, "same-spin window does not fit in LDS");
@@ -458,6 +458,6 @@ int sqd_same_spin_windowed(sqd_ctx* ctx, sqd_space* sp, spin_tables& col, spin_t
     }
     prof_scope ps(ctx, timer);
     if (fp32)
-        return launch_win<float, kWinRows32>(ctx, sp, col, row, (const float*)X, (float*)Y, nrows, ncols, diag, skip);
-    return launch_win<double, kWinRows>(ctx, sp, col, row, (const double*)X, (double*)Y, nrows, ncols, diag, skip);
+        return launch_win<float, kWinRows32>(ctx, sp, col, row, (const float*)X, (float*)Y, nrows, ncols, skip);
+    return launch_win<double, kWinRows>(ctx, sp, col, row, (const double*)X, (double*)Y, nrows, ncols, skip);
 }
