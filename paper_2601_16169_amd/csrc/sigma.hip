@@ -302,15 +302,16 @@ bool use_window(sqd_ctx* ctx, int64_t nrows, int64_t ncols, int norb, size_t es)
 }
 
 // colmajor: X and Y hold the transposes (the alpha-alpha term read from C and
-// added into sigma directly); only for the row-staged kernel.
-// The alpha-alpha term runs the row-staged kernel column-major on C (no
-// transposes) when a staged column of C is a whole 64-byte piece (measured on
-// MI355X: FP64 with 8 rows, 4.0e6 workload, sigma 0.878 -> 0.867 ms; FP32
-// with 8 rows, 32-byte pieces: no change; FP32 with 2 rows of the 2.56e8
-// workload, 8-byte pieces: alpha-alpha with its transposes 17.1 ms, in place
-// 20.8 ms), else the transposes around the row-major kernel.
+// added into sigma directly).
+// The alpha-alpha term runs column-major on C (no transposes) when a staged
+// column of C is a whole 64-byte piece: the windowed kernel (8 FP64 or 16
+// FP32 rows) and the row-staged kernel with 8 FP64 rows (measured on MI355X:
+// 4.0e6 workload, sigma FP64 0.878 -> 0.867 ms; FP32 with 8 rows, 32-byte
+// pieces: no change; FP32 with 2 rows of the 2.56e8 workload, 8-byte pieces:
+// alpha-alpha with its transposes 17.1 ms, in place 20.8 ms); otherwise the
+// transposes around the row-major kernel.
 bool aa_in_place(sqd_ctx* ctx, int64_t nb, int64_t na, int norb, size_t es) {
-    if (use_window(ctx, nb, na, norb, es)) return false;
+    if (use_window(ctx, nb, na, norb, es)) return true;
     return (size_t)pick_rows(ctx, nb, na, norb, es) * es >= 64;
 }
 
@@ -319,13 +320,13 @@ int launch_same_spin(sqd_ctx* ctx, sqd_space* sp, const T* X, T* Y, int64_t nrow
                      const spin_tables& col, const spin_tables& row, const T* jk, int norb, const double* diag,
                      int accumulate, const int* skip, const char* timer_name, int colmajor = 0) {
     const size_t es = sizeof(T);
-    if (!accumulate && !colmajor && use_window(ctx, nrows, ncols, norb, es)) {
+    if (use_window(ctx, nrows, ncols, norb, es)) {
         // the windowed kernel writes its targets in scattered order, so the
         // diagonal (scattered reads of diag and X there) goes in a coalesced
         // pass after it (2.56e8 workload: beta-beta with the fused diagonal
         // 35.5 ms, without 28.1 ms)
-        int rc = sqd_same_spin_windowed(ctx, sp, owner(sp, col), owner(sp, row), X, Y, nrows, ncols, sizeof(T) == 4,
-                                        skip, timer_name);
+        int rc = sqd_same_spin_windowed(ctx, sp, owner(sp, col), owner(sp, row), X, Y, nrows, ncols, colmajor,
+                                        accumulate, sizeof(T) == 4, skip, timer_name);
         if (rc || !diag) return rc;
         if constexpr (sizeof(T) == 8) {
             prof_scope pd(ctx, "k_diag_apply");
@@ -654,7 +655,7 @@ int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma, 
             written = true;
         }
         if ((mask & SQD_TERM_AA) && aa_in_place(ctx, nb, na, norb, 8)) {
-            // row-staged: beta rows read from the columns of C, added into sigma
+            // beta rows read from the columns of C, added into sigma
             if ((rc = launch_same_spin<double>(ctx, sp, c, sigma, nb, na, A, B, ctx->jk64, norb, nullptr,
                                                written ? 1 : 0, skip, "k_same_spin<double>[aa]", 1)))
                 return rc;

@@ -186,6 +186,7 @@ struct sqd_space {
     int64_t h_nnz = 0;
     int64_t h_bytes = 0;
     int h_version = -1;
+    int64_t h_xcd_rows[9] = {};   // row ranges of equal element counts, one per XCD
     // partial sums of the windowed same-spin kernel (rows x slots, FP64-sized)
     void* win_P = nullptr;
     size_t win_P_bytes = 0;
@@ -232,7 +233,8 @@ int sqd_sigma_ab_kh(sqd_ctx* ctx, sqd_space* sp, const void* c, void* sigma, voi
 // column spin's tables, by windows of source strings; Y written (no
 // accumulation).  col / row: the owning spin_tables of the column and row spins.
 int sqd_same_spin_windowed(sqd_ctx* ctx, sqd_space* sp, spin_tables& col, spin_tables& row, const void* X, void* Y,
-                           int64_t nrows, int64_t ncols, int fp32, const int* skip, const char* timer);
+                           int64_t nrows, int64_t ncols, int colmajor, int accumulate, int fp32, const int* skip,
+                           const char* timer);
 void sqd_free_window_tables(spin_tables* t);
 bool sqd_space_built_for(sqd_ctx* ctx, const sqd_space* sp, int precision, unsigned mask);
 int sqd_window_count(sqd_ctx* ctx, int64_t ncols);    // 0: a window does not fit

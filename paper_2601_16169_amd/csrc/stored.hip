@@ -124,16 +124,26 @@ __global__ void __launch_bounds__(256) k_store_fill(store_args a) {
     }
 }
 
+struct xcd_rows {
+    int64_t r[9];
+};
+
 // y[r] = sum_k val[k] x[col[k]]: one wavefront per row, four 64-entry blocks
 // of the row in flight per lane; the matrix stream is read non-temporally so
-// that the cached lines of x stay resident.
+// that the cached lines of x stay resident.  The rows are cut into eight
+// ranges of equal element counts, one per XCD (workgroup k runs on XCD k mod
+// 8 and walks range k mod 8), so that the rows in flight on one XCD share
+// their alpha string and the rows of x they gather from stay in that XCD's
+// L2.
 __global__ void __launch_bounds__(256) k_spmv(const int64_t* __restrict__ rp, const int* __restrict__ col,
                                               const double* __restrict__ val, const double* __restrict__ x,
-                                              double* __restrict__ y, int64_t n, const int* __restrict__ skip) {
+                                              double* __restrict__ y, xcd_rows xr, const int* __restrict__ skip) {
     if (skip && *skip) return;
     const int lane = threadIdx.x & 63;
-    for (int64_t r = (int64_t)blockIdx.x * kRowsPerBlock + (threadIdx.x >> 6); r < n;
-         r += (int64_t)gridDim.x * kRowsPerBlock) {
+    const int xcd = (int)(blockIdx.x & 7);
+    const int64_t j = blockIdx.x >> 3, nj = gridDim.x >> 3;
+    const int64_t r0 = xr.r[xcd], r1 = xr.r[xcd + 1];
+    for (int64_t r = r0 + j * kRowsPerBlock + (threadIdx.x >> 6); r < r1; r += nj * kRowsPerBlock) {
         const int64_t k1 = rp[r + 1];
         int64_t k = rp[r] + lane;
         double acc = 0.0;
@@ -244,6 +254,25 @@ int sqd_store_h_impl(sqd_ctx* ctx, sqd_space* sp, int64_t* nnz_out) {
         return sqd_hip_fail(ctx, e, "stored H build");
     }
     sp->h_nnz = nnz;
+    // row ranges of equal element counts for the eight XCDs (binary search
+    // on the row pointer)
+    sp->h_xcd_rows[0] = 0;
+    sp->h_xcd_rows[8] = dim;
+    for (int q = 1; q < 8; ++q) {
+        const int64_t target = nnz * q / 8;
+        int64_t lo = sp->h_xcd_rows[q - 1], hi = dim;   // first row whose start is >= target
+        while (lo < hi) {
+            const int64_t mid = lo + (hi - lo) / 2;
+            int64_t v = 0;
+            e = hipMemcpy(&v, sp->h_rowptr + mid, sizeof(int64_t), hipMemcpyDeviceToHost);
+            if (e != hipSuccess) {
+                sqd_release_stored_h(sp);
+                return sqd_hip_fail(ctx, e, "stored H row ranges");
+            }
+            if (v < target) lo = mid + 1; else hi = mid;
+        }
+        sp->h_xcd_rows[q] = lo;
+    }
     sp->h_version = ctx->ham_version;
     if (nnz_out) *nnz_out = nnz;
     return SQD_OK;
@@ -253,8 +282,13 @@ int sqd_spmv_impl(sqd_ctx* ctx, sqd_space* sp, const double* x, double* y, const
     if (!sp->h_val || sp->h_version != ctx->ham_version)
         return sqd_fail(ctx, SQD_E_STATE, "no current stored H on this space (call sqd_store_hamiltonian)");
     prof_scope ps(ctx, "k_spmv");
-    hipLaunchKernelGGL(k_spmv, dim3(fill_grid(sp->dim)), dim3(256), 0, ctx->stream, sp->h_rowptr, sp->h_col,
-                       sp->h_val, x, y, sp->dim, skip);
+    // eight workgroups of four rows per CU, a multiple of the 8 XCDs
+    const int64_t want = std::max<int64_t>(1, (sp->dim + kRowsPerBlock - 1) / kRowsPerBlock);
+    const unsigned grid = (unsigned)(8 * std::max<int64_t>(1, std::min<int64_t>(ctx->num_cu, (want + 7) / 8)));
+    xcd_rows xr;
+    for (int q = 0; q < 9; ++q) xr.r[q] = sp->h_xcd_rows[q];
+    hipLaunchKernelGGL(k_spmv, dim3(grid), dim3(256), 0, ctx->stream, sp->h_rowptr, sp->h_col, sp->h_val, x, y, xr,
+                       skip);
     SQD_HIP(ctx, hipGetLastError());
     return SQD_OK;
 }

@@ -67,6 +67,8 @@ struct win_args {
     const T* d_val;
     const T* wg;                // row spin: nrows x norb2
     int norb;
+    int colmajor;               // X, Y hold the transposes: (row, col) at col * nrows + row
+    int accumulate;             // Y += (else Y =)
 };
 
 // One workgroup per block of R rows; windows in turn.  LDS: xs[(width + 1) * R]
@@ -101,8 +103,10 @@ __global__ void __launch_bounds__(1024) k_same_spin_win(win_args<T> a, const int
             for (int u = 0; u < 2; ++u) {
                 const int c = c0 + u * nthr;
                 const int cc = c < len ? c : 0;
+                const int64_t src = w + (int64_t)cc * a.W;
 #pragma unroll
-                for (int r = 0; r < R; ++r) v[u][r] = a.X[rowc(r) * a.ncols + w + (int64_t)cc * a.W];
+                for (int r = 0; r < R; ++r)
+                    v[u][r] = a.colmajor ? a.X[src * a.nrows + rowc(r)] : a.X[rowc(r) * a.ncols + src];
             }
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
@@ -202,8 +206,8 @@ __global__ void __launch_bounds__(1024) k_same_spin_win(win_args<T> a, const int
                 if (!last) {
                     a.P[row * ldp + slot] = val;
                 } else if (t < a.ncols) {
-                    const int64_t o = row * a.ncols + t;
-                    a.Y[o] = val;
+                    const int64_t o = a.colmajor ? (int64_t)t * a.nrows + row : row * a.ncols + t;
+                    a.Y[o] = a.accumulate ? a.Y[o] + val : val;
                 }
             }
         }
@@ -369,14 +373,14 @@ void set_lds_attr(F f, int bytes) {
 
 template <typename T, int R>
 int launch_win(sqd_ctx* ctx, sqd_space* sp, spin_tables& col, spin_tables& row, const T* X, T* Y, int64_t nrows,
-               int64_t ncols, const int* skip) {
+               int64_t ncols, int colmajor, int accumulate, const int* skip) {
     const T* sv;
     const T* dv;
     const T* wg;
     if constexpr (sizeof(T) == 8) { sv = (const T*)col.win_s_v64; dv = (const T*)col.win_d_v64; wg = (const T*)row.wg64; }
     else { sv = (const T*)col.win_s_v32; dv = (const T*)col.win_d_v32; wg = (const T*)row.wg32; }
     win_args<T> a{X, Y, (T*)sp->win_P, nrows, ncols, col.win_W, col.win_width, col.nslices, col.perm_ss,
-                  col.win_s_off, col.win_d_off, col.win_s_pk, sv, col.win_d_nbr, dv, wg, sp->norb};
+                  col.win_s_off, col.win_d_off, col.win_s_pk, sv, col.win_d_nbr, dv, wg, sp->norb, colmajor, accumulate};
     const size_t lds = (size_t)(col.win_width + 1) * R * sizeof(T);
     set_lds_attr(k_same_spin_win<T, R>, (int)lds);
     hipLaunchKernelGGL((k_same_spin_win<T, R>), dim3(nblk(nrows, R)), dim3(1024), lds, ctx->stream, a, skip);
@@ -428,7 +432,7 @@ size_t sqd_window_scratch_bytes(const sqd_space* sp) {
 }
 
 int sqd_same_spin_windowed(sqd_ctx* ctx, sqd_space* sp, spin_tables& col, spin_tables& row, const void* X, void* Y,
-                           int64_t nrows, int64_t ncols, int fp32, const int* skip,
+                           int64_t nrows, int64_t ncols, int colmajor, int accumulate, int fp32, const int* skip,
                            const char* timer) {
     const int W = sqd_window_count(ctx, ncols);
     if (W == 0) return sqd_fail(ctx, SQD_E_LIMIT, "same-spin window does not fit in LDS");
@@ -458,6 +462,8 @@ int sqd_same_spin_windowed(sqd_ctx* ctx, sqd_space* sp, spin_tables& col, spin_t
     }
     prof_scope ps(ctx, timer);
     if (fp32)
-        return launch_win<float, kWinRows32>(ctx, sp, col, row, (const float*)X, (float*)Y, nrows, ncols, skip);
-    return launch_win<double, kWinRows>(ctx, sp, col, row, (const double*)X, (double*)Y, nrows, ncols, skip);
+        return launch_win<float, kWinRows32>(ctx, sp, col, row, (const float*)X, (float*)Y, nrows, ncols, colmajor,
+                                             accumulate, skip);
+    return launch_win<double, kWinRows>(ctx, sp, col, row, (const double*)X, (double*)Y, nrows, ncols, colmajor,
+                                          accumulate, skip);
 }
