@@ -188,3 +188,30 @@ def test_cfg5_rdm_and_finite_differences(ctx):
     assert np.abs(g2 - g2.transpose(2, 3, 0, 1)).max() <= 1e-11
     sp.close()
     _fd_check(ctx, p, 50, 55, 1e-9)
+
+
+def test_cfg5_rdm_matches_stored_oracle(ctx):
+    """1.6e7-determinant workload: the 1- and 2-RDM of a seeded normalised
+    vector against the oracle's (definition-based enumeration, stored by
+    tests/golden/make_golden.py cfg5_rdm), element by element within 1e-12
+    of the largest entry of each."""
+    torch = need_gpu()
+    import json
+    import os
+    golden = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    meta = json.load(open(os.path.join(golden, "cfg5_oracle_rdm.json")))
+    assert meta["vector"] == "random_vector(dim, 55) normalised"
+    ref = np.load(os.path.join(golden, "cfg5_oracle_rdm.npz"))
+    banner("rdm cfg5 vs stored oracle")
+    p = I.cfg5()
+    sp = _space(ctx, p)
+    c = I.random_vector(sp.dim, 55)
+    c /= np.linalg.norm(c)
+    g1, g2 = sp.rdm(torch.tensor(c, device="cuda:0"))
+    g1, g2 = g1.cpu().numpy(), g2.cpu().numpy()
+    r1, r2 = ref["rdm1"], ref["rdm2"]
+    e1 = np.abs(g1 - r1).max() / np.abs(r1).max()
+    e2 = np.abs(g2 - r2).max() / np.abs(r2).max()
+    print("cfg5 rdm relative max differences", e1, e2)
+    assert e1 <= 1e-12 and e2 <= 1e-12, (e1, e2)
+    sp.close()
