@@ -8,7 +8,7 @@
 // each row by target index (canonical order) and packed.  The integral-
 // dependent same-spin values are computed per entry afterwards, so that a new
 // Hamiltonian does not rebuild the structure.
-#include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
 
 #include "sqd_internal.h"
 
@@ -424,16 +424,17 @@ __global__ void k_sell_values(const int* __restrict__ sell_csr, int64_t m, const
 
 inline unsigned nblocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
-// Sort (key, value) pairs with hipcub radix sort; end_bit bits of key used.
+// Sort (key, value) pairs with rocPRIM's device radix sort; end_bit bits of key used.
 template <typename K, typename V>
 int radix_sort(sqd_ctx* ctx, K* keys, V* vals, int64_t n, int end_bit) {
     if (n <= 1) return SQD_OK;
     K* k2 = nullptr; V* v2 = nullptr; void* tmp = nullptr; size_t tmpb = 0;
     SQD_HIP(ctx, hipMalloc(&k2, sizeof(K) * n));
     SQD_HIP(ctx, hipMalloc(&v2, sizeof(V) * n));
-    SQD_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(nullptr, tmpb, keys, k2, vals, v2, (int)n, 0, end_bit, ctx->stream));
+    SQD_HIP(ctx, rocprim::radix_sort_pairs(nullptr, tmpb, keys, k2, vals, v2, (size_t)n, 0u, (unsigned)end_bit,
+                                           ctx->stream));
     SQD_HIP(ctx, hipMalloc(&tmp, tmpb > 0 ? tmpb : 1));
-    SQD_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(tmp, tmpb, keys, k2, vals, v2, (int)n, 0, end_bit, ctx->stream));
+    SQD_HIP(ctx, rocprim::radix_sort_pairs(tmp, tmpb, keys, k2, vals, v2, (size_t)n, 0u, (unsigned)end_bit, ctx->stream));
     SQD_HIP(ctx, hipMemcpyAsync(keys, k2, sizeof(K) * n, hipMemcpyDeviceToDevice, ctx->stream));
     SQD_HIP(ctx, hipMemcpyAsync(vals, v2, sizeof(V) * n, hipMemcpyDeviceToDevice, ctx->stream));
     SQD_HIP(ctx, hipStreamSynchronize(ctx->stream));

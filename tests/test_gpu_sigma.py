@@ -536,3 +536,34 @@ def test_sigma_windowed_cfg2_matches_row_staged(ctx):
         e_inf, e_2 = rel_err(got, ref)
         assert e_inf <= bar and e_2 <= bar, (prec, e_inf, e_2)
     sp.close()
+
+
+@pytest.mark.parametrize("name,make", [
+    ("sab_neq_10_4_3", lambda: I.small_problem(10, 4, 3, 70, 97, 4)),     # 97 beta rows: a 1-row last block
+    ("rows_64_8_3_4", lambda: I.small_problem(8, 3, 4, 53, 64, 5)),       # whole 8-row blocks, even rows
+    ("rows_9_8_4_4", lambda: I.small_problem(8, 4, 4, 60, 9, 7)),         # two blocks, the second of one row
+])
+def test_sigma_alpha_alpha_column_major(ctx, name, make):
+    """The alpha-alpha term read from C column-major (8 staged FP64 rows, the
+    path of the 4.0e6 workload) on small ragged spaces, forced with
+    SQD_TUNE_SS_ROWS = 8: against the oracle per term and in total, FP64
+    <= 1e-12 (and FP32, which keeps the transposes at 8 rows, <= 2e-6)."""
+    torch = need_gpu()
+    from paper_2601_16169_amd import sqd
+    banner(f"alpha-alpha column-major {name}")
+    p = make()
+    sp = _space(ctx, p)
+    osp = core.Space.from_problem(p)
+    c = I.random_vector(sp.dim, 19)
+    ct = torch.tensor(c, device="cuda:0")
+    ctx.set_tuning(sqd.TUNE_SS_ROWS, 8)
+    try:
+        for mask in (TERMS["AA"], TERMS["AA"] | TERMS["BB"], TERMS["ALL"]):
+            ref = osp.sigma(c, mask)
+            for prec, bar in ((sqd.FP64, 1e-12), (sqd.FP32, 2e-6)):
+                got = sp.sigma(ct, precision=prec, terms=mask).cpu().numpy()
+                e_inf, e_2 = rel_err(got, ref)
+                assert e_inf <= bar and e_2 <= bar, (mask, prec, e_inf, e_2)
+    finally:
+        ctx.set_tuning(sqd.TUNE_SS_ROWS, 0)
+    sp.close()
