@@ -74,7 +74,7 @@ extern "C" {
 
 /* Davidson precision modes */
 #define SQD_DAV_FP64 0
-#define SQD_DAV_MIXED 1   /* FP32 sigma until ||r|| < switch_tol, then FP64 refinement */
+#define SQD_DAV_MIXED 1   /* FP32 sigma (and an FP32 basis) until ||r|| < switch_tol, then FP64 refinement */
 
 /* Davidson product (Sec. II: the two methods of the CPU code) */
 #define SQD_PRODUCT_MATRIX_FREE 0   /* every H_IJ recomputed in each product (sqd_sigma)  */

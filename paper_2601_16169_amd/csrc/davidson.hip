@@ -18,7 +18,8 @@
 //   collapse   (only when m == m_max) V[0] = V y, AV[0] = AV y in place.
 //   orth1      t1 = t - V h, partials of h2 = V^T t1 and |t1|^2 (second pass).
 //   orth2      v = (t1 - V h2) / |t1 - V h2| -> V[m] and the product input.
-//   sigma      AV[m] = H v (FP64, or FP32 off-diagonal terms in mixed mode).
+//   sigma      AV[m] = H v (FP64, or FP32 off-diagonal terms in mixed mode,
+//              whose FP32 phase keeps V and AV in FP32).
 //   dots       G[:, m] = V^T AV[m]; last block: m += 1 and a parallel cyclic
 //              Jacobi eigen-solve of G for the next (theta, y).
 #include <chrono>
@@ -41,64 +42,78 @@ template <int MODE>
 __global__ void __launch_bounds__(kThreads) k_pick_fin(const double* __restrict__ partial, int nrows, dav_state* st) {
     f_pick_fin<MODE>(partial, nrows, st);
 }
+template <typename VT>
 __global__ void __launch_bounds__(kThreads) k_start(const double* __restrict__ guess, const double* __restrict__ noise,
-                                                    int64_t n, const dav_state* st, double* __restrict__ V0,
+                                                    int64_t n, const dav_state* st, VT* __restrict__ V0,
                                                     double* __restrict__ partial) {
-    d_start(guess, noise, n, st, V0, partial, blockIdx.x, gridDim.x);
+    d_start<VT>(guess, noise, n, st, V0, partial, blockIdx.x, gridDim.x);
 }
 __global__ void __launch_bounds__(kThreads) k_norm_fin(const double* __restrict__ partial, int nrows, dav_state* st) {
     f_norm_fin(partial, nrows, st);
 }
-__global__ void __launch_bounds__(kThreads) k_scale_copy(double* __restrict__ V0, int64_t n, const dav_state* st,
+template <typename VT>
+__global__ void __launch_bounds__(kThreads) k_scale_copy(VT* __restrict__ V0, int64_t n, const dav_state* st,
                                                          double* __restrict__ cin, float* __restrict__ c32) {
-    d_scale_copy(V0, n, st, cin, c32, blockIdx.x, gridDim.x);
+    d_scale_copy<VT>(V0, n, st, cin, c32, blockIdx.x, gridDim.x);
 }
-template <int MT>
-__global__ void __launch_bounds__(kThreads) k_residual(const double* __restrict__ V, const double* __restrict__ AV,
+// dst = src and the |src|^2 partials (the FP64 refinement's first vector,
+// normalised afterwards by k_norm_fin and k_scale_copy)
+__global__ void __launch_bounds__(kThreads) k_copy_norm(const double* __restrict__ src, double* __restrict__ dst,
+                                                        int64_t n, double* __restrict__ partial) {
+    double acc[1] = {0.0};
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+        const double v = src[i];
+        dst[i] = v;
+        acc[0] += v * v;
+    }
+    block_to_partial<1>(acc, partial, blockIdx.x, gridDim.x);
+}
+template <int MT, typename VT>
+__global__ void __launch_bounds__(kThreads) k_residual(const VT* __restrict__ V, const VT* __restrict__ AV,
                                                        const double* __restrict__ diag, int64_t n, const dav_state* st,
                                                        double* __restrict__ T, double* __restrict__ partial) {
-    d_residual<MT>(V, AV, diag, n, st, T, partial, blockIdx.x, gridDim.x);
+    d_residual<MT, VT>(V, AV, diag, n, st, T, partial, blockIdx.x, gridDim.x);
 }
 template <int MT>
 __global__ void __launch_bounds__(kThreads) k_res_fin(const double* __restrict__ partial, int nrows, dav_state* st,
                                                       dav_params prm) {
     f_res_fin<MT>(partial, nrows, st, prm);
 }
-template <int MT>
-__global__ void __launch_bounds__(kThreads) k_collapse(double* __restrict__ V, double* __restrict__ AV, int64_t n,
+template <int MT, typename VT>
+__global__ void __launch_bounds__(kThreads) k_collapse(VT* __restrict__ V, VT* __restrict__ AV, int64_t n,
                                                        const dav_state* st, int force, double* __restrict__ cin) {
-    d_collapse<MT>(V, AV, n, st, force, cin, blockIdx.x, gridDim.x);
+    d_collapse<MT, VT>(V, AV, n, st, force, cin, blockIdx.x, gridDim.x);
 }
 __global__ void k_collapse_fin(dav_state* st, int force) { f_collapse_fin(st, force); }
-template <int MT>
-__global__ void __launch_bounds__(kThreads) k_orth1(const double* __restrict__ V, int64_t n, const dav_state* st,
+template <int MT, typename VT>
+__global__ void __launch_bounds__(kThreads) k_orth1(const VT* __restrict__ V, int64_t n, const dav_state* st,
                                                     double* __restrict__ T, double* __restrict__ partial) {
-    d_orth1<MT>(V, n, st, T, partial, blockIdx.x, gridDim.x);
+    d_orth1<MT, VT>(V, n, st, T, partial, blockIdx.x, gridDim.x);
 }
 template <int MT>
 __global__ void __launch_bounds__(kThreads) k_orth1_fin(const double* __restrict__ partial, int nrows, dav_state* st) {
     f_orth1_fin<MT>(partial, nrows, st);
 }
-template <int MT>
-__global__ void __launch_bounds__(kThreads) k_orth2(double* __restrict__ V, int64_t n, const dav_state* st,
+template <int MT, typename VT>
+__global__ void __launch_bounds__(kThreads) k_orth2(VT* __restrict__ V, int64_t n, const dav_state* st,
                                                     const double* __restrict__ T, double* __restrict__ cin,
                                                     float* __restrict__ c32) {
-    d_orth2<MT>(V, n, st, T, cin, c32, blockIdx.x, gridDim.x);
+    d_orth2<MT, VT>(V, n, st, T, cin, c32, blockIdx.x, gridDim.x);
 }
-template <int MT>
-__global__ void __launch_bounds__(kThreads) k_dots(const double* __restrict__ V, double* __restrict__ AV,
+template <int MT, typename VT>
+__global__ void __launch_bounds__(kThreads) k_dots(const VT* __restrict__ V, VT* __restrict__ AV,
                                                    const double* __restrict__ S, int64_t n, const dav_state* st,
                                                    double* __restrict__ partial) {
-    d_dots<MT>(V, AV, S, n, st, partial, blockIdx.x, gridDim.x);
+    d_dots<MT, VT>(V, AV, S, n, st, partial, blockIdx.x, gridDim.x);
 }
 template <int MT>
 __global__ void __launch_bounds__(kThreads) k_dots_fin(const double* __restrict__ partial, int nrows, dav_state* st) {
     f_dots_fin<MT>(partial, nrows, st);
 }
-template <int MT>
-__global__ void __launch_bounds__(kThreads) k_final(const double* __restrict__ V, int64_t n, const dav_state* st,
+template <int MT, typename VT>
+__global__ void __launch_bounds__(kThreads) k_final(const VT* __restrict__ V, int64_t n, const dav_state* st,
                                                     double* __restrict__ out, double* __restrict__ partial) {
-    d_final<MT>(V, n, st, out, partial, blockIdx.x, gridDim.x);
+    d_final<MT, VT>(V, n, st, out, partial, blockIdx.x, gridDim.x);
 }
 __global__ void k_final_sign(const double* __restrict__ out, dav_state* st) { f_final_sign(out, st); }
 __global__ void __launch_bounds__(kThreads) k_final_scale(double* __restrict__ out, int64_t n, const dav_state* st) {
@@ -138,32 +153,35 @@ inline int grid_for(int64_t n) {
     return (int)b;
 }
 
-// Launch helpers templated on the compile-time basis bound.
-template <int MT>
+// Launch helpers templated on the compile-time basis bound and the storage
+// type of the basis V and its products AV (FP64; FP32 in the FP32 phase of a
+// mixed solve, where FP32 products carry no more digits and the passes over
+// the basis move half the bytes).
+template <int MT, typename VT>
 struct dav_launch {
-    static void residual(int g, hipStream_t s, const double* V, const double* AV, const double* d, int64_t n,
-                         dav_state* st, dav_params p, double* T, double* part) {
-        hipLaunchKernelGGL((k_residual<MT>), dim3(g), dim3(kThreads), 0, s, V, AV, d, n, st, T, part);
+    static void residual(int g, hipStream_t s, const VT* V, const VT* AV, const double* d, int64_t n, dav_state* st,
+                         dav_params p, double* T, double* part) {
+        hipLaunchKernelGGL((k_residual<MT, VT>), dim3(g), dim3(kThreads), 0, s, V, AV, d, n, st, T, part);
         hipLaunchKernelGGL((k_res_fin<MT>), dim3(1), dim3(kThreads), 0, s, part, g, st, p);
     }
-    static void collapse(int g, hipStream_t s, double* V, double* AV, int64_t n, dav_state* st, int force, double* cin) {
-        hipLaunchKernelGGL((k_collapse<MT>), dim3(g), dim3(kThreads), 0, s, V, AV, n, st, force, cin);
+    static void collapse(int g, hipStream_t s, VT* V, VT* AV, int64_t n, dav_state* st, int force, double* cin) {
+        hipLaunchKernelGGL((k_collapse<MT, VT>), dim3(g), dim3(kThreads), 0, s, V, AV, n, st, force, cin);
         hipLaunchKernelGGL(k_collapse_fin, dim3(1), dim3(64), 0, s, st, force);
     }
-    static void orth1(int g, hipStream_t s, const double* V, int64_t n, dav_state* st, double* T, double* part) {
-        hipLaunchKernelGGL((k_orth1<MT>), dim3(g), dim3(kThreads), 0, s, V, n, st, T, part);
+    static void orth1(int g, hipStream_t s, const VT* V, int64_t n, dav_state* st, double* T, double* part) {
+        hipLaunchKernelGGL((k_orth1<MT, VT>), dim3(g), dim3(kThreads), 0, s, V, n, st, T, part);
         hipLaunchKernelGGL((k_orth1_fin<MT>), dim3(1), dim3(kThreads), 0, s, part, g, st);
     }
-    static void orth2(int g, hipStream_t s, double* V, int64_t n, dav_state* st, const double* T, double* cin, float* c32) {
-        hipLaunchKernelGGL((k_orth2<MT>), dim3(g), dim3(kThreads), 0, s, V, n, st, T, cin, c32);
+    static void orth2(int g, hipStream_t s, VT* V, int64_t n, dav_state* st, const double* T, double* cin, float* c32) {
+        hipLaunchKernelGGL((k_orth2<MT, VT>), dim3(g), dim3(kThreads), 0, s, V, n, st, T, cin, c32);
     }
-    static void dots(int g, hipStream_t s, const double* V, double* AV, const double* S, int64_t n, dav_state* st,
+    static void dots(int g, hipStream_t s, const VT* V, VT* AV, const double* S, int64_t n, dav_state* st,
                      double* part) {
-        hipLaunchKernelGGL((k_dots<MT>), dim3(g), dim3(kThreads), 0, s, V, AV, S, n, st, part);
+        hipLaunchKernelGGL((k_dots<MT, VT>), dim3(g), dim3(kThreads), 0, s, V, AV, S, n, st, part);
         hipLaunchKernelGGL((k_dots_fin<MT>), dim3(1), dim3(kThreads), 0, s, part, g, st);
     }
-    static void final_(int g, hipStream_t s, const double* V, int64_t n, dav_state* st, double* out, double* part) {
-        hipLaunchKernelGGL((k_final<MT>), dim3(g), dim3(kThreads), 0, s, V, n, st, out, part);
+    static void final_(int g, hipStream_t s, const VT* V, int64_t n, dav_state* st, double* out, double* part) {
+        hipLaunchKernelGGL((k_final<MT, VT>), dim3(g), dim3(kThreads), 0, s, V, n, st, out, part);
         hipLaunchKernelGGL((k_pick_fin<1>), dim3(1), dim3(kThreads), 0, s, part, g, st);
     }
 };
@@ -189,7 +207,8 @@ struct dav_work {
 template <int MT>
 static int davidson_run(sqd_ctx* ctx, sqd_space* sp, const sqd_davidson_opts* o, double* energy, double* vec,
                         sqd_report* rep, dav_work& w, const dav_params& prm, const double* X, int nx) {
-    using L = dav_launch<MT>;
+    using L = dav_launch<MT, double>;
+    using L32 = dav_launch<MT, float>;
     const auto t0 = std::chrono::steady_clock::now();
     const int64_t n = sp->dim;
     hipStream_t s = ctx->stream;
@@ -207,13 +226,26 @@ static int davidson_run(sqd_ctx* ctx, sqd_space* sp, const sqd_davidson_opts* o,
         hipLaunchKernelGGL(k_argmin, dim3(g), dim3(kThreads), 0, s, diag, n, w.partial);
         hipLaunchKernelGGL((k_pick_fin<0>), dim3(1), dim3(kThreads), 0, s, w.partial, g, w.st);
     }
-    hipLaunchKernelGGL(k_start, dim3(g), dim3(kThreads), 0, s, o->guess_dev, o->guess_noise_dev, n, w.st, w.V,
-                       w.partial);
-    if (nx > 0) {
-        lock_project(g, s, X, nx, w.V, 0, n, w.st, w.cin, w.c32, w.partial);
-    } else {
+    // the FP32 phase of a mixed solve keeps its basis in FP32, in the first
+    // halves of the FP64 buffers (not with locked roots, whose projections
+    // work on FP64 rows)
+    bool basis32 = prm.mixed && nx == 0;
+    float* V32 = reinterpret_cast<float*>(w.V);
+    float* AV32 = reinterpret_cast<float*>(w.AV);
+    if (basis32) {
+        hipLaunchKernelGGL(k_start<float>, dim3(g), dim3(kThreads), 0, s, o->guess_dev, o->guess_noise_dev, n, w.st,
+                           V32, w.partial);
         hipLaunchKernelGGL(k_norm_fin, dim3(1), dim3(kThreads), 0, s, w.partial, g, w.st);
-        hipLaunchKernelGGL(k_scale_copy, dim3(g), dim3(kThreads), 0, s, w.V, n, w.st, w.cin, w.c32);
+        hipLaunchKernelGGL(k_scale_copy<float>, dim3(g), dim3(kThreads), 0, s, V32, n, w.st, w.cin, w.c32);
+    } else {
+        hipLaunchKernelGGL(k_start<double>, dim3(g), dim3(kThreads), 0, s, o->guess_dev, o->guess_noise_dev, n, w.st,
+                           w.V, w.partial);
+        if (nx > 0) {
+            lock_project(g, s, X, nx, w.V, 0, n, w.st, w.cin, w.c32, w.partial);
+        } else {
+            hipLaunchKernelGGL(k_norm_fin, dim3(1), dim3(kThreads), 0, s, w.partial, g, w.st);
+            hipLaunchKernelGGL(k_scale_copy<double>, dim3(g), dim3(kThreads), 0, s, w.V, n, w.st, w.cin, w.c32);
+        }
     }
     const int* skip = &w.st->done;
     int prec = prm.mixed ? SQD_FP32 : SQD_FP64;
@@ -225,7 +257,8 @@ static int davidson_run(sqd_ctx* ctx, sqd_space* sp, const sqd_davidson_opts* o,
                               p == SQD_FP32 ? w.c32 : nullptr, skip);
     };
     if ((rc = product(prec))) return rc;
-    L::dots(g, s, w.V, w.AV, w.sout, n, w.st, w.partial);
+    if (basis32) L32::dots(g, s, V32, AV32, w.sout, n, w.st, w.partial);
+    else L::dots(g, s, w.V, w.AV, w.sout, n, w.st, w.partial);
     if (hipGetLastError() != hipSuccess) return sqd_fail(ctx, SQD_E_HIP, "launch failed in Davidson start");
 
     int enqueued = 0;
@@ -235,14 +268,23 @@ static int davidson_run(sqd_ctx* ctx, sqd_space* sp, const sqd_davidson_opts* o,
         // enqueue check_every iterations, then poll the device flag; kernels of
         // iterations past the end return at once
         for (int k = 0; k < o->check_every; ++k) {
-            L::residual(g, s, w.V, w.AV, diag, n, w.st, prm, w.T, w.partial);
-            L::collapse(g, s, w.V, w.AV, n, w.st, 0, nullptr);
-            L::orth1(g, s, w.V, n, w.st, w.T, w.partial);
-            L::orth2(g, s, w.V, n, w.st, w.T, w.cin, prec == SQD_FP32 ? w.c32 : nullptr);
-            if (nx > 0)
-                lock_project(g, s, X, nx, w.V, 1, n, w.st, w.cin, prec == SQD_FP32 ? w.c32 : nullptr, w.partial);
-            if ((rc = product(prec))) return rc;
-            L::dots(g, s, w.V, w.AV, w.sout, n, w.st, w.partial);
+            if (basis32) {
+                L32::residual(g, s, V32, AV32, diag, n, w.st, prm, w.T, w.partial);
+                L32::collapse(g, s, V32, AV32, n, w.st, 0, nullptr);
+                L32::orth1(g, s, V32, n, w.st, w.T, w.partial);
+                L32::orth2(g, s, V32, n, w.st, w.T, w.cin, w.c32);
+                if ((rc = product(prec))) return rc;
+                L32::dots(g, s, V32, AV32, w.sout, n, w.st, w.partial);
+            } else {
+                L::residual(g, s, w.V, w.AV, diag, n, w.st, prm, w.T, w.partial);
+                L::collapse(g, s, w.V, w.AV, n, w.st, 0, nullptr);
+                L::orth1(g, s, w.V, n, w.st, w.T, w.partial);
+                L::orth2(g, s, w.V, n, w.st, w.T, w.cin, prec == SQD_FP32 ? w.c32 : nullptr);
+                if (nx > 0)
+                    lock_project(g, s, X, nx, w.V, 1, n, w.st, w.cin, prec == SQD_FP32 ? w.c32 : nullptr, w.partial);
+                if ((rc = product(prec))) return rc;
+                L::dots(g, s, w.V, w.AV, w.sout, n, w.st, w.partial);
+            }
             ++enqueued;
         }
         if (hipGetLastError() != hipSuccess) return sqd_fail(ctx, SQD_E_HIP, "launch failed in Davidson loop");
@@ -259,7 +301,18 @@ static int davidson_run(sqd_ctx* ctx, sqd_space* sp, const sqd_davidson_opts* o,
             // its product in FP64, rebuild G[0][0] and continue
             switch_iter = w.st_host->iter;
             prec = SQD_FP64;
-            L::collapse(g, s, w.V, w.AV, n, w.st, 1, w.cin);
+            if (basis32) {
+                // x = V y from the FP32 basis into cin, then V[0] = x / |x|
+                // in FP64 (the FP32 rows are not orthonormal to FP64 accuracy)
+                L32::collapse(g, s, V32, AV32, n, w.st, 1, w.cin);
+                hipLaunchKernelGGL(k_copy_norm, dim3(g), dim3(kThreads), 0, s, w.cin, w.V, n, w.partial);
+                hipLaunchKernelGGL(k_norm_fin, dim3(1), dim3(kThreads), 0, s, w.partial, g, w.st);
+                hipLaunchKernelGGL(k_scale_copy<double>, dim3(g), dim3(kThreads), 0, s, w.V, n, w.st, w.cin,
+                                   nullptr);
+                basis32 = false;
+            } else {
+                L::collapse(g, s, w.V, w.AV, n, w.st, 1, w.cin);
+            }
             hipLaunchKernelGGL(k_set_phase, dim3(1), dim3(64), 0, s, w.st, 1, DONE_RUNNING);
             if ((rc = product(SQD_FP64))) return rc;
             L::dots(g, s, w.V, w.AV, w.sout, n, w.st, w.partial);
@@ -268,7 +321,8 @@ static int davidson_run(sqd_ctx* ctx, sqd_space* sp, const sqd_davidson_opts* o,
         final_done = done;
         break;
     }
-    L::final_(g, s, w.V, n, w.st, vec, w.partial);
+    if (basis32) L32::final_(g, s, V32, n, w.st, vec, w.partial);
+    else L::final_(g, s, w.V, n, w.st, vec, w.partial);
     hipLaunchKernelGGL(k_final_sign, dim3(1), dim3(64), 0, s, vec, w.st);
     hipLaunchKernelGGL(k_final_scale, dim3(g), dim3(kThreads), 0, s, vec, n, w.st);
     if (hipMemcpyAsync(w.st_host, w.st, sizeof(dav_state), hipMemcpyDeviceToHost, s) != hipSuccess ||

@@ -40,7 +40,8 @@ __device__ __forceinline__ void with_rows(int cnt, F&& f) {
 
 // Row k of a block of vectors of length n, clamped to the last valid row
 // (row 0 when the block is empty).
-__device__ __forceinline__ const double* row_ptr(const double* B, int k, int cnt, int64_t n) {
+template <typename VT>
+__device__ __forceinline__ const VT* row_ptr(const VT* B, int k, int cnt, int64_t n) {
     const int r = k < cnt ? k : cnt - 1;
     return B + (int64_t)(r > 0 ? r : 0) * n;
 }
@@ -261,8 +262,9 @@ __device__ __forceinline__ double start_noise(uint64_t stream, int64_t i, int64_
 
 // V0 = guess, or e_kmin + noise (the caller's, else start_noise stream 0);
 // |V0|^2 partials.
+template <typename VT = double>
 __device__ __forceinline__ void d_start(const double* __restrict__ guess, const double* __restrict__ noise,
-                                                    int64_t n, const dav_state* st, double* __restrict__ V0,
+                                                    int64_t n, const dav_state* st, VT* __restrict__ V0,
                                                     double* __restrict__ partial, int64_t bid, int64_t nblk) {
     double acc[1] = {0.0};
     const int64_t kmin = st->kmin;
@@ -270,7 +272,7 @@ __device__ __forceinline__ void d_start(const double* __restrict__ guess, const 
         double v;
         if (guess) v = guess[i];
         else v = (i == kmin ? 1.0 : 0.0) + (noise ? noise[i] : start_noise(0, i, n));
-        V0[i] = v;
+        V0[i] = (VT)v;
         acc[0] += v * v;
     }
     block_to_partial<1>(acc, partial, bid, nblk);
@@ -283,12 +285,13 @@ __device__ __forceinline__ void f_norm_fin(const double* __restrict__ partial, i
 }
 
 // V0 *= tinv; copies into the product input (and its FP32 copy)
-__device__ __forceinline__ void d_scale_copy(double* __restrict__ V0, int64_t n, const dav_state* st,
+template <typename VT = double>
+__device__ __forceinline__ void d_scale_copy(VT* __restrict__ V0, int64_t n, const dav_state* st,
                                                          double* __restrict__ cin, float* __restrict__ c32, int64_t bid, int64_t nblk) {
     const double sc = st->tinv;
     for (int64_t i = (int64_t)bid * kThreads + threadIdx.x; i < n; i += (int64_t)nblk * kThreads) {
-        const double v = V0[i] * sc;
-        V0[i] = v;
+        const double v = (double)V0[i] * sc;
+        V0[i] = (VT)v;
         cin[i] = v;
         if (c32) c32[i] = (float)v;
     }
@@ -296,8 +299,8 @@ __device__ __forceinline__ void d_scale_copy(double* __restrict__ V0, int64_t n,
 
 // Residual, preconditioned correction and the first Gram-Schmidt projection:
 // partial columns 0..MT-1: V^T t; MT: |r|^2; MT+1: |t|^2.
-template <int MT>
-__device__ __forceinline__ void d_residual(const double* __restrict__ V, const double* __restrict__ AV, const double* __restrict__ diag, int64_t n,
+template <int MT, typename VT = double>
+__device__ __forceinline__ void d_residual(const VT* __restrict__ V, const VT* __restrict__ AV, const double* __restrict__ diag, int64_t n,
            const dav_state* st, double* __restrict__ T, double* __restrict__ partial, int64_t bid, int64_t nblk) {
     if (st->done) return;
     const int m = st->m;
@@ -308,8 +311,8 @@ __device__ __forceinline__ void d_residual(const double* __restrict__ V, const d
     with_rows<MT>(m, [&](auto nr_) {
         constexpr int NR = decltype(nr_)::value;
         double y[NR];
-        const double* vr[NR];
-        const double* ar[NR];
+        const VT* vr[NR];
+        const VT* ar[NR];
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
             y[k] = (k < m) ? st->y[k] : 0.0;
@@ -436,8 +439,8 @@ __device__ __forceinline__ void f_res_fin(const double* __restrict__ partial, in
 
 // In-place collapse: V[a] = V qc[a], AV[a] = AV qc[a] for the kept columns a.
 // force = 1 (switch to FP64 refinement): keep x = V y only, AV not kept.
-template <int MT>
-__device__ __forceinline__ void d_collapse(double* __restrict__ V, double* __restrict__ AV, int64_t n, const dav_state* st, int force,
+template <int MT, typename VT = double>
+__device__ __forceinline__ void d_collapse(VT* __restrict__ V, VT* __restrict__ AV, int64_t n, const dav_state* st, int force,
            double* __restrict__ cin, int64_t bid, int64_t nblk) {
     int keep;
     if (force) {
@@ -447,13 +450,16 @@ __device__ __forceinline__ void d_collapse(double* __restrict__ V, double* __res
         keep = st->collapse;
     }
     const int m = st->m;
+    // an FP32 basis leaves the FP64 refinement's first vector to the caller
+    // (it overlaps the FP32 rows still being read): only cin is written
+    const bool wv = !(force && sizeof(VT) < sizeof(double));
     const double* q1p = force ? st->y : st->qc[0];
     const double* q2p = st->qc[1];
     with_rows<MT>(m, [&](auto nr_) {
         constexpr int NR = decltype(nr_)::value;
         double q1[NR], q2[NR];
-        const double* vr[NR];
-        const double* ar[NR];
+        const VT* vr[NR];
+        const VT* ar[NR];
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
             q1[k] = (k < m) ? q1p[k] : 0.0;
@@ -483,11 +489,13 @@ __device__ __forceinline__ void d_collapse(double* __restrict__ V, double* __res
                     a1 += q1[k] * a[k];
                     a2 += q2[k] * a[k];
                 }
-                AV[i] = a1;
-                if (keep == 2) AV[n + i] = a2;
+                AV[i] = (VT)a1;
+                if (keep == 2) AV[n + i] = (VT)a2;
             }
-            V[i] = x1;
-            if (keep == 2) V[n + i] = x2;
+            if (wv) {
+                V[i] = (VT)x1;
+                if (keep == 2) V[n + i] = (VT)x2;
+            }
             if (cin) cin[i] = x1;
         }
     });
@@ -522,8 +530,8 @@ __device__ __forceinline__ void f_collapse_fin(dav_state* st, int force) {
 }
 
 // t1 = t - V h; partial columns 0..MT-1: V^T t1; MT: |t1|^2.
-template <int MT>
-__device__ __forceinline__ void d_orth1(const double* __restrict__ V, int64_t n, const dav_state* st, double* __restrict__ T,
+template <int MT, typename VT = double>
+__device__ __forceinline__ void d_orth1(const VT* __restrict__ V, int64_t n, const dav_state* st, double* __restrict__ T,
         double* __restrict__ partial, int64_t bid, int64_t nblk) {
     if (st->done) return;
     const int m = st->m;
@@ -533,7 +541,7 @@ __device__ __forceinline__ void d_orth1(const double* __restrict__ V, int64_t n,
     with_rows<MT>(m, [&](auto nr_) {
         constexpr int NR = decltype(nr_)::value;
         double h[NR];
-        const double* vr[NR];
+        const VT* vr[NR];
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
             h[k] = (k < m) ? st->h[k] : 0.0;
@@ -578,19 +586,19 @@ __device__ __forceinline__ void f_orth1_fin(const double* __restrict__ partial, 
     }
 }
 
-template <int MT>
-__device__ __forceinline__ void d_orth2(double* __restrict__ V, int64_t n, const dav_state* st, const double* __restrict__ T, double* __restrict__ cin,
+template <int MT, typename VT = double>
+__device__ __forceinline__ void d_orth2(VT* __restrict__ V, int64_t n, const dav_state* st, const double* __restrict__ T, double* __restrict__ cin,
         float* __restrict__ c32, int64_t bid, int64_t nblk) {
     if (st->done) return;
     const int m = st->m;
     const double sc = st->tinv;
     const bool re = st->reortho != 0;
-    double* vm = V + (int64_t)m * n;
+    VT* vm = V + (int64_t)m * n;
     const bool lo = (st->phase == 0) && c32;
     if (!re) {
         for (int64_t i = (int64_t)bid * kThreads + threadIdx.x; i < n; i += (int64_t)nblk * kThreads) {
             const double t = T[i] * sc;
-            vm[i] = t;
+            vm[i] = (VT)t;
             cin[i] = t;
             if (lo) c32[i] = (float)t;
         }
@@ -599,7 +607,7 @@ __device__ __forceinline__ void d_orth2(double* __restrict__ V, int64_t n, const
     with_rows<MT>(m, [&](auto nr_) {
         constexpr int NR = decltype(nr_)::value;
         double h[NR];
-        const double* vr[NR];
+        const VT* vr[NR];
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
             h[k] = (k < m) ? st->h[k] : 0.0;
@@ -613,7 +621,7 @@ __device__ __forceinline__ void d_orth2(double* __restrict__ V, int64_t n, const
 #pragma unroll
             for (int k = 0; k < NR; ++k) t -= h[k] * v[k];
             t *= sc;
-            vm[i] = t;
+            vm[i] = (VT)t;
             cin[i] = t;
             if (lo) c32[i] = (float)t;
         }
@@ -621,19 +629,19 @@ __device__ __forceinline__ void d_orth2(double* __restrict__ V, int64_t n, const
 }
 
 // AV[m] = S; partial columns 0..m: V[k] . S.
-template <int MT>
-__device__ __forceinline__ void d_dots(const double* __restrict__ V, double* __restrict__ AV, const double* __restrict__ S, int64_t n,
+template <int MT, typename VT = double>
+__device__ __forceinline__ void d_dots(const VT* __restrict__ V, VT* __restrict__ AV, const double* __restrict__ S, int64_t n,
        const dav_state* st, double* __restrict__ partial, int64_t bid, int64_t nblk) {
     if (st->done) return;
     const int m = st->m;
     double acc[MT + 1];
 #pragma unroll
     for (int k = 0; k <= MT; ++k) acc[k] = 0.0;
-    double* avm = AV + (int64_t)m * n;
+    VT* avm = AV + (int64_t)m * n;
     const int cnt = m + 1;   // rows 0..m, the new vector included (cnt <= MT)
     with_rows<MT>(cnt, [&](auto nr_) {
         constexpr int NR = decltype(nr_)::value;
-        const double* vr[NR];
+        const VT* vr[NR];
 #pragma unroll
         for (int k = 0; k < NR; ++k) vr[k] = row_ptr(V, k, cnt, n);
         for (int64_t i = (int64_t)bid * kThreads + threadIdx.x; i < n; i += (int64_t)nblk * kThreads) {
@@ -641,7 +649,7 @@ __device__ __forceinline__ void d_dots(const double* __restrict__ V, double* __r
 #pragma unroll
             for (int k = 0; k < NR; ++k) v[k] = vr[k][i];
             const double s = S[i];
-            avm[i] = s;
+            avm[i] = (VT)s;
 #pragma unroll
             for (int k = 0; k < NR; ++k) acc[k] += (k < cnt) ? v[k] * s : 0.0;
         }
@@ -810,8 +818,8 @@ __device__ __forceinline__ void f_dots_fin(const double* __restrict__ partial, i
 }
 
 // Final vector x = V y; per-block largest |x| (lowest index on ties) and |x|^2.
-template <int MT>
-__device__ __forceinline__ void d_final(const double* __restrict__ V, int64_t n, const dav_state* st, double* __restrict__ out,
+template <int MT, typename VT = double>
+__device__ __forceinline__ void d_final(const VT* __restrict__ V, int64_t n, const dav_state* st, double* __restrict__ out,
         double* __restrict__ partial, int64_t bid, int64_t nblk) {
     const int m = st->m;
     __shared__ double sv[kThreads], sn[kThreads];
@@ -821,7 +829,7 @@ __device__ __forceinline__ void d_final(const double* __restrict__ V, int64_t n,
     with_rows<MT>(m, [&](auto nr_) {
         constexpr int NR = decltype(nr_)::value;
         double y[NR];
-        const double* vr[NR];
+        const VT* vr[NR];
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
             y[k] = (k < m) ? st->y[k] : 0.0;
