@@ -161,12 +161,15 @@ __global__ void __launch_bounds__(256) kb_combine(const bdesc* __restrict__ D, c
 }
 
 // ---------------------------------------------------------------- Davidson
-template <int MT>
+// VT: storage of the basis V and its products AV (float in the FP32 phase of a
+// mixed batch, held in the first halves of the FP64 buffers)
+template <int MT, typename VT>
 __global__ void __launch_bounds__(kThreads) kb_residual(const bdesc* __restrict__ D, const int2* __restrict__ units,
                                                         int nunits, double* __restrict__ partial) {
     for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
         const bdesc& d = D[units[u].x];
-        d_residual<MT>(d.V, d.AV, d.diag, d.n, d.st, d.T, partial + (size_t)d.part0 * kPstride, units[u].y, d.nblk);
+        d_residual<MT, VT>(reinterpret_cast<const VT*>(d.V), reinterpret_cast<const VT*>(d.AV), d.diag, d.n, d.st, d.T,
+                           partial + (size_t)d.part0 * kPstride, units[u].y, d.nblk);
         __syncthreads();
     }
 }
@@ -177,13 +180,31 @@ __global__ void __launch_bounds__(kThreads) kb_res_fin(const bdesc* __restrict__
     f_res_fin<MT>(partial + (size_t)d.part0 * kPstride, d.nblk, d.st, prm);
 }
 // force: 0 pending restarts; 1 spaces at their precision switch
-template <int MT>
+template <int MT, typename VT>
 __global__ void __launch_bounds__(kThreads) kb_collapse(const bdesc* __restrict__ D, const int2* __restrict__ units,
                                                         int nunits, int force) {
     for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
         const bdesc& d = D[units[u].x];
         if (force && d.st->done != DONE_SWITCH) continue;
-        d_collapse<MT>(d.V, d.AV, d.n, d.st, force, force ? d.cin : nullptr, units[u].y, d.nblk);
+        d_collapse<MT, VT>(reinterpret_cast<VT*>(d.V), reinterpret_cast<VT*>(d.AV), d.n, d.st, force,
+                           force ? d.cin : nullptr, units[u].y, d.nblk);
+    }
+}
+// Spaces at their switch: V[0] = cin (the Ritz vector formed from an FP32
+// basis) and its |.|^2 partials, normalised by kb_norm_fin / kb_scale_copy.
+__global__ void __launch_bounds__(kThreads) kb_copy_norm(const bdesc* __restrict__ D, const int2* __restrict__ units,
+                                                         int nunits, double* __restrict__ partial) {
+    for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
+        const bdesc& d = D[units[u].x];
+        if (d.st->done != DONE_SWITCH) continue;
+        double acc[1] = {0.0};
+        for (int64_t i = (int64_t)units[u].y * kThreads + threadIdx.x; i < d.n; i += (int64_t)d.nblk * kThreads) {
+            const double v = d.cin[i];
+            d.V[i] = v;
+            acc[0] += v * v;
+        }
+        block_to_partial<1>(acc, partial + (size_t)d.part0 * kPstride, units[u].y, d.nblk);
+        __syncthreads();
     }
 }
 __global__ void kb_collapse_fin(const bdesc* __restrict__ D, int force) {
@@ -196,12 +217,13 @@ __global__ void kb_collapse_fin(const bdesc* __restrict__ D, int force) {
     }
     f_collapse_fin(d.st, 0);
 }
-template <int MT>
+template <int MT, typename VT>
 __global__ void __launch_bounds__(kThreads) kb_orth1(const bdesc* __restrict__ D, const int2* __restrict__ units,
                                                      int nunits, double* __restrict__ partial) {
     for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
         const bdesc& d = D[units[u].x];
-        d_orth1<MT>(d.V, d.n, d.st, d.T, partial + (size_t)d.part0 * kPstride, units[u].y, d.nblk);
+        d_orth1<MT, VT>(reinterpret_cast<const VT*>(d.V), d.n, d.st, d.T, partial + (size_t)d.part0 * kPstride,
+                        units[u].y, d.nblk);
         __syncthreads();
     }
 }
@@ -210,20 +232,21 @@ __global__ void __launch_bounds__(kThreads) kb_orth1_fin(const bdesc* __restrict
     const bdesc& d = D[blockIdx.x];
     f_orth1_fin<MT>(partial + (size_t)d.part0 * kPstride, d.nblk, d.st);
 }
-template <int MT>
+template <int MT, typename VT>
 __global__ void __launch_bounds__(kThreads) kb_orth2(const bdesc* __restrict__ D, const int2* __restrict__ units,
                                                      int nunits, int lowp) {
     for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
         const bdesc& d = D[units[u].x];
-        d_orth2<MT>(d.V, d.n, d.st, d.T, d.cin, lowp ? d.c32 : nullptr, units[u].y, d.nblk);
+        d_orth2<MT, VT>(reinterpret_cast<VT*>(d.V), d.n, d.st, d.T, d.cin, lowp ? d.c32 : nullptr, units[u].y, d.nblk);
     }
 }
-template <int MT>
+template <int MT, typename VT>
 __global__ void __launch_bounds__(kThreads) kb_dots(const bdesc* __restrict__ D, const int2* __restrict__ units,
                                                     int nunits, double* __restrict__ partial) {
     for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
         const bdesc& d = D[units[u].x];
-        d_dots<MT>(d.V, d.AV, d.sout, d.n, d.st, partial + (size_t)d.part0 * kPstride, units[u].y, d.nblk);
+        d_dots<MT, VT>(reinterpret_cast<const VT*>(d.V), reinterpret_cast<VT*>(d.AV), d.sout, d.n, d.st,
+                       partial + (size_t)d.part0 * kPstride, units[u].y, d.nblk);
         __syncthreads();
     }
 }
@@ -247,6 +270,7 @@ __global__ void __launch_bounds__(kThreads) kb_pick_fin(const bdesc* __restrict_
 }
 // Start vector of space b: e_kmin plus start_noise of counter stream b;
 // |V0|^2 partials.
+template <typename VT>
 __global__ void __launch_bounds__(kThreads) kb_start(const bdesc* __restrict__ D, const int2* __restrict__ units,
                                                      int nunits, double* __restrict__ partial) {
     for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
@@ -256,30 +280,40 @@ __global__ void __launch_bounds__(kThreads) kb_start(const bdesc* __restrict__ D
         double acc[1] = {0.0};
         for (int64_t i = (int64_t)units[u].y * kThreads + threadIdx.x; i < d.n; i += (int64_t)d.nblk * kThreads) {
             const double v = (i == kmin ? 1.0 : 0.0) + start_noise((uint64_t)b, i, d.n);
-            d.V[i] = v;
+            reinterpret_cast<VT*>(d.V)[i] = (VT)v;
             acc[0] += v * v;
         }
         block_to_partial<1>(acc, partial + (size_t)d.part0 * kPstride, units[u].y, d.nblk);
         __syncthreads();
     }
 }
-__global__ void __launch_bounds__(kThreads) kb_norm_fin(const bdesc* __restrict__ D, double* __restrict__ partial) {
+// sel 1: only the spaces at their precision switch
+__global__ void __launch_bounds__(kThreads) kb_norm_fin(const bdesc* __restrict__ D, double* __restrict__ partial,
+                                                        int sel) {
     const bdesc& d = D[blockIdx.x];
+    if (sel && d.st->done != DONE_SWITCH) return;
     f_norm_fin(partial + (size_t)d.part0 * kPstride, d.nblk, d.st);
 }
+template <typename VT>
 __global__ void __launch_bounds__(kThreads) kb_scale_copy(const bdesc* __restrict__ D, const int2* __restrict__ units,
-                                                          int nunits, int lowp) {
+                                                          int nunits, int lowp, int sel) {
     for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
         const bdesc& d = D[units[u].x];
-        d_scale_copy(d.V, d.n, d.st, d.cin, lowp ? d.c32 : nullptr, units[u].y, d.nblk);
+        if (sel && d.st->done != DONE_SWITCH) continue;
+        d_scale_copy<VT>(reinterpret_cast<VT*>(d.V), d.n, d.st, d.cin, lowp ? d.c32 : nullptr, units[u].y, d.nblk);
     }
 }
+// b32: spaces still in the FP32 phase (stopped by their cap) hold an FP32 basis
 template <int MT>
 __global__ void __launch_bounds__(kThreads) kb_final(const bdesc* __restrict__ D, const int2* __restrict__ units,
-                                                     int nunits, double* __restrict__ partial) {
+                                                     int nunits, double* __restrict__ partial, int b32) {
     for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
         const bdesc& d = D[units[u].x];
-        d_final<MT>(d.V, d.n, d.st, d.out, partial + (size_t)d.part0 * kPstride, units[u].y, d.nblk);
+        if (b32 && d.st->phase == 0)
+            d_final<MT, float>(reinterpret_cast<const float*>(d.V), d.n, d.st, d.out,
+                               partial + (size_t)d.part0 * kPstride, units[u].y, d.nblk);
+        else
+            d_final<MT, double>(d.V, d.n, d.st, d.out, partial + (size_t)d.part0 * kPstride, units[u].y, d.nblk);
         __syncthreads();
     }
 }
@@ -411,28 +445,49 @@ int batched_run(sqd_ctx* ctx, batch_plan& p, const sqd_davidson_opts* o, double*
     // start vectors e_argmin(H_II), their products, G[0][0]
     hipLaunchKernelGGL(kb_argmin, sgrid(p.vec.n), dim3(kThreads), 0, s, p.D, p.vec.dev, p.vec.n, p.partial);
     hipLaunchKernelGGL((kb_pick_fin<0>), dim3(ns), dim3(kThreads), 0, s, p.D, p.partial);
-    hipLaunchKernelGGL(kb_start, sgrid(p.vec.n), dim3(kThreads), 0, s, p.D, p.vec.dev, p.vec.n, p.partial);
-    hipLaunchKernelGGL(kb_norm_fin, dim3(ns), dim3(kThreads), 0, s, p.D, p.partial);
-    hipLaunchKernelGGL(kb_scale_copy, sgrid(p.vec.n), dim3(kThreads), 0, s, p.D, p.vec.dev, p.vec.n, mixed ? 1 : 0);
-    batched_sigma<R, G, RF>(ctx, p, s, mixed ? SQD_FP32 : SQD_FP64, nw_ss, nw_ab);
-    hipLaunchKernelGGL((kb_dots<MT>), sgrid(p.vec.n), dim3(kThreads), 0, s, p.D, p.vec.dev, p.vec.n, p.partial);
+    // a mixed batch keeps the basis of its FP32 phase in FP32
+    if (mixed) {
+        hipLaunchKernelGGL(kb_start<float>, sgrid(p.vec.n), dim3(kThreads), 0, s, p.D, p.vec.dev, p.vec.n, p.partial);
+        hipLaunchKernelGGL(kb_norm_fin, dim3(ns), dim3(kThreads), 0, s, p.D, p.partial, 0);
+        hipLaunchKernelGGL(kb_scale_copy<float>, sgrid(p.vec.n), dim3(kThreads), 0, s, p.D, p.vec.dev, p.vec.n, 1, 0);
+        batched_sigma<R, G, RF>(ctx, p, s, SQD_FP32, nw_ss, nw_ab);
+        hipLaunchKernelGGL((kb_dots<MT, float>), sgrid(p.vec.n), dim3(kThreads), 0, s, p.D, p.vec.dev, p.vec.n,
+                           p.partial);
+    } else {
+        hipLaunchKernelGGL(kb_start<double>, sgrid(p.vec.n), dim3(kThreads), 0, s, p.D, p.vec.dev, p.vec.n,
+                           p.partial);
+        hipLaunchKernelGGL(kb_norm_fin, dim3(ns), dim3(kThreads), 0, s, p.D, p.partial, 0);
+        hipLaunchKernelGGL(kb_scale_copy<double>, sgrid(p.vec.n), dim3(kThreads), 0, s, p.D, p.vec.dev, p.vec.n, 0, 0);
+        batched_sigma<R, G, RF>(ctx, p, s, SQD_FP64, nw_ss, nw_ab);
+        hipLaunchKernelGGL((kb_dots<MT, double>), sgrid(p.vec.n), dim3(kThreads), 0, s, p.D, p.vec.dev, p.vec.n,
+                           p.partial);
+    }
     hipLaunchKernelGGL((kb_dots_fin<MT>), dim3(ns), dim3(kThreads), 0, s, p.D, p.partial);
     SQD_HIP(ctx, hipGetLastError());
     SQD_HIP(ctx, hipStreamSynchronize(s));
 
-    // one iteration of every space, captured once per precision
-    auto record = [&](int prec) {
-        hipLaunchKernelGGL((kb_residual<MT>), sgrid(p.vec.n), dim3(kThreads), 0, s, p.D, p.vec.dev, p.vec.n, p.partial);
+    // one iteration of every space, captured once per precision (the FP32
+    // one on the FP32 basis)
+    auto record_vt = [&](int prec, auto vt) {
+        using VT = decltype(vt);
+        hipLaunchKernelGGL((kb_residual<MT, VT>), sgrid(p.vec.n), dim3(kThreads), 0, s, p.D, p.vec.dev, p.vec.n,
+                           p.partial);
         hipLaunchKernelGGL((kb_res_fin<MT>), dim3(ns), dim3(kThreads), 0, s, p.D, p.partial, prm);
-        hipLaunchKernelGGL((kb_collapse<MT>), sgrid(p.vec.n), dim3(kThreads), 0, s, p.D, p.vec.dev, p.vec.n, 0);
+        hipLaunchKernelGGL((kb_collapse<MT, VT>), sgrid(p.vec.n), dim3(kThreads), 0, s, p.D, p.vec.dev, p.vec.n, 0);
         hipLaunchKernelGGL(kb_collapse_fin, dim3(ns), dim3(64), 0, s, p.D, 0);
-        hipLaunchKernelGGL((kb_orth1<MT>), sgrid(p.vec.n), dim3(kThreads), 0, s, p.D, p.vec.dev, p.vec.n, p.partial);
+        hipLaunchKernelGGL((kb_orth1<MT, VT>), sgrid(p.vec.n), dim3(kThreads), 0, s, p.D, p.vec.dev, p.vec.n,
+                           p.partial);
         hipLaunchKernelGGL((kb_orth1_fin<MT>), dim3(ns), dim3(kThreads), 0, s, p.D, p.partial);
-        hipLaunchKernelGGL((kb_orth2<MT>), sgrid(p.vec.n), dim3(kThreads), 0, s, p.D, p.vec.dev, p.vec.n,
+        hipLaunchKernelGGL((kb_orth2<MT, VT>), sgrid(p.vec.n), dim3(kThreads), 0, s, p.D, p.vec.dev, p.vec.n,
                            prec == SQD_FP32 ? 1 : 0);
         batched_sigma<R, G, RF>(ctx, p, s, prec, nw_ss, nw_ab);
-        hipLaunchKernelGGL((kb_dots<MT>), sgrid(p.vec.n), dim3(kThreads), 0, s, p.D, p.vec.dev, p.vec.n, p.partial);
+        hipLaunchKernelGGL((kb_dots<MT, VT>), sgrid(p.vec.n), dim3(kThreads), 0, s, p.D, p.vec.dev, p.vec.n,
+                           p.partial);
         hipLaunchKernelGGL((kb_dots_fin<MT>), dim3(ns), dim3(kThreads), 0, s, p.D, p.partial);
+    };
+    auto record = [&](int prec) {
+        if (prec == SQD_FP32) record_vt(prec, 0.0f);
+        else record_vt(prec, 0.0);
     };
     hipGraphExec_t exec[2] = {nullptr, nullptr};
     hipGraph_t graph[2] = {nullptr, nullptr};
@@ -471,10 +526,18 @@ int batched_run(sqd_ctx* ctx, batch_plan& p, const sqd_davidson_opts* o, double*
             SQD_HIP(ctx, hipMemcpy(h.data(), p.states, sizeof(dav_state) * ns, hipMemcpyDeviceToHost));
             for (int b = 0; b < ns; ++b)
                 if (h[b].done == DONE_SWITCH) switch_iter[b] = h[b].iter;
-            hipLaunchKernelGGL((kb_collapse<MT>), sgrid(p.vec.n), dim3(kThreads), 0, s, p.D, p.vec.dev, p.vec.n, 1);
+            // the Ritz vector from the FP32 basis into cin, then V[0] = it,
+            // normalised in FP64
+            hipLaunchKernelGGL((kb_collapse<MT, float>), sgrid(p.vec.n), dim3(kThreads), 0, s, p.D, p.vec.dev, p.vec.n,
+                               1);
+            hipLaunchKernelGGL(kb_copy_norm, sgrid(p.vec.n), dim3(kThreads), 0, s, p.D, p.vec.dev, p.vec.n, p.partial);
+            hipLaunchKernelGGL(kb_norm_fin, dim3(ns), dim3(kThreads), 0, s, p.D, p.partial, 1);
+            hipLaunchKernelGGL(kb_scale_copy<double>, sgrid(p.vec.n), dim3(kThreads), 0, s, p.D, p.vec.dev, p.vec.n,
+                               0, 1);
             hipLaunchKernelGGL(kb_collapse_fin, dim3(ns), dim3(64), 0, s, p.D, 1);
             batched_sigma<R, G, RF>(ctx, p, s, SQD_FP64, nw_ss, nw_ab);
-            hipLaunchKernelGGL((kb_dots<MT>), sgrid(p.vec.n), dim3(kThreads), 0, s, p.D, p.vec.dev, p.vec.n, p.partial);
+            hipLaunchKernelGGL((kb_dots<MT, double>), sgrid(p.vec.n), dim3(kThreads), 0, s, p.D, p.vec.dev, p.vec.n,
+                               p.partial);
             hipLaunchKernelGGL((kb_dots_fin<MT>), dim3(ns), dim3(kThreads), 0, s, p.D, p.partial);
             phase = 1;
             replays = 0;
@@ -487,7 +550,8 @@ int batched_run(sqd_ctx* ctx, batch_plan& p, const sqd_davidson_opts* o, double*
         if (graph[k]) (void)hipGraphDestroy(graph[k]);
     }
     if (rc) return rc;
-    hipLaunchKernelGGL((kb_final<MT>), sgrid(p.vec.n), dim3(kThreads), 0, s, p.D, p.vec.dev, p.vec.n, p.partial);
+    hipLaunchKernelGGL((kb_final<MT>), sgrid(p.vec.n), dim3(kThreads), 0, s, p.D, p.vec.dev, p.vec.n, p.partial,
+                       mixed ? 1 : 0);
     hipLaunchKernelGGL((kb_pick_fin<1>), dim3(ns), dim3(kThreads), 0, s, p.D, p.partial);
     hipLaunchKernelGGL(kb_final_sign, dim3(ns), dim3(64), 0, s, p.D);
     hipLaunchKernelGGL(kb_final_scale, sgrid(p.vec.n), dim3(kThreads), 0, s, p.D, p.vec.dev, p.vec.n);
