@@ -506,7 +506,8 @@ def test_sigma_windowed_same_spin(ctx, name, make, width):
     ct = torch.tensor(c, device="cuda:0")
     ctx.set_tuning(sqd.TUNE_SS_WINDOW, width)
     try:
-        for mask in (TERMS["AA"], TERMS["BB"], TERMS["BB"] | TERMS["DIAG"], TERMS["ALL"]):
+        for mask in (TERMS["AA"], TERMS["BB"], TERMS["BB"] | TERMS["DIAG"], TERMS["AA"] | TERMS["DIAG"],
+                     TERMS["ALL"]):
             ref = osp.sigma(c, mask)
             for prec, bar in ((sqd.FP64, 1e-12), (sqd.FP32, 2e-6)):
                 got = sp.sigma(ct, precision=prec, terms=mask).cpu().numpy()
@@ -558,7 +559,8 @@ def test_sigma_alpha_alpha_column_major(ctx, name, make):
     ct = torch.tensor(c, device="cuda:0")
     ctx.set_tuning(sqd.TUNE_SS_ROWS, 8)
     try:
-        for mask in (TERMS["AA"], TERMS["AA"] | TERMS["BB"], TERMS["ALL"]):
+        for mask in (TERMS["AA"], TERMS["AA"] | TERMS["BB"], TERMS["ALL"], TERMS["AA"] | TERMS["DIAG"],
+                     TERMS["DIAG"] | TERMS["AA"] | TERMS["BB"]):
             ref = osp.sigma(c, mask)
             for prec, bar in ((sqd.FP64, 1e-12), (sqd.FP32, 2e-6)):
                 got = sp.sigma(ct, precision=prec, terms=mask).cpu().numpy()
