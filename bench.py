@@ -51,6 +51,19 @@ COPY_BYTES = 1 << 28
 PROFILES = os.path.join(ROOT, "profiles")
 
 
+def _settle(fn, seconds=0.25):
+    """Run fn (a product) untimed for `seconds`.  After an idle spell the
+    GPU's clocks need some 30 ms of load to come back up (on MI355X the first
+    ~40 products after 0.1-1 s idle run 5-15% slower), so the steady-state
+    figures are taken after this."""
+    import torch
+    t_end = time.perf_counter() + seconds
+    while time.perf_counter() < t_end:
+        for _ in range(8):
+            fn()
+        torch.cuda.synchronize()
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -119,17 +132,6 @@ def main():
         torch.cuda.synchronize()
         return (time.perf_counter() - t) / steps
 
-    def settle(fn, seconds=0.25):
-        # After an idle spell the GPU's clocks take some 30 ms of load to come
-        # back up (the first ~40 sigmas after an idle 0.1-1 s run 5-15% slower
-        # on MI355X); the figures below are steady-state throughput, so the
-        # product runs untimed for a quarter second first.
-        t_end = time.perf_counter() + seconds
-        while time.perf_counter() < t_end:
-            for _ in range(8):
-                fn()
-            torch.cuda.synchronize()
-
     # ---- headline: FP64 sigma, all terms.  The same loop straight after the
     # table build (clocks still ramping) is reported beside it.
     sig64 = lambda: sp.sigma(c, out, precision=sqd.FP64)
@@ -138,7 +140,7 @@ def main():
         t64 = t64_cold = timed(sig64, a.steps, a.warmup)
     else:
         t64_cold = timed(sig64, a.steps, a.warmup)
-        settle(sig64)
+        _settle(sig64)
         t64 = timed(sig64, a.steps, a.warmup)
     log(f"sigma fp64 {t64 * 1e3:.3f} ms (straight after the table build: {t64_cold * 1e3:.3f} ms)")
     if a.profile_only:
@@ -217,7 +219,7 @@ def main():
         dav = {}
         sp.davidson(tol=1e-8, noise=noise, max_iter=5)  # warm-up of every kernel
         for mode, name in ((sqd.DAV_FP64, "fp64"), (sqd.DAV_MIXED, "mixed")):
-            settle(sig64)
+            _settle(sig64)
             t = time.perf_counter()
             E, x, rep = sp.davidson(tol=1e-8, mode=mode, switch_tol=1e-4, noise=noise)
             torch.cuda.synchronize()
@@ -376,7 +378,7 @@ def _secondary_cfg4(a):
         gold = json.load(open(gold_path)) if os.path.exists(gold_path) else None
         ctx.davidson_batched(spaces, tol=1e-8, max_iter=3)   # warm-up of every kernel
         for mode, name in ((sqd.DAV_FP64, "fp64"), (sqd.DAV_MIXED, "mixed")):
-            settle(sig64)
+            torch.cuda.synchronize()
             t = time.perf_counter()
             E, vecs, reps, rc = ctx.davidson_batched(spaces, tol=1e-8, max_iter=600, mode=mode)
             torch.cuda.synchronize()
@@ -448,16 +450,19 @@ def _leg(a, ctx, sp, prob, c, out, info):
         # Davidson (one subspace), next to the single lowest root
         noise = torch.tensor(I.guess_noise(sp.dim), device="cuda:0")
         sp.davidson_block(4, tol=1e-8, max_iter=3)   # warm-up of every kernel
+        sig64 = lambda: sp.sigma(c, out, precision=sqd.FP64)
         for mode, name in ((sqd.DAV_FP64, "fp64"), (sqd.DAV_MIXED, "mixed")):
-            settle(sig64)
+            _settle(sig64)
             t = time.perf_counter()
             E1, _, r1 = sp.davidson(tol=1e-8, mode=mode, noise=noise)
             torch.cuda.synchronize()
             t1 = time.perf_counter() - t
+            _settle(sig64)
             t = time.perf_counter()
             E, X, reps = sp.davidson_roots(4, tol=1e-8, mode=mode, noise=noise, max_iter=400)
             torch.cuda.synchronize()
             tl = time.perf_counter() - t
+            _settle(sig64)
             t = time.perf_counter()
             Eb, Xb, repb = sp.davidson_block(4, tol=1e-8, mode=mode, max_iter=400)
             torch.cuda.synchronize()

@@ -21,6 +21,8 @@
 //              when at least 1e-6 of its norm survives.
 //   products   AV[new] = H V[new] (FP64, or FP32 off-diagonal terms in the
 //              first phase of a mixed solve), then G's new columns V^T AV[new].
+// Basis rows are streamed with non-temporal loads (the basis is larger than
+// the caches; the corrections and c stay cached).
 // All reductions are deterministic: per-block partial sums and one finishing
 // workgroup that adds them in block order.
 #include <chrono>
@@ -132,7 +134,7 @@ __global__ void __launch_bounds__(kThreads) k_bo1(const double* __restrict__ V, 
             const double x = t[i];
             double v[NR];
 #pragma unroll
-            for (int l = 0; l < NR; ++l) v[l] = row_ptr(Vb, l, cnt, n)[i];
+            for (int l = 0; l < NR; ++l) v[l] = __builtin_nontemporal_load(row_ptr(Vb, l, cnt, n) + i);
 #pragma unroll
             for (int l = 0; l < NR; ++l) acc[l] += (l < cnt ? v[l] : 0.0) * x;
             acc[NR] += x * x;
@@ -172,7 +174,7 @@ __global__ void __launch_bounds__(kThreads) k_bo2(const double* __restrict__ V, 
         for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
             double v[NR];
 #pragma unroll
-            for (int l = 0; l < NR; ++l) v[l] = row_ptr(Vb, l, cnt, n)[i];
+            for (int l = 0; l < NR; ++l) v[l] = __builtin_nontemporal_load(row_ptr(Vb, l, cnt, n) + i);
             double x = t[i];
 #pragma unroll
             for (int l = 0; l < NR; ++l) x -= h[l] * (l < cnt ? v[l] : 0.0);
@@ -226,7 +228,7 @@ __global__ void __launch_bounds__(kThreads) k_bo3(double* __restrict__ V, const 
         for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
             double v[NR];
 #pragma unroll
-            for (int l = 0; l < NR; ++l) v[l] = row_ptr(Vb, l, cnt, n)[i];
+            for (int l = 0; l < NR; ++l) v[l] = __builtin_nontemporal_load(row_ptr(Vb, l, cnt, n) + i);
             double x = t[i];
 #pragma unroll
             for (int l = 0; l < NR; ++l) x -= h[l] * (l < cnt ? v[l] : 0.0);
@@ -259,7 +261,7 @@ __global__ void __launch_bounds__(kThreads) k_bproj(const double* __restrict__ V
 #pragma unroll
         for (int j = 0; j < NK; ++j) x[j] = j < nk ? T[(int64_t)j * n + i] : 0.0;
         for (int l = 0; l < m; ++l) {
-            const double v = V[(int64_t)l * n + i];
+            const double v = __builtin_nontemporal_load(V + (int64_t)l * n + i);
 #pragma unroll
             for (int j = 0; j < NK; ++j) x[j] -= Ps[l * NK + j] * v;
         }
@@ -282,7 +284,7 @@ __global__ void __launch_bounds__(kThreads) k_bgcols(const double* __restrict__ 
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
         double v[kGB], w[NB];
 #pragma unroll
-        for (int a = 0; a < kGB; ++a) v[a] = V[(int64_t)(l0 + (a < nl ? a : nl - 1)) * n + i];
+        for (int a = 0; a < kGB; ++a) v[a] = __builtin_nontemporal_load(V + (int64_t)(l0 + (a < nl ? a : nl - 1)) * n + i);
 #pragma unroll
         for (int b = 0; b < NB; ++b) w[b] = AV[(int64_t)(c0 + (b < nc ? b : nc - 1)) * n + i];
 #pragma unroll
@@ -450,7 +452,8 @@ __global__ void __launch_bounds__(kThreads) k_bresid(const double* __restrict__ 
 #pragma unroll
         for (int j = 0; j < K; ++j) { x[j] = 0.0; ax[j] = 0.0; }
         for (int l = 0; l < m; ++l) {
-            const double v = V[(int64_t)l * n + i], av = AV[(int64_t)l * n + i];
+            const double v = __builtin_nontemporal_load(V + (int64_t)l * n + i),
+                         av = __builtin_nontemporal_load(AV + (int64_t)l * n + i);
 #pragma unroll
             for (int j = 0; j < K; ++j) {
                 x[j] += Ys[l * K + j] * v;
@@ -553,7 +556,8 @@ __global__ void __launch_bounds__(kThreads) k_bcombine(const double* __restrict_
 #pragma unroll
         for (int c = 0; c < NK; ++c) { x[c] = 0.0; ax[c] = 0.0; }
         for (int l = 0; l < m; ++l) {
-            const double v = V[(int64_t)l * n + i], av = AV[(int64_t)l * n + i];
+            const double v = __builtin_nontemporal_load(V + (int64_t)l * n + i),
+                         av = __builtin_nontemporal_load(AV + (int64_t)l * n + i);
 #pragma unroll
             for (int c = 0; c < NK; ++c) {
                 x[c] += Zs[l * NK + c] * v;
@@ -610,7 +614,7 @@ __global__ void __launch_bounds__(kThreads) k_bfinal(const double* __restrict__ 
 #pragma unroll
         for (int j = 0; j < K; ++j) x[j] = 0.0;
         for (int l = 0; l < m; ++l) {
-            const double v = V[(int64_t)l * n + i];
+            const double v = __builtin_nontemporal_load(V + (int64_t)l * n + i);
 #pragma unroll
             for (int j = 0; j < K; ++j) x[j] += Ys[l * K + j] * v;
         }
