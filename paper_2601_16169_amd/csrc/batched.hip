@@ -227,10 +227,10 @@ __global__ void __launch_bounds__(kThreads) kb_orth1(const bdesc* __restrict__ D
         __syncthreads();
     }
 }
-template <int MT>
+template <int MT, typename VT>
 __global__ void __launch_bounds__(kThreads) kb_orth1_fin(const bdesc* __restrict__ D, double* __restrict__ partial) {
     const bdesc& d = D[blockIdx.x];
-    f_orth1_fin<MT>(partial + (size_t)d.part0 * kPstride, d.nblk, d.st);
+    f_orth1_fin<MT, VT>(partial + (size_t)d.part0 * kPstride, d.nblk, d.st);
 }
 template <int MT, typename VT>
 __global__ void __launch_bounds__(kThreads) kb_orth2(const bdesc* __restrict__ D, const int2* __restrict__ units,
@@ -477,7 +477,7 @@ int batched_run(sqd_ctx* ctx, batch_plan& p, const sqd_davidson_opts* o, double*
         hipLaunchKernelGGL(kb_collapse_fin, dim3(ns), dim3(64), 0, s, p.D, 0);
         hipLaunchKernelGGL((kb_orth1<MT, VT>), sgrid(p.vec.n), dim3(kThreads), 0, s, p.D, p.vec.dev, p.vec.n,
                            p.partial);
-        hipLaunchKernelGGL((kb_orth1_fin<MT>), dim3(ns), dim3(kThreads), 0, s, p.D, p.partial);
+        hipLaunchKernelGGL((kb_orth1_fin<MT, VT>), dim3(ns), dim3(kThreads), 0, s, p.D, p.partial);
         hipLaunchKernelGGL((kb_orth2<MT, VT>), sgrid(p.vec.n), dim3(kThreads), 0, s, p.D, p.vec.dev, p.vec.n,
                            prec == SQD_FP32 ? 1 : 0);
         batched_sigma<R, G, RF>(ctx, p, s, prec, nw_ss, nw_ab);

@@ -90,9 +90,9 @@ __global__ void __launch_bounds__(kThreads) k_orth1(const VT* __restrict__ V, in
                                                     double* __restrict__ T, double* __restrict__ partial) {
     d_orth1<MT, VT>(V, n, st, T, partial, blockIdx.x, gridDim.x);
 }
-template <int MT>
+template <int MT, typename VT>
 __global__ void __launch_bounds__(kThreads) k_orth1_fin(const double* __restrict__ partial, int nrows, dav_state* st) {
-    f_orth1_fin<MT>(partial, nrows, st);
+    f_orth1_fin<MT, VT>(partial, nrows, st);
 }
 template <int MT, typename VT>
 __global__ void __launch_bounds__(kThreads) k_orth2(VT* __restrict__ V, int64_t n, const dav_state* st,
@@ -170,7 +170,7 @@ struct dav_launch {
     }
     static void orth1(int g, hipStream_t s, const VT* V, int64_t n, dav_state* st, double* T, double* part) {
         hipLaunchKernelGGL((k_orth1<MT, VT>), dim3(g), dim3(kThreads), 0, s, V, n, st, T, part);
-        hipLaunchKernelGGL((k_orth1_fin<MT>), dim3(1), dim3(kThreads), 0, s, part, g, st);
+        hipLaunchKernelGGL((k_orth1_fin<MT, VT>), dim3(1), dim3(kThreads), 0, s, part, g, st);
     }
     static void orth2(int g, hipStream_t s, VT* V, int64_t n, dav_state* st, const double* T, double* cin, float* c32) {
         hipLaunchKernelGGL((k_orth2<MT, VT>), dim3(g), dim3(kThreads), 0, s, V, n, st, T, cin, c32);

@@ -567,7 +567,7 @@ __device__ __forceinline__ void d_orth1(const VT* __restrict__ V, int64_t n, con
     block_to_partial<MT + 1>(acc, partial, bid, nblk);
 }
 
-template <int MT>
+template <int MT, typename VT = double>
 __device__ __forceinline__ void f_orth1_fin(const double* __restrict__ partial, int nrows, dav_state* st) {
     if (st->done) return;
     __shared__ double out[MT + 1];
@@ -581,8 +581,12 @@ __device__ __forceinline__ void f_orth1_fin(const double* __restrict__ partial, 
     }
     const double t1 = out[MT];
     const double nrm2 = t1 - hh;
-    // a second projection only when the first left a visible overlap
-    st->reortho = (hh > 1e-26 * t1) ? 1 : 0;
+    // a second projection only when the first left an overlap above what
+    // the basis rows hold: an FP32 basis is orthonormal to its rounding
+    // (6e-8), so a second pass there cannot improve the stored vector unless
+    // the first left more than 1e-6 of it
+    constexpr double kVisible = sizeof(VT) < sizeof(double) ? 1e-12 : 1e-26;
+    st->reortho = (hh > kVisible * t1) ? 1 : 0;
     if (!(nrm2 > 1e-28 * st->tt0) || !(nrm2 > 0.0)) {
         st->done = (st->rnorm <= 0.0) ? DONE_CONVERGED : DONE_STALLED;
     } else {

@@ -444,6 +444,31 @@ def test_sigma_ab_variants_cfg2(ctx, variant):
     sp.close()
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_sigma_long_beta_rows(ctx, precision):
+    """Rows of 16500 beta strings: in FP64 a row (132,000 bytes) is longer
+    than the gather assembles in LDS, so the alpha-beta sums are added into
+    sigma in place, and the beta-beta term takes the windowed kernel (fewer
+    than two rows fit); sampled rows against the oracle, all terms and the
+    alpha-beta term alone."""
+    torch = need_gpu()
+    banner(f"sigma long beta rows precision={precision}")
+    p = I.small_problem(18, 3, 9, 6, 16500, 31)
+    sp = _space(ctx, p)
+    assert sp.nb == 16500 and sp.nb * 8 > 128 * 1024
+    c = I.random_vector(sp.dim, 24)
+    ct = torch.tensor(c, device="cuda:0")
+    rows = _sampled_rows(sp.dim, 384, 8)
+    osp = core.Space.from_problem(p)
+    tol = 1e-12 if precision == 0 else 2e-6
+    for mask in (TERMS["ALL"], TERMS["AB"]):
+        got = sp.sigma(ct, precision=precision, terms=mask).cpu().numpy()[rows]
+        o = osp.sigma_rows(c, rows, mask)
+        err = np.abs(got - o).max() / np.abs(o).max()
+        assert err <= tol, (mask, err)
+    sp.close()
+
+
 @pytest.mark.slow
 @pytest.mark.parametrize("precision", [0, 1])
 def test_sigma_cfg3_sampled_rows(ctx, precision):
