@@ -203,6 +203,28 @@ __device__ __forceinline__ void ss_block(const ss_args<T>& a, const T* __restric
 #pragma unroll
         for (int r = 0; r < R; ++r) acc[r] = (T)0;
         const int s0 = a.sl_s_off[sl], s1 = a.sl_s_off[sl + 1];
+        const int d0 = a.sl_d_off[sl], d1 = a.sl_d_off[sl + 1];
+        // table entries in flight: sixteen for FP32, whose entries are half
+        // the bytes and whose LDS reads are cheaper; eight for FP64 (measured
+        // on MI355X: sixteen is slower there, with one row or eight)
+        constexpr int kD = sizeof(T) == 4 ? 16 : 8;
+        // with one or two staged rows (long rows: the table streams from
+        // beyond the L2) the first batch of doubles loads while the singles
+        // run (2.56e8 workload, FP32 same-spin: 16.0 -> 14.7 ms; with eight
+        // rows it only costs registers: FP32 90 -> 106 us on the 4.0e6 one)
+        constexpr bool kPre = R <= 2;
+        int nbP[kPre ? kD : 1];
+        T vP[kPre ? kD : 1];
+        const bool pre = kPre && d0 + kD <= d1;
+        if constexpr (kPre) {
+            if (pre) {
+#pragma unroll
+                for (int u = 0; u < kD; ++u) {
+                    nbP[u] = a.d_nbr[(int64_t)(d0 + u) * 64 + lane];
+                    vP[u] = a.d_val[(int64_t)(d0 + u) * 64 + lane];
+                }
+            }
+        }
         auto single = [&](uint32_t e, T v) {
             const int nbr = (int)(e & SQD_NBR_MASK);
             const int pair = (int)((e >> SQD_PAIR_SHIFT) & SQD_PAIR_MASK);
@@ -226,7 +248,6 @@ __device__ __forceinline__ void ss_block(const ss_args<T>& a, const T* __restric
             for (int u = 0; u < 4; ++u) single(e[u], v[u]);
         }
         for (; k < s1; ++k) single(a.s_pk[(int64_t)k * 64 + lane], a.s_val[(int64_t)k * 64 + lane]);
-        const int d0 = a.sl_d_off[sl], d1 = a.sl_d_off[sl + 1];
         auto dbl = [&](int nbr, T v) {
             T xr[R];
             lds_cols<T, R>::load(xs, nbr, xr);
@@ -234,10 +255,13 @@ __device__ __forceinline__ void ss_block(const ss_args<T>& a, const T* __restric
             for (int r = 0; r < R; ++r) acc[r] += v * xr[r];
         };
         k = d0;
-        // table entries in flight: sixteen for FP32, whose entries are half
-        // the bytes and whose LDS reads are cheaper; eight for FP64 (measured
-        // on MI355X: sixteen is slower there, with one row or eight)
-        constexpr int kD = sizeof(T) == 4 ? 16 : 8;
+        if constexpr (kPre) {
+            if (pre) {
+#pragma unroll
+                for (int u = 0; u < kD; ++u) dbl(nbP[u], vP[u]);
+                k += kD;
+            }
+        }
         for (; k + kD <= d1; k += kD) {
             int nbd[kD];
             T v[kD];
