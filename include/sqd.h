@@ -98,7 +98,10 @@ extern "C" {
 #define SQD_TUNE_KH_TILE 5     /* beta targets per KH tile: 32 or 64 (0 = auto) */
 #define SQD_TUNE_AB_VARIANT 6  /* direct alpha-beta kernel: 1 grouped by alpha pair (with an
                                   intermediate of nnz_singles_alpha x nb values and a gather),
-                                  2 staged per target row (no intermediate); 0 = auto */
+                                  2 staged per target row (no intermediate), 3 grouped by
+                                  source string (the same intermediate; auto takes it where
+                                  one FP64 source row is all a pair group can stage);
+                                  0 = auto */
 #define SQD_TUNE_AB_GROUP 7    /* alpha singles per grouped alpha-beta unit: 1,2,4,8 (0 = auto) */
 #define SQD_TUNE_SS_WINDOW 8   /* same-spin term by windows of source strings (rows of C too
                                   long for two to fit in LDS): 0 auto, 1 never, 2 always,

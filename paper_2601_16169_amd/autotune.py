@@ -3,7 +3,8 @@
 Knobs (libsqd tuning keys, 0 = the library's automatic choice):
   same-spin   rows staged per workgroup (1, 2, 4, 8) x waves per workgroup (4, 8, 16)
   alpha-beta  grouped kernel: alpha singles per unit (1, 2, 4, 8) x waves (4, 8, 16);
-              row-staged kernel: sources per pass (1, 2, 4, 8) x waves
+              row-staged kernel: sources per pass (1, 2, 4, 8) x waves;
+              kernel grouped by source string: waves
 
 Tile choices interact through the caches (the alpha-beta intermediate streams
 through the same L2 and Infinity Cache the same-spin tables live in), so every
@@ -39,7 +40,8 @@ SS_KNOBS: List[Setting] = ([(sqd.TUNE_SS_WINDOW, 1, sqd.TUNE_SS_ROWS, r, sqd.TUN
                            + [(sqd.TUNE_SS_WINDOW, 2, sqd.TUNE_SS_ROWS, 0, sqd.TUNE_SS_WAVES, 0)])
 AB_KNOBS: List[Setting] = (
     [(sqd.TUNE_AB_VARIANT, 1, sqd.TUNE_AB_GROUP, g, sqd.TUNE_AB_WAVES, w) for g in (1, 2, 4, 8) for w in (4, 8, 16)]
-    + [(sqd.TUNE_AB_VARIANT, 2, sqd.TUNE_AB_CHUNK, k, sqd.TUNE_AB_WAVES, w) for k in (1, 2, 4, 8) for w in (8, 16)])
+    + [(sqd.TUNE_AB_VARIANT, 2, sqd.TUNE_AB_CHUNK, k, sqd.TUNE_AB_WAVES, w) for k in (1, 2, 4, 8) for w in (8, 16)]
+    + [(sqd.TUNE_AB_VARIANT, 3, sqd.TUNE_AB_WAVES, w) for w in (8, 16)])
 # the batched solver has no row-staged alpha-beta variant
 AB_KNOBS_BATCHED: List[Setting] = [s for s in AB_KNOBS if s[1] == 1]
 ALL_KEYS = (sqd.TUNE_SS_ROWS, sqd.TUNE_SS_WAVES, sqd.TUNE_AB_VARIANT, sqd.TUNE_AB_GROUP, sqd.TUNE_AB_CHUNK,

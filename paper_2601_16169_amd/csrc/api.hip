@@ -114,12 +114,14 @@ static void space_release_device(sqd_space* sp) {
     sqd_free_spin_tables(&sp->sp[1]);
     sqd_free_spin_tables(&sp->sp[0]);
     void* ptrs[] = {sp->diag, sp->ua, sp->ab_grp, sp->ab_chunk_pair, sp->ab_rev, sp->kh_tile_off, sp->kh_pairs,
-                    sp->kh_map, sp->ab_row_order, sp->win_P};
+                    sp->kh_map, sp->ab_row_order, sp->win_P, sp->abs_grp, sp->abs_src};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     sp->diag = sp->ua = nullptr;
     sp->ab_grp = sp->ab_chunk_pair = sp->ab_rev = sp->kh_tile_off = sp->kh_pairs = sp->kh_map = nullptr;
     sp->ab_row_order = nullptr;
+    sp->abs_grp = sp->abs_src = nullptr;
+    sp->abs_G = sp->abs_nchunks = 0;
     sp->win_P = nullptr;
     sp->win_P_bytes = 0;
     sp->ab_G = 0;
@@ -198,7 +200,7 @@ int sqd_set_tuning(sqd_ctx* ctx, int key, int value) {
     if (key < 0 || key >= SQD_TUNE_COUNT) return sqd_fail(ctx, SQD_E_INVALID_ARG, "unknown tuning key");
     static const int allowed[SQD_TUNE_COUNT][5] = {
         {0, 1, 2, 4, 8}, {0, 1, 2, 4, 8}, {0, 4, 8, 16, -1}, {0, 4, 8, 16, -1}, {0, 1, 2, -1, -1}, {0, 32, 64, -1, -1},
-        {0, 1, 2, -1, -1}, {0, 1, 2, 4, 8}, {0, 1, 2, -1, -1}};
+        {0, 1, 2, 3, -1}, {0, 1, 2, 4, 8}, {0, 1, 2, -1, -1}};
     bool ok = false;
     for (int v : allowed[key]) ok |= (v == value);
     // same-spin windows: also an explicit window width (a multiple of 64)

@@ -220,6 +220,17 @@ k_ab_grouped(abg_args<T> a, const T* __restrict__ V, int norb, const int* __rest
     abg_block<T, G>(a, V, norb, blockIdx.x, lds_raw);
 }
 
+// ---------------------------------------------------------------- alpha-beta, grouped by source string
+// (body and layout: abs_block); the same gather follows.
+template <typename T, int GS>
+__global__ void __launch_bounds__(1024)
+k_ab_srcgrouped(abg_args<T> a, const int* __restrict__ chunk_src, const T* __restrict__ V, int norb,
+                const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    abs_block<T, GS>(a, chunk_src, V, norb, blockIdx.x, lds_raw);
+}
+
 // sigma[ia][perm(p)] += sum_{e = a_off[ia]}^{a_off[ia+1]-1} Y[e][p] (gather_row),
 // one workgroup per alpha row; STAGED: the row is assembled in LDS first.
 template <typename T, bool STAGED>
@@ -414,9 +425,27 @@ int ab_group_size(sqd_ctx* ctx, const sqd_space* sp) {
     return 0;
 }
 
+// Gather order: heaviest alpha rows first, so that the rows with the most
+// singles start together on different compute units.
+int ensure_ab_row_order(sqd_ctx* ctx, sqd_space* sp) {
+    if (sp->ab_row_order) return SQD_OK;
+    const spin_tables& A = sp->sp[0];
+    std::vector<int> off(A.n + 1);
+    SQD_HIP(ctx, hipMemcpy(off.data(), A.s_off, sizeof(int) * (A.n + 1), hipMemcpyDeviceToHost));
+    std::vector<int> order(A.n);
+    for (int64_t r = 0; r < A.n; ++r) order[r] = (int)r;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return off[x + 1] - off[x] > off[y + 1] - off[y]; });
+    int rc;
+    if ((rc = sqd_alloc(ctx, (void**)&sp->ab_row_order, sizeof(int) * (A.n + 1), &sp->bytes))) return rc;
+    SQD_HIP(ctx, hipMemcpy(sp->ab_row_order, order.data(), sizeof(int) * A.n, hipMemcpyHostToDevice));
+    return SQD_OK;
+}
+
 // Group the alpha singles (CSR positions) by orbital pair, padded to chunks of G.
 int ensure_ab_groups_impl(sqd_ctx* ctx, sqd_space* sp, int G) {
     if (sp->ab_G == G && sp->ab_grp) return SQD_OK;
+    if (G <= 0) return sqd_fail(ctx, SQD_E_LIMIT, "alpha-beta group does not fit in LDS");
     const spin_tables& A = sp->sp[0];
     std::vector<uint32_t> pk(A.nnz_s);
     if (A.nnz_s > 0)
@@ -435,18 +464,7 @@ int ensure_ab_groups_impl(sqd_ctx* ctx, sqd_space* sp, int G) {
     if (sp->ab_grp) { (void)hipFree(sp->ab_grp); sp->ab_grp = nullptr; }
     if (sp->ab_chunk_pair) { (void)hipFree(sp->ab_chunk_pair); sp->ab_chunk_pair = nullptr; }
     int rc;
-    if (!sp->ab_row_order) {
-        // gather order: heaviest alpha rows first, so that the rows with the
-        // most singles start together on different compute units
-        std::vector<int> off(A.n + 1);
-        SQD_HIP(ctx, hipMemcpy(off.data(), A.s_off, sizeof(int) * (A.n + 1), hipMemcpyDeviceToHost));
-        std::vector<int> order(A.n);
-        for (int64_t r = 0; r < A.n; ++r) order[r] = (int)r;
-        std::stable_sort(order.begin(), order.end(),
-                         [&](int x, int y) { return off[x + 1] - off[x] > off[y + 1] - off[y]; });
-        if ((rc = sqd_alloc(ctx, (void**)&sp->ab_row_order, sizeof(int) * (A.n + 1), &sp->bytes))) return rc;
-        SQD_HIP(ctx, hipMemcpy(sp->ab_row_order, order.data(), sizeof(int) * A.n, hipMemcpyHostToDevice));
-    }
+    if ((rc = ensure_ab_row_order(ctx, sp))) return rc;
     if ((rc = sqd_alloc(ctx, (void**)&sp->ab_grp, sizeof(int) * (grp.size() + 1), &sp->bytes))) return rc;
     if ((rc = sqd_alloc(ctx, (void**)&sp->ab_chunk_pair, sizeof(int) * (cp.size() + 1), &sp->bytes))) return rc;
     if (!grp.empty()) {
@@ -458,11 +476,61 @@ int ensure_ab_groups_impl(sqd_ctx* ctx, sqd_space* sp, int G) {
     return SQD_OK;
 }
 
+// Singles per chunk of the source-grouped kernel: the most (ai|..) rows that
+// fit in LDS beside one FP64 source row (0: fewer than two).
+int ab_source_group_size(sqd_ctx* ctx, const sqd_space* sp) {
+    const size_t nb = (size_t)sp->sp[1].n, n2 = (size_t)sp->norb * sp->norb;
+    auto bytes = [&](int G) { return (nb + 1) * sizeof(double) + (size_t)G * n2 * sizeof(double); };
+    for (int G : {8, 4, 3, 2}) if (bytes(G) <= (size_t)ctx->max_lds) return G;
+    return 0;
+}
+
+// The source-grouped kernel is taken where the pair-grouped chunks would
+// hold a single source row (2.56e8 workload: 16000-string FP64 rows), or
+// when forced (SQD_TUNE_AB_VARIANT 3).
+bool ab_use_source_groups(sqd_ctx* ctx, const sqd_space* sp) {
+    const int variant = ctx->tune[SQD_TUNE_AB_VARIANT];
+    if (variant == 3) return ab_source_group_size(ctx, sp) > 0;
+    if (variant != 0 || ctx->tune[SQD_TUNE_AB_GROUP]) return false;
+    return ab_group_size(ctx, sp) == 1 && ab_source_group_size(ctx, sp) >= 2;
+}
+
+// Group the alpha singles (CSR positions) by source string, padded to chunks of G.
+int ensure_ab_source_groups(sqd_ctx* ctx, sqd_space* sp, int G) {
+    if (sp->abs_G == G && sp->abs_grp) return SQD_OK;
+    const spin_tables& A = sp->sp[0];
+    std::vector<uint32_t> pk(A.nnz_s);
+    if (A.nnz_s > 0)
+        SQD_HIP(ctx, hipMemcpy(pk.data(), A.s_pk, sizeof(uint32_t) * A.nnz_s, hipMemcpyDeviceToHost));
+    std::vector<std::vector<int>> by(A.n);
+    for (int64_t e = 0; e < A.nnz_s; ++e) by[pk[e] & SQD_NBR_MASK].push_back((int)e);
+    std::vector<int> grp, cs;
+    for (int64_t j = 0; j < A.n; ++j) {
+        const auto& v = by[j];
+        for (size_t k = 0; k < v.size(); k += G) {
+            for (int r = 0; r < G; ++r) grp.push_back(k + r < v.size() ? v[k + r] : -1);
+            cs.push_back((int)j);
+        }
+    }
+    if (sp->abs_grp) { (void)hipFree(sp->abs_grp); sp->abs_grp = nullptr; }
+    if (sp->abs_src) { (void)hipFree(sp->abs_src); sp->abs_src = nullptr; }
+    int rc;
+    if ((rc = sqd_alloc(ctx, (void**)&sp->abs_grp, sizeof(int) * (grp.size() + 1), &sp->bytes))) return rc;
+    if ((rc = sqd_alloc(ctx, (void**)&sp->abs_src, sizeof(int) * (cs.size() + 1), &sp->bytes))) return rc;
+    if (!grp.empty()) {
+        SQD_HIP(ctx, hipMemcpy(sp->abs_grp, grp.data(), sizeof(int) * grp.size(), hipMemcpyHostToDevice));
+        SQD_HIP(ctx, hipMemcpy(sp->abs_src, cs.data(), sizeof(int) * cs.size(), hipMemcpyHostToDevice));
+    }
+    sp->abs_G = G;
+    sp->abs_nchunks = (int)cs.size();
+    return SQD_OK;
+}
+
 // Y bytes of the grouped alpha-beta path (0 if it is not to be used).
 size_t ab_grouped_bytes(sqd_ctx* ctx, const sqd_space* sp, size_t es) {
     const int variant = ctx->tune[SQD_TUNE_AB_VARIANT];
     if (variant == 2) return 0;
-    if (ab_group_size(ctx, sp) == 0) return 0;
+    if (ab_group_size(ctx, sp) == 0 && !ab_use_source_groups(ctx, sp)) return 0;
     const size_t bytes = (size_t)sp->sp[0].nnz_s * (size_t)sp->sp[1].nslices * 64 * es;
     const size_t cap = (size_t)64 << 30;   // keep the intermediate below 64 GiB
     if (variant == 0 && bytes > cap) return 0;
@@ -473,9 +541,33 @@ template <typename T>
 int launch_ab_grouped(sqd_ctx* ctx, sqd_space* sp, const T* C, T* S, T* Y, const T* V, const int* skip) {
     const spin_tables& A = sp->sp[0];
     const spin_tables& B = sp->sp[1];
+    int rc;
+    if (ab_use_source_groups(ctx, sp)) {
+        const int GS = ab_source_group_size(ctx, sp);
+        if ((rc = ensure_ab_row_order(ctx, sp)) || (rc = ensure_ab_source_groups(ctx, sp, GS))) return rc;
+        if (sp->abs_nchunks > 0) {
+            const size_t lds = ((size_t)(B.n + 1) + (size_t)GS * sp->norb * sp->norb) * sizeof(T);
+            const int nw = ctx->tune[SQD_TUNE_AB_WAVES] ? ctx->tune[SQD_TUNE_AB_WAVES] : 16;
+            abg_args<T> args{C, Y, B.n, (int64_t)B.nslices * 64, sp->abs_grp, nullptr, A.s_pk, B.perm_ab,
+                             B.nslices, B.sl_ab_off, B.sell_ab_pk};
+            prof_scope ps(ctx, sizeof(T) == 8 ? "k_ab_srcgrouped<double>" : "k_ab_srcgrouped<float>");
+#define SQD_ABS_LAUNCH(GG)                                                                                    \
+    case GG:                                                                                                  \
+        set_lds(k_ab_srcgrouped<T, GG>, (int)lds);                                                            \
+        hipLaunchKernelGGL((k_ab_srcgrouped<T, GG>), dim3(sp->abs_nchunks), dim3(64 * nw), lds, ctx->stream,    \
+                           args, sp->abs_src, V, sp->norb, skip);                                             \
+        break;
+            switch (GS) {
+                SQD_ABS_LAUNCH(2)
+                SQD_ABS_LAUNCH(3)
+                SQD_ABS_LAUNCH(4)
+                SQD_ABS_LAUNCH(8)
+            }
+#undef SQD_ABS_LAUNCH
+        }
+    } else {
     const int G = ab_group_size(ctx, sp);
-    int rc = ensure_ab_groups_impl(ctx, sp, G);
-    if (rc) return rc;
+    if ((rc = ensure_ab_groups_impl(ctx, sp, G))) return rc;
     if (sp->ab_nchunks > 0) {
         const size_t lds = ((size_t)(B.n + 1) * G + (size_t)sp->norb * sp->norb) * sizeof(T);
         // measured on MI355X: 16 waves for FP64, and for FP32 when few rows
@@ -498,6 +590,7 @@ int launch_ab_grouped(sqd_ctx* ctx, sqd_space* sp, const T* C, T* S, T* Y, const
             SQD_ABG_LAUNCH(8)
         }
 #undef SQD_ABG_LAUNCH
+    }
     }
     const unsigned gx = (unsigned)std::min<int64_t>(A.n, 1 << 20);
     prof_scope ps(ctx, sizeof(T) == 8 ? "k_ab_gather<double>" : "k_ab_gather<float>");
@@ -571,6 +664,8 @@ bool sqd_sigma_prepared(sqd_ctx* ctx, const sqd_space* sp, int precision, unsign
     if (ab_path == SQD_AB_KH) return sp->kh_map != nullptr && sp->ab_rev != nullptr;
     const size_t es = precision == SQD_FP64 ? 8 : 4;
     if (ab_grouped_bytes(ctx, sp, es) == 0) return true;   // row-staged kernel: nothing per space
+    if (ab_use_source_groups(ctx, sp))
+        return sp->abs_grp != nullptr && sp->abs_G == ab_source_group_size(ctx, sp) && sp->ab_row_order != nullptr;
     return sp->ab_grp != nullptr && sp->ab_G == ab_group_size(ctx, sp) && sp->ab_row_order != nullptr;
 }
 

@@ -442,6 +442,93 @@ __device__ __forceinline__ void abg_block(const abg_args<T>& a, const T* __restr
     }
 }
 
+// The same Y from chunks of up to GS alpha singles that share their source
+// string (chunk_src): one staged row of C serves GS pairs, whose (ai|..) rows
+// are staged beside it.  Where a row of C fills most of the LDS (long rows,
+// where the pair-grouped chunks hold one single) this reads 8 bytes of LDS
+// per table entry for C and 8 per single for the integral, (8 + 8 GS) / GS
+// bytes per connection instead of 16, and stages each source row once per GS
+// singles.  Same products and summation order as abg_block.
+template <typename T, int GS>
+__device__ __forceinline__ void abs_block(const abg_args<T>& a, const int* __restrict__ chunk_src,
+                                          const T* __restrict__ V, int norb, int64_t chunk, unsigned char* lds_raw) {
+    T* xs = reinterpret_cast<T*>(lds_raw);   // the source row, column nb zero
+    const int norb2 = norb * norb;
+    const int64_t nb = a.nb;
+    T* vrows = xs + (nb + 1);                // GS rows of (ai|..), row g at g * norb2
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int64_t src = chunk_src[chunk];
+    int e[GS], pr[GS];
+    T sgn[GS];
+#pragma unroll
+    for (int g = 0; g < GS; ++g) {
+        e[g] = a.grp[chunk * GS + g];
+        const uint32_t x = e[g] >= 0 ? a.a_pk[e[g]] : 0u;
+        sgn[g] = (x >> 31) ? (T)-1 : (T)1;
+        pr[g] = (int)((x >> SQD_PAIR_SHIFT) & SQD_PAIR_MASK);
+    }
+    const T* crow = a.C + src * nb;
+    for (int64_t k = tid; k < nb; k += nthr) xs[k] = crow[k];
+    if (tid == 0) xs[nb] = (T)0;
+    for (int q = tid; q < GS * norb2; q += nthr) {
+        const int g = q / norb2, r = q - g * norb2;
+        vrows[q] = e[g] >= 0 ? V[(int64_t)pr[g] * norb2 + r] : (T)0;
+    }
+    __syncthreads();
+    const int wave = tid >> 6, lane = tid & 63, nw = nthr >> 6;
+    for (int sl = wave; sl < a.nbslices; sl += nw) {
+        T acc[GS];
+#pragma unroll
+        for (int g = 0; g < GS; ++g) acc[g] = (T)0;
+        const int c0 = a.bsl_off[sl], c1 = a.bsl_off[sl + 1];
+        auto one = [&](uint32_t b) {
+            const int nbr = (int)(b & SQD_NBR_MASK);
+            const int pb = (int)((b >> SQD_PAIR_SHIFT) & SQD_PAIR_MASK);
+            T x = xs[nbr];
+            T v[GS];
+#pragma unroll
+            for (int g = 0; g < GS; ++g) v[g] = vrows[g * norb2 + pb];
+            if (b >> 31) {
+#pragma unroll
+                for (int g = 0; g < GS; ++g) v[g] = -v[g];
+            }
+#pragma unroll
+            for (int g = 0; g < GS; ++g) acc[g] += v[g] * x;
+        };
+        int col = c0;
+        constexpr int kD = 16;   // table entries in flight
+        for (; col + kD <= c1; col += kD) {
+            uint32_t bd[kD];
+#pragma unroll
+            for (int u = 0; u < kD; ++u) bd[u] = a.bs_pk[(int64_t)(col + u) * 64 + lane];
+#pragma unroll
+            for (int u = 0; u < kD; ++u) one(bd[u]);
+        }
+        if (col + 8 <= c1) {
+            uint32_t b8[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) b8[u] = a.bs_pk[(int64_t)(col + u) * 64 + lane];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) one(b8[u]);
+            col += 8;
+        }
+        if (col + 4 <= c1) {
+            uint32_t b4[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) b4[u] = a.bs_pk[(int64_t)(col + u) * 64 + lane];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) one(b4[u]);
+            col += 4;
+        }
+        for (; col < c1; ++col) one(a.bs_pk[(int64_t)col * 64 + lane]);
+        // padding lanes read only the zero column: their value is zero
+        const int64_t slot = (int64_t)sl * 64 + lane;
+#pragma unroll
+        for (int g = 0; g < GS; ++g)
+            if (e[g] >= 0) __builtin_nontemporal_store(sgn[g] * acc[g], a.Y + (int64_t)e[g] * a.ldy + slot);
+    }
+}
+
 // sigma[ia][perm(p)] += sum_{e in row ia} Y[e][p] over all slots p of row ia,
 // one workgroup per row: each thread reads two adjacent slots with
 // one vector load (ldy is a multiple of 64), eight rows of Y in flight.  Y is

@@ -170,6 +170,12 @@ struct sqd_space {
     int* ab_chunk_pair = nullptr; // pair index of each chunk
     int* ab_rev = nullptr;        // alpha singles: entry of the neighbour's row pointing back
     int* ab_row_order = nullptr;  // alpha rows by decreasing number of singles (gather order)
+    // the same singles grouped by source string (rows too long for two
+    // staged sources: one staged source row serves several pairs)
+    int abs_G = 0;
+    int abs_nchunks = 0;
+    int* abs_grp = nullptr;       // abs_nchunks * abs_G CSR positions (-1 = padding)
+    int* abs_src = nullptr;       // source alpha string of each chunk
     // Knowles-Handy beta tiles (64 targets each): the union of the pair columns
     // their singles use, and for every (target, column) the source of that
     // single (0: none, else source + 1, bit 31 = negative sign)

@@ -419,10 +419,41 @@ def test_sigma_ab_knowles_handy(ctx, name, make, precision):
     sp.close()
 
 
-@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("name,make", SMALL + [("src_long_rows_16_3_6", lambda: I.small_problem(16, 3, 6, 24, 8008, 12))])
+def test_sigma_ab_source_grouped(ctx, name, make):
+    """The alpha-beta kernel grouped by source string (SQD_TUNE_AB_VARIANT 3)
+    against the oracle, FP64 <= 1e-12 and FP32 <= 2e-6, and bit for bit
+    against the pair-grouped kernel (same products, same summation order),
+    on ragged and degenerate spaces and on 8008-string beta rows."""
+    torch = need_gpu()
+    from paper_2601_16169_amd import sqd
+    banner(f"sigma ab source-grouped {name}")
+    p = make()
+    sp = _space(ctx, p)
+    c = I.random_vector(sp.dim, 25)
+    ct = torch.tensor(c, device="cuda:0")
+    o = core.Space.from_problem(p).sigma(c, TERMS["AB"])
+    for prec, tol in ((0, 1e-12), (1, 2e-6)):
+        try:
+            ctx.set_tuning(sqd.TUNE_AB_VARIANT, 3)
+            s3 = sp.sigma(ct, precision=prec, terms=TERMS["AB"]).cpu().numpy()
+            ctx.set_tuning(sqd.TUNE_AB_VARIANT, 1)
+            s1 = sp.sigma(ct, precision=prec, terms=TERMS["AB"]).cpu().numpy()
+        finally:
+            ctx.set_tuning(sqd.TUNE_AB_VARIANT, 0)
+        assert np.array_equal(s3, s1), (prec, np.abs(s3 - s1).max())
+        if np.abs(o).max() == 0.0:
+            assert np.abs(s3).max() == 0.0
+        else:
+            assert max(rel_err(s3, o)) <= tol, (prec, rel_err(s3, o))
+    sp.close()
+
+
+@pytest.mark.parametrize("variant", [1, 2, 3])
 def test_sigma_ab_variants_cfg2(ctx, variant):
-    """Both direct alpha-beta kernels (grouped, row-staged) and KH agree on
-    the 4.0e6-determinant workload (sampled rows against the oracle)."""
+    """The direct alpha-beta kernels (grouped by pair, row-staged, grouped by
+    source) and KH agree on the 4.0e6-determinant workload (sampled rows
+    against the oracle)."""
     torch = need_gpu()
     from paper_2601_16169_amd import sqd
     p = I.cfg2()
