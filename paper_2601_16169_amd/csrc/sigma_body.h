@@ -485,18 +485,14 @@ __device__ __forceinline__ void abs_block(const abg_args<T>& a, const int* __res
             const int nbr = (int)(b & SQD_NBR_MASK);
             const int pb = (int)((b >> SQD_PAIR_SHIFT) & SQD_PAIR_MASK);
             T x = xs[nbr];
-            T v[GS];
+            if (b >> 31) x = -x;   // (-v) x = v (-x) exactly
 #pragma unroll
-            for (int g = 0; g < GS; ++g) v[g] = vrows[g * norb2 + pb];
-            if (b >> 31) {
-#pragma unroll
-                for (int g = 0; g < GS; ++g) v[g] = -v[g];
-            }
-#pragma unroll
-            for (int g = 0; g < GS; ++g) acc[g] += v[g] * x;
+            for (int g = 0; g < GS; ++g) acc[g] += vrows[g * norb2 + pb] * x;
         };
         int col = c0;
-        constexpr int kD = 16;   // table entries in flight
+        // table entries in flight: sixteen while GS rows leave the registers
+        // for them (with GS = 8 FP64 sixteen entries spilled)
+        constexpr int kD = GS <= 3 ? 16 : 8;
         for (; col + kD <= c1; col += kD) {
             uint32_t bd[kD];
 #pragma unroll
@@ -504,7 +500,7 @@ __device__ __forceinline__ void abs_block(const abg_args<T>& a, const int* __res
 #pragma unroll
             for (int u = 0; u < kD; ++u) one(bd[u]);
         }
-        if (col + 8 <= c1) {
+        if (kD > 8 && col + 8 <= c1) {
             uint32_t b8[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) b8[u] = a.bs_pk[(int64_t)(col + u) * 64 + lane];
