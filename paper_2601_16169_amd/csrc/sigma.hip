@@ -486,13 +486,20 @@ int ab_source_group_size(sqd_ctx* ctx, const sqd_space* sp) {
 }
 
 // The source-grouped kernel is taken where the pair-grouped chunks would
-// hold a single source row (2.56e8 workload: 16000-string FP64 rows), or
-// when forced (SQD_TUNE_AB_VARIANT 3).
+// hold one or two source rows, or when forced (SQD_TUNE_AB_VARIANT 3).
+// Every chunk walks the whole beta table, so grouping more singles per chunk
+// cuts the table stream as well as the staging; measured on MI355X
+// (alpha-beta FP64 / FP32): 16000-string rows (pair groups of one) 24.8 /
+// 14.5 -> 13.8 / 8.5 ms, the full-CI 14-orbital space (pair groups of two,
+// 49 singles per source) 6.3 / 4.8 -> 3.8 / 2.8 ms, while on the 4.0e6
+// workload (pair groups of four, 17 singles per source) the pair groups win
+// (278 against 333 us).
 bool ab_use_source_groups(sqd_ctx* ctx, const sqd_space* sp) {
     const int variant = ctx->tune[SQD_TUNE_AB_VARIANT];
     if (variant == 3) return ab_source_group_size(ctx, sp) > 0;
     if (variant != 0 || ctx->tune[SQD_TUNE_AB_GROUP]) return false;
-    return ab_group_size(ctx, sp) == 1 && ab_source_group_size(ctx, sp) >= 2;
+    const int G = ab_group_size(ctx, sp);
+    return G >= 1 && G <= 2 && ab_source_group_size(ctx, sp) > G;
 }
 
 // Group the alpha singles (CSR positions) by source string, padded to chunks of G.

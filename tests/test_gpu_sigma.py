@@ -449,6 +449,29 @@ def test_sigma_ab_source_grouped(ctx, name, make):
     sp.close()
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_sigma_full14_sampled_rows(ctx, precision):
+    """The full-CI 14-orbital space (3432 strings per spin, dim 1.18e7),
+    where the automatic alpha-beta path groups the singles by source string
+    (pair groups would hold two source rows): 320 sampled rows of the whole
+    product and of the alpha-beta term against the oracle."""
+    torch = need_gpu()
+    banner(f"sigma full14 sampled precision={precision}")
+    p = I.full14()
+    sp = _space(ctx, p)
+    c = I.random_vector(sp.dim, 26)
+    ct = torch.tensor(c, device="cuda:0")
+    rows = _sampled_rows(sp.dim, 320, 9)
+    osp = core.Space.from_problem(p)
+    tol = 1e-12 if precision == 0 else 2e-6
+    for mask in (TERMS["ALL"], TERMS["AB"]):
+        got = sp.sigma(ct, precision=precision, terms=mask)[torch.tensor(rows, device="cuda:0")].cpu().numpy()
+        o = osp.sigma_rows(c, rows, mask)
+        err = np.abs(got - o).max() / np.abs(o).max()
+        assert err <= tol, (mask, err)
+    sp.close()
+
+
 @pytest.mark.parametrize("variant", [1, 2, 3])
 def test_sigma_ab_variants_cfg2(ctx, variant):
     """The direct alpha-beta kernels (grouped by pair, row-staged, grouped by
