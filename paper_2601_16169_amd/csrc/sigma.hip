@@ -491,7 +491,7 @@ int ab_source_group_size(sqd_ctx* ctx, const sqd_space* sp) {
 // cuts the table stream as well as the staging; measured on MI355X
 // (alpha-beta FP64 / FP32): 16000-string rows (pair groups of one) 24.8 /
 // 14.5 -> 13.8 / 8.5 ms, the full-CI 14-orbital space (pair groups of two,
-// 49 singles per source) 6.3 / 4.8 -> 3.8 / 2.8 ms, while on the 4.0e6
+// 49 singles per source) 6.1 / 4.7 -> 3.6 / 2.8 ms, while on the 4.0e6
 // workload (pair groups of four, 17 singles per source) the pair groups win
 // (278 against 333 us).
 bool ab_use_source_groups(sqd_ctx* ctx, const sqd_space* sp) {
