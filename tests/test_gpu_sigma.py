@@ -121,15 +121,18 @@ def test_sigma_terms_fp32(ctx, name, make, term):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-def test_sigma_graph_capture_replays(precision):
+@pytest.mark.parametrize("ab_variant", [0, 3])
+def test_sigma_graph_capture_replays(precision, ab_variant):
     """sqd_sigma captured in a HIP graph (after a warm-up call has set up the
     tables and scratch) replays to the eager result, every replay, with eager
-    library work and synchronisations between the replays."""
+    library work and synchronisations between the replays; with the automatic
+    alpha-beta kernel and with the source-grouped one."""
     torch = need_gpu()
     from paper_2601_16169_amd import sqd
-    banner(f"sigma graph capture precision {precision}")
+    banner(f"sigma graph capture precision {precision} ab variant {ab_variant}")
     stream = torch.cuda.Stream()
     gctx = sqd.Context(0, stream)
+    gctx.set_tuning(sqd.TUNE_AB_VARIANT, ab_variant)
     try:
         p = I.small_problem(10, 4, 3, 70, 97, 4)
         big_a = I.small_problem(10, 4, 3, 210, 120, 4).astr
