@@ -349,14 +349,15 @@ struct batch_plan {
     int nspace = 0;
     std::vector<bdesc> host;
     bdesc* D = nullptr;
-    unit_list vec, tr, ss_bb, ss_aa, abg, gath;
+    unit_list vec, tr, ss_bb, ss_aa, abg, abg2, gath;
     int* counters = nullptr;
     int* count_dev = nullptr;
     int* count_host = nullptr;
     double* partial = nullptr;
     dav_state* states = nullptr;
     int R = 0, G = 0, Rf = 0;
-    size_t lds_ss64 = 0, lds_ss32 = 0, lds_ab64 = 0, lds_ab32 = 0;
+    int G2 = 0;                // pair group of the spaces with shorter rows (0: one class)
+    size_t lds_ss64 = 0, lds_ss32 = 0, lds_ab64 = 0, lds_ab32 = 0, lds_ab64_2 = 0, lds_ab32_2 = 0;
     size_t gather_lds64 = 0;   // FP64 row bytes of the staged gather (0: in-place gather)
     int grid_persist = 0;
 };
@@ -367,6 +368,25 @@ void lds_attr(F f, size_t bytes) {
 }
 
 constexpr int kGridCap = 4096;
+
+// The alpha-beta chunks of the second class (spaces whose rows allow a
+// larger pair group than the longest rows of the batch).
+template <typename T>
+void launch_ab_class2(batch_plan& p, hipStream_t s, dim3 gp, int nw_ab, const T* V, int norb, int* counter) {
+    if (!p.G2 || p.abg2.n == 0) return;
+    const size_t lds = sizeof(T) == 8 ? p.lds_ab64_2 : p.lds_ab32_2;
+#define SQD_AB2_LAUNCH(GG)                                                                                       \
+    case GG:                                                                                                     \
+        hipLaunchKernelGGL((kb_ab_grouped<T, GG>), gp, dim3(64 * nw_ab), lds, s, p.D, p.abg2.dev, p.abg2.n, counter, \
+                           V, norb);                                                                             \
+        break;
+    switch (p.G2) {
+        SQD_AB2_LAUNCH(2)
+        SQD_AB2_LAUNCH(4)
+        SQD_AB2_LAUNCH(8)
+    }
+#undef SQD_AB2_LAUNCH
+}
 
 // Launch the sigma of every running space (precision prec) into its sout.
 template <int R, int G, int RF>
@@ -384,6 +404,7 @@ int batched_sigma(sqd_ctx* ctx, batch_plan& p, hipStream_t s, int prec, int nw_s
                            p.counters + 1, ctx->jk64, norb);
         hipLaunchKernelGGL((kb_ab_grouped<double, G>), gp, dim3(64 * nw_ab), p.lds_ab64, s, p.D, p.abg.dev, p.abg.n,
                            p.counters + 2, ctx->eri, norb);
+        launch_ab_class2<double>(p, s, gp, nw_ab, ctx->eri, norb, p.counters + 6);
         if (p.gather_lds64)
             hipLaunchKernelGGL((kb_gather<double, true>), sgrid(p.gath.n), dim3(256), p.gather_lds64, s, p.D,
                                p.gath.dev, p.gath.n);
@@ -399,6 +420,7 @@ int batched_sigma(sqd_ctx* ctx, batch_plan& p, hipStream_t s, int prec, int nw_s
                            p.ss_bb.n, p.counters + 4, ctx->jk32, norb);
         hipLaunchKernelGGL((kb_ab_grouped<float, G>), gp, dim3(64 * nw_ab), p.lds_ab32, s, p.D, p.abg.dev, p.abg.n,
                            p.counters + 5, ctx->eri32, norb);
+        launch_ab_class2<float>(p, s, gp, nw_ab, ctx->eri32, norb, p.counters + 7);
         if (p.gather_lds64)
             hipLaunchKernelGGL((kb_gather<float, true>), sgrid(p.gath.n), dim3(256), p.gather_lds64 / 2, s, p.D,
                                p.gath.dev, p.gath.n);
@@ -429,6 +451,12 @@ int batched_run(sqd_ctx* ctx, batch_plan& p, const sqd_davidson_opts* o, double*
     lds_attr(kb_same_spin<float, RF>, p.lds_ss32);
     lds_attr(kb_ab_grouped<double, G>, p.lds_ab64);
     lds_attr(kb_ab_grouped<float, G>, p.lds_ab32);
+    switch (p.G2) {
+        case 2: lds_attr(kb_ab_grouped<double, 2>, p.lds_ab64_2); lds_attr(kb_ab_grouped<float, 2>, p.lds_ab32_2); break;
+        case 4: lds_attr(kb_ab_grouped<double, 4>, p.lds_ab64_2); lds_attr(kb_ab_grouped<float, 4>, p.lds_ab32_2); break;
+        case 8: lds_attr(kb_ab_grouped<double, 8>, p.lds_ab64_2); lds_attr(kb_ab_grouped<float, 8>, p.lds_ab32_2); break;
+        default: break;
+    }
     const int ns = p.nspace;
     auto sgrid = [&](int n) { return dim3((unsigned)std::max(1, std::min(n, kGridCap))); };
     // initial states
@@ -622,10 +650,26 @@ int sqd_davidson_batched_impl(sqd_ctx* ctx, int nspace, sqd_space* const* spaces
     p.Rf = p.R;
     p.G = pick_G(ctx, max_nb, norb);
     if (!p.R || !p.Rf || !p.G) return sqd_fail(ctx, SQD_E_LIMIT, "batched tiles do not fit in LDS");
+    // spaces whose own rows allow a larger pair group than the batch's
+    // longest rows form a second class with its own launch (cfg-4-like
+    // batches: beta rows of 200-3000 strings, groups of four below about
+    // 2400 strings and of two above); a forced group size keeps one class
+    std::vector<char> cls2(nspace, 0);
+    int64_t max_nb2 = 0;
+    if (!ctx->tune[SQD_TUNE_AB_GROUP]) {
+        for (int b = 0; b < nspace; ++b)
+            if (pick_G(ctx, spaces[b]->sp[1].n, norb) > p.G) {
+                cls2[b] = 1;
+                max_nb2 = std::max(max_nb2, spaces[b]->sp[1].n);
+            }
+        if (max_nb2 > 0) p.G2 = pick_G(ctx, max_nb2, norb);
+    }
     p.lds_ss64 = ((size_t)(max_cols + 1) * p.R + (size_t)norb * norb * p.R) * 8;
     p.lds_ss32 = ((size_t)(max_cols + 1) * p.R + (size_t)norb * norb * p.R) * 4;
     p.lds_ab64 = ((size_t)(max_nb + 1) * p.G + (size_t)norb * norb) * 8;
     p.lds_ab32 = ((size_t)(max_nb + 1) * p.G + (size_t)norb * norb) * 4;
+    p.lds_ab64_2 = ((size_t)(max_nb2 + 1) * p.G2 + (size_t)norb * norb) * 8;
+    p.lds_ab32_2 = ((size_t)(max_nb2 + 1) * p.G2 + (size_t)norb * norb) * 4;
     p.gather_lds64 = (size_t)max_nb * 8 <= (size_t)(64 * 1024) ? (size_t)max_nb * 8 : 0;
     p.grid_persist = ctx->num_cu * 2;
     const bool mixed = o->mode == SQD_DAV_MIXED;
@@ -639,13 +683,13 @@ int sqd_davidson_batched_impl(sqd_ctx* ctx, int nspace, sqd_space* const* spaces
     auto want = [&](void** ptr, size_t bytes) { req.push_back({ptr, bytes}); };
     p.host.resize(nspace);
     int part = 0;
-    std::vector<int2> vec, tr, ssbb, ssaa, abg, gath;
+    std::vector<int2> vec, tr, ssbb, ssaa, abg, abg2, gath;
     std::vector<std::pair<double, int>> order;  // longest-first by sigma work
     for (int b = 0; b < nspace; ++b) {
         sqd_space* sp = spaces[b];
         const spin_tables& A = sp->sp[0];
         const spin_tables& B = sp->sp[1];
-        if ((rc = sqd_ensure_ab_groups(ctx, sp, p.G))) return rc;
+        if ((rc = sqd_ensure_ab_groups(ctx, sp, cls2[b] ? p.G2 : p.G))) return rc;
         bdesc& d = p.host[b];
         std::memset(&d, 0, sizeof(d));
         d.n = sp->dim;
@@ -686,15 +730,16 @@ int sqd_davidson_batched_impl(sqd_ctx* ctx, int nspace, sqd_space* const* spaces
         const bdesc& d = p.host[b];
         for (int64_t r = 0; r < (d.na + p.R - 1) / p.R; ++r) ssbb.push_back(make_int2(b, (int)r));
         for (int64_t r = 0; r < (d.nb + p.R - 1) / p.R; ++r) ssaa.push_back(make_int2(b, (int)r));
-        for (int c = 0; c < spaces[b]->ab_nchunks; ++c) abg.push_back(make_int2(b, c));
+        for (int c = 0; c < spaces[b]->ab_nchunks; ++c) (cls2[b] ? abg2 : abg).push_back(make_int2(b, c));
     }
     want((void**)&p.partial, sizeof(double) * (size_t)part * kPstride);
     want((void**)&p.states, sizeof(dav_state) * nspace);
     want((void**)&p.counters, sizeof(int) * 8);
     want((void**)&p.count_dev, sizeof(int));
     want((void**)&p.D, sizeof(bdesc) * nspace);
-    std::pair<std::vector<int2>*, unit_list*> lists[6] = {{&vec, &p.vec}, {&tr, &p.tr}, {&ssbb, &p.ss_bb},
-                                                          {&ssaa, &p.ss_aa}, {&abg, &p.abg}, {&gath, &p.gath}};
+    std::pair<std::vector<int2>*, unit_list*> lists[7] = {{&vec, &p.vec}, {&tr, &p.tr}, {&ssbb, &p.ss_bb},
+                                                          {&ssaa, &p.ss_aa}, {&abg, &p.abg}, {&abg2, &p.abg2},
+                                                          {&gath, &p.gath}};
     for (auto& l : lists) {
         l.second->n = (int)l.first->size();
         if (l.first->empty()) l.first->push_back(make_int2(0, 0));
