@@ -56,6 +56,7 @@ struct bdesc {
     float* Y32;
     const int* a_off;
     const int* a_order;   // alpha rows, heaviest first (gather order)
+    const int* abs_src;   // source string of each alpha-beta chunk (source-grouped spaces)
     ss_args<double> bb64, aa64;
     ss_args<float> bb32, aa32;
     abg_args<double> ab64;
@@ -106,6 +107,22 @@ __global__ void __launch_bounds__(1024) kb_ab_grouped(const bdesc* __restrict__ 
         const bdesc& d = D[units[u].x];
         if (d.st->done) continue;
         abg_block<T, G>(aba(d, T()), V, norb, units[u].y, lds_raw);
+        __syncthreads();
+    }
+}
+
+// The spaces of the longest rows with their alpha singles grouped by source
+// string (abs_block; the chunks in ab64/ab32.grp, their sources in abs_src).
+template <typename T, int GS>
+__global__ void __launch_bounds__(1024) kb_ab_srcgrouped(const bdesc* __restrict__ D, const int2* __restrict__ units,
+                                                         int nunits, int* counter, const T* __restrict__ V, int norb) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    while (true) {
+        const int u = next_unit(counter);
+        if (u >= nunits) break;
+        const bdesc& d = D[units[u].x];
+        if (d.st->done) continue;
+        abs_block<T, GS>(aba(d, T()), d.abs_src, V, norb, units[u].y, lds_raw);
         __syncthreads();
     }
 }
@@ -357,6 +374,8 @@ struct batch_plan {
     dav_state* states = nullptr;
     int R = 0, G = 0, Rf = 0;
     int G2 = 0;                // pair group of the spaces with shorter rows (0: one class)
+    int GS = 0;                // the first class grouped by source string, GS singles per chunk (0: by pair)
+    size_t lds_abs64 = 0, lds_abs32 = 0;
     size_t lds_ss64 = 0, lds_ss32 = 0, lds_ab64 = 0, lds_ab32 = 0, lds_ab64_2 = 0, lds_ab32_2 = 0;
     size_t gather_lds64 = 0;   // FP64 row bytes of the staged gather (0: in-place gather)
     int grid_persist = 0;
@@ -388,6 +407,24 @@ void launch_ab_class2(batch_plan& p, hipStream_t s, dim3 gp, int nw_ab, const T*
 #undef SQD_AB2_LAUNCH
 }
 
+// The first class grouped by source string.
+template <typename T>
+void launch_ab_src(batch_plan& p, hipStream_t s, dim3 gp, int nw_ab, const T* V, int norb, int* counter) {
+    const size_t lds = sizeof(T) == 8 ? p.lds_abs64 : p.lds_abs32;
+#define SQD_ABS_LAUNCH(GG)                                                                                      \
+    case GG:                                                                                                    \
+        hipLaunchKernelGGL((kb_ab_srcgrouped<T, GG>), gp, dim3(64 * nw_ab), lds, s, p.D, p.abg.dev, p.abg.n,      \
+                           counter, V, norb);                                                                   \
+        break;
+    switch (p.GS) {
+        SQD_ABS_LAUNCH(2)
+        SQD_ABS_LAUNCH(3)
+        SQD_ABS_LAUNCH(4)
+        SQD_ABS_LAUNCH(8)
+    }
+#undef SQD_ABS_LAUNCH
+}
+
 // Launch the sigma of every running space (precision prec) into its sout.
 template <int R, int G, int RF>
 int batched_sigma(sqd_ctx* ctx, batch_plan& p, hipStream_t s, int prec, int nw_ss, int nw_ab) {
@@ -402,8 +439,10 @@ int batched_sigma(sqd_ctx* ctx, batch_plan& p, hipStream_t s, int prec, int nw_s
         hipLaunchKernelGGL((kb_transpose<double>), sgrid(p.tr.n), dim3(256), 0, s, p.D, 1, p.tr.dev, p.tr.n);
         hipLaunchKernelGGL((kb_same_spin<double, R>), gp, dim3(64 * nw_ss), p.lds_ss64, s, p.D, 0, p.ss_bb.dev, p.ss_bb.n,
                            p.counters + 1, ctx->jk64, norb);
-        hipLaunchKernelGGL((kb_ab_grouped<double, G>), gp, dim3(64 * nw_ab), p.lds_ab64, s, p.D, p.abg.dev, p.abg.n,
-                           p.counters + 2, ctx->eri, norb);
+        if (p.GS) launch_ab_src<double>(p, s, gp, nw_ab, ctx->eri, norb, p.counters + 2);
+        else
+            hipLaunchKernelGGL((kb_ab_grouped<double, G>), gp, dim3(64 * nw_ab), p.lds_ab64, s, p.D, p.abg.dev,
+                               p.abg.n, p.counters + 2, ctx->eri, norb);
         launch_ab_class2<double>(p, s, gp, nw_ab, ctx->eri, norb, p.counters + 6);
         if (p.gather_lds64)
             hipLaunchKernelGGL((kb_gather<double, true>), sgrid(p.gath.n), dim3(256), p.gather_lds64, s, p.D,
@@ -418,8 +457,10 @@ int batched_sigma(sqd_ctx* ctx, batch_plan& p, hipStream_t s, int prec, int nw_s
         hipLaunchKernelGGL((kb_transpose<float>), sgrid(p.tr.n), dim3(256), 0, s, p.D, 1, p.tr.dev, p.tr.n);
         hipLaunchKernelGGL((kb_same_spin<float, RF>), gp, dim3(64 * nw_ss), p.lds_ss32, s, p.D, 0, p.ss_bb.dev,
                            p.ss_bb.n, p.counters + 4, ctx->jk32, norb);
-        hipLaunchKernelGGL((kb_ab_grouped<float, G>), gp, dim3(64 * nw_ab), p.lds_ab32, s, p.D, p.abg.dev, p.abg.n,
-                           p.counters + 5, ctx->eri32, norb);
+        if (p.GS) launch_ab_src<float>(p, s, gp, nw_ab, ctx->eri32, norb, p.counters + 5);
+        else
+            hipLaunchKernelGGL((kb_ab_grouped<float, G>), gp, dim3(64 * nw_ab), p.lds_ab32, s, p.D, p.abg.dev,
+                               p.abg.n, p.counters + 5, ctx->eri32, norb);
         launch_ab_class2<float>(p, s, gp, nw_ab, ctx->eri32, norb, p.counters + 7);
         if (p.gather_lds64)
             hipLaunchKernelGGL((kb_gather<float, true>), sgrid(p.gath.n), dim3(256), p.gather_lds64 / 2, s, p.D,
@@ -451,6 +492,13 @@ int batched_run(sqd_ctx* ctx, batch_plan& p, const sqd_davidson_opts* o, double*
     lds_attr(kb_same_spin<float, RF>, p.lds_ss32);
     lds_attr(kb_ab_grouped<double, G>, p.lds_ab64);
     lds_attr(kb_ab_grouped<float, G>, p.lds_ab32);
+    switch (p.GS) {
+        case 2: lds_attr(kb_ab_srcgrouped<double, 2>, p.lds_abs64); lds_attr(kb_ab_srcgrouped<float, 2>, p.lds_abs32); break;
+        case 3: lds_attr(kb_ab_srcgrouped<double, 3>, p.lds_abs64); lds_attr(kb_ab_srcgrouped<float, 3>, p.lds_abs32); break;
+        case 4: lds_attr(kb_ab_srcgrouped<double, 4>, p.lds_abs64); lds_attr(kb_ab_srcgrouped<float, 4>, p.lds_abs32); break;
+        case 8: lds_attr(kb_ab_srcgrouped<double, 8>, p.lds_abs64); lds_attr(kb_ab_srcgrouped<float, 8>, p.lds_abs32); break;
+        default: break;
+    }
     switch (p.G2) {
         case 2: lds_attr(kb_ab_grouped<double, 2>, p.lds_ab64_2); lds_attr(kb_ab_grouped<float, 2>, p.lds_ab32_2); break;
         case 4: lds_attr(kb_ab_grouped<double, 4>, p.lds_ab64_2); lds_attr(kb_ab_grouped<float, 4>, p.lds_ab32_2); break;
@@ -663,12 +711,22 @@ int sqd_davidson_batched_impl(sqd_ctx* ctx, int nspace, sqd_space* const* spaces
                 max_nb2 = std::max(max_nb2, spaces[b]->sp[1].n);
             }
         if (max_nb2 > 0) p.G2 = pick_G(ctx, max_nb2, norb);
+        // where the longest rows leave pair groups of one or two, that class
+        // groups its singles by source string instead (as the single-space
+        // product does)
+        if (p.G <= 2 && ctx->tune[SQD_TUNE_AB_VARIANT] != 1) {
+            const size_t n2 = (size_t)norb * norb;
+            for (int G : {8, 4, 3, 2})
+                if ((size_t)(max_nb + 1) * 8 + (size_t)G * n2 * 8 <= (size_t)ctx->max_lds) { p.GS = G > p.G ? G : 0; break; }
+        }
     }
     p.lds_ss64 = ((size_t)(max_cols + 1) * p.R + (size_t)norb * norb * p.R) * 8;
     p.lds_ss32 = ((size_t)(max_cols + 1) * p.R + (size_t)norb * norb * p.R) * 4;
     p.lds_ab64 = ((size_t)(max_nb + 1) * p.G + (size_t)norb * norb) * 8;
     p.lds_ab32 = ((size_t)(max_nb + 1) * p.G + (size_t)norb * norb) * 4;
     p.lds_ab64_2 = ((size_t)(max_nb2 + 1) * p.G2 + (size_t)norb * norb) * 8;
+    p.lds_abs64 = ((size_t)(max_nb + 1) + (size_t)p.GS * norb * norb) * 8;
+    p.lds_abs32 = ((size_t)(max_nb + 1) + (size_t)p.GS * norb * norb) * 4;
     p.lds_ab32_2 = ((size_t)(max_nb2 + 1) * p.G2 + (size_t)norb * norb) * 4;
     p.gather_lds64 = (size_t)max_nb * 8 <= (size_t)(64 * 1024) ? (size_t)max_nb * 8 : 0;
     p.grid_persist = ctx->num_cu * 2;
@@ -689,7 +747,9 @@ int sqd_davidson_batched_impl(sqd_ctx* ctx, int nspace, sqd_space* const* spaces
         sqd_space* sp = spaces[b];
         const spin_tables& A = sp->sp[0];
         const spin_tables& B = sp->sp[1];
-        if ((rc = sqd_ensure_ab_groups(ctx, sp, cls2[b] ? p.G2 : p.G))) return rc;
+        if (cls2[b]) rc = sqd_ensure_ab_groups(ctx, sp, p.G2);
+        else rc = p.GS ? sqd_ensure_ab_source_groups(ctx, sp, p.GS) : sqd_ensure_ab_groups(ctx, sp, p.G);
+        if (rc) return rc;
         bdesc& d = p.host[b];
         std::memset(&d, 0, sizeof(d));
         d.n = sp->dim;
@@ -730,7 +790,8 @@ int sqd_davidson_batched_impl(sqd_ctx* ctx, int nspace, sqd_space* const* spaces
         const bdesc& d = p.host[b];
         for (int64_t r = 0; r < (d.na + p.R - 1) / p.R; ++r) ssbb.push_back(make_int2(b, (int)r));
         for (int64_t r = 0; r < (d.nb + p.R - 1) / p.R; ++r) ssaa.push_back(make_int2(b, (int)r));
-        for (int c = 0; c < spaces[b]->ab_nchunks; ++c) (cls2[b] ? abg2 : abg).push_back(make_int2(b, c));
+        const int nch = (!cls2[b] && p.GS) ? spaces[b]->abs_nchunks : spaces[b]->ab_nchunks;
+        for (int c = 0; c < nch; ++c) (cls2[b] ? abg2 : abg).push_back(make_int2(b, c));
     }
     want((void**)&p.partial, sizeof(double) * (size_t)part * kPstride);
     want((void**)&p.states, sizeof(dav_state) * nspace);
@@ -786,10 +847,14 @@ int sqd_davidson_batched_impl(sqd_ctx* ctx, int nspace, sqd_space* const* spaces
                                 A.sell_s_v32, A.sell_d_nbr, A.sell_d_v32, B.str, B.nw, nullptr, 0};
         d.bb32 = ss_args<float>{d.c32, d.S32, A.n, B.n, B.perm_ss, B.nslices, B.sl_s_off, B.sl_d_off, B.sell_s_pk,
                                 B.sell_s_v32, B.sell_d_nbr, B.sell_d_v32, A.str, A.nw, nullptr, 1};
-        d.ab64 = abg_args<double>{d.cin, d.Y64, B.n, ldy, sp->ab_grp, sp->ab_chunk_pair, A.s_pk, B.perm_ab,
-                                  B.nslices, B.sl_ab_off, B.sell_ab_pk};
-        d.ab32 = abg_args<float>{d.c32, d.Y32, B.n, ldy, sp->ab_grp, sp->ab_chunk_pair, A.s_pk, B.perm_ab,
-                                 B.nslices, B.sl_ab_off, B.sell_ab_pk};
+        const bool src = !cls2[b] && p.GS;
+        const int* grp = src ? sp->abs_grp : sp->ab_grp;
+        const int* cpair = src ? nullptr : sp->ab_chunk_pair;
+        d.abs_src = src ? sp->abs_src : nullptr;
+        d.ab64 = abg_args<double>{d.cin, d.Y64, B.n, ldy, grp, cpair, A.s_pk, B.perm_ab, B.nslices, B.sl_ab_off,
+                                  B.sell_ab_pk};
+        d.ab32 = abg_args<float>{d.c32, d.Y32, B.n, ldy, grp, cpair, A.s_pk, B.perm_ab, B.nslices, B.sl_ab_off,
+                                 B.sell_ab_pk};
     }
     if (!ctx->batch_count_host &&
         hipHostMalloc((void**)&ctx->batch_count_host, sizeof(int), hipHostMallocDefault) != hipSuccess) {

@@ -622,6 +622,10 @@ int launch_ab_grouped(sqd_ctx* ctx, sqd_space* sp, const T* C, T* S, T* Y, const
 }  // namespace
 
 int sqd_ensure_ab_groups(sqd_ctx* ctx, sqd_space* sp, int G) { return ensure_ab_groups_impl(ctx, sp, G); }
+int sqd_ensure_ab_source_groups(sqd_ctx* ctx, sqd_space* sp, int G) {
+    int rc = ensure_ab_row_order(ctx, sp);
+    return rc ? rc : ensure_ab_source_groups(ctx, sp, G);
+}
 
 int sqd_ensure_diag(sqd_ctx* ctx, sqd_space* sp) {
     int rc = sqd_build_values(ctx, sp);

@@ -228,6 +228,8 @@ int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma,
 int sqd_sigma_auto_path(sqd_ctx* ctx, const sqd_space* sp, int precision);
 bool sqd_sigma_prepared(sqd_ctx* ctx, const sqd_space* sp, int precision, unsigned mask, int ab_path);
 int sqd_ensure_ab_groups(sqd_ctx* ctx, sqd_space* sp, int G);
+// the alpha singles grouped by source string, chunks of G (for the batched solver)
+int sqd_ensure_ab_source_groups(sqd_ctx* ctx, sqd_space* sp, int G);
 
 // ---- kh.hip ----
 size_t sqd_kh_bytes(const sqd_space* sp, size_t es);
