@@ -77,6 +77,31 @@ def test_batched_matches_single_space(ctx, mode):
         s.close()
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_batched_alpha_beta_classes(ctx, mode):
+    """A batch whose longest beta rows (2600 strings) leave pair groups of
+    two: that space's alpha singles are grouped by source string, while the
+    shorter spaces form a second class with larger pair groups; every energy
+    (and FP64 vector) equals the single-space solve."""
+    torch = need_gpu()
+    banner(f"batched alpha-beta classes mode={mode}")
+    counts = [2600, 300, 900]
+    ints, probs = _batch(24, 8, counts, 6, nchol=60)
+    ctx.set_hamiltonian(ints.h, ints.eri)
+    spaces = [ctx.build_space(p.nalpha, p.nbeta, p.astr, p.bstr) for p in probs]
+    assert max(s.nb for s in spaces) == 2600
+    E, vecs, reps, rc = ctx.davidson_batched(spaces, tol=1e-8, mode=mode, max_iter=400)
+    tolE = 1e-9 if mode == 0 else 1e-6
+    for s, p, e, v, r in zip(spaces, probs, E, vecs, reps):
+        assert r["converged"], (p.name, r["status"], r["residual"])
+        e1, x1, r1 = s.davidson(tol=1e-8, max_iter=400)
+        assert abs(e - e1) <= tolE, (p.name, e, e1)
+        if mode == 0:
+            assert 1 - abs(float(torch.dot(v, x1))) <= 1e-8
+    for s in spaces:
+        s.close()
+
+
 def test_batched_one_space_and_cap(ctx):
     torch = need_gpu()
     p = I.cfg1()
