@@ -277,7 +277,10 @@ int sqd_diag(sqd_ctx* ctx, const sqd_space* space, double* diag_dev);
  * shared by the graph and eager calls on the same context (do not run them
  * concurrently); eager calls that need a larger scratch later keep the
  * captured buffer alive until sqd_release_workspace or sqd_destroy, after
- * which the graph must not be replayed. */
+ * which the graph must not be replayed.  A later call that changes how the
+ * space's alpha singles are grouped (another SQD_TUNE_AB_* setting, or a
+ * batched solve that includes the space) rebuilds that schedule: graphs
+ * captured on the space before must then not be replayed either. */
 int sqd_sigma(sqd_ctx* ctx, const sqd_space* space, const double* c_dev,
               double* sigma_dev, int precision, unsigned terms_mask, int ab_path);
 
