@@ -104,7 +104,7 @@ extern "C" {
                                   0 = auto */
 #define SQD_TUNE_AB_GROUP 7    /* alpha singles per grouped alpha-beta unit: 1,2,4,8 (0 = auto) */
 #define SQD_TUNE_SS_WINDOW 8   /* same-spin term by windows of source strings (rows of C too
-                                  long for two to fit in LDS): 0 auto, 1 never, 2 always,
+                                  long for four to fit in LDS): 0 auto, 1 never, 2 always,
                                   or a window width (multiple of 64, <= 65536; always) */
 #define SQD_TUNE_COUNT 9
 

@@ -300,16 +300,21 @@ spin_tables& owner(sqd_space* sp, const spin_tables& t) {
 }
 
 // Windowed same-spin kernel: forced on or off by SQD_TUNE_SS_WINDOW, else used
-// when fewer than two rows fit in one workgroup's LDS (measured on MI355X,
-// 2.56e8-determinant workload, beta-beta term: FP64 one row staged 46.2 ms,
-// windowed 30.5 ms; FP32 two rows staged 15.8 ms, windowed 20.8 ms).
+// when fewer than four rows fit in one workgroup's LDS.  Measured on MI355X
+// on norb-36 spaces of n strings per spin (same-spin beta-beta / alpha-alpha
+// terms, ms, row-staged against windowed): FP64 with two rows staged, n =
+// 4000: 1.41 / 1.55 against 1.00 / 0.91; n = 8000: 5.75 / 6.18 against 4.64 /
+// 3.99; one row, n = 16000: 48.6 / 50.8 against 23.6 / 21.5.  FP32 with four
+// rows staged, n = 6000: 1.29 / 1.44 against 1.56 / 1.48; n = 8000: 2.25 /
+// 2.50 against 2.53 / 2.35; two rows, n = 10000: 5.41 / 5.82 against 4.65 /
+// 4.23; n = 16000: 15.0 / 16.0 against 12.9 / 11.0.
 bool use_window(sqd_ctx* ctx, int64_t nrows, int64_t ncols, int norb, size_t es) {
     const int mode = ctx->tune[SQD_TUNE_SS_WINDOW];
     if (mode == 1) return false;
     if (mode >= 2) return true;
     if (ctx->tune[SQD_TUNE_SS_ROWS]) return false;
-    const size_t lds2 = ((size_t)(ncols + 1) * 2 + (size_t)norb * norb * 2) * es;
-    return lds2 > (size_t)ctx->max_lds && nrows >= 2;
+    const size_t lds4 = ((size_t)(ncols + 1) * 4 + (size_t)norb * norb * 4) * es;
+    return lds4 > (size_t)ctx->max_lds && nrows >= 2;
 }
 
 // colmajor: X and Y hold the transposes (the alpha-alpha term read from C and

@@ -138,14 +138,15 @@ struct spin_tables {
     int* win_s_off = nullptr;     // win_W * (nslices + 1) slot-column offsets (units of 64)
     int* win_d_off = nullptr;
     uint32_t* win_s_pk = nullptr; // local source | pair << 17 | negative << 31
-    int* win_d_nbr = nullptr;     // local source
+    uint16_t* win_d_nbr = nullptr; // local source (below the window width)
     int* win_s_csr = nullptr;     // CSR index of each slot (-1: padding)
     int* win_d_csr = nullptr;
     double* win_s_v64 = nullptr; float* win_s_v32 = nullptr;
     double* win_d_v64 = nullptr; float* win_d_v32 = nullptr;
     int64_t win_bytes = 0;
-    // cross-spin table of these strings as the row spin: wg[s * norb^2 + pq] =
-    // sum_{k in s} (pq|kk) (FP64 and FP32), per Hamiltonian version
+    // cross-spin table of these strings as the row spin: wg[pq * ldw + s] =
+    // sum_{k in s} (pq|kk) (FP64 and FP32; ldw = n rounded up to 16, zero
+    // past n), per Hamiltonian version
     double* wg64 = nullptr; float* wg32 = nullptr;
     int wg_version = -1;
 };
