@@ -505,9 +505,9 @@ def test_sigma_ab_variants_cfg2(ctx, variant):
 def test_sigma_long_beta_rows(ctx, precision):
     """Rows of 16500 beta strings: in FP64 a row (132,000 bytes) is longer
     than the gather assembles in LDS, so the alpha-beta sums are added into
-    sigma in place, and the beta-beta term takes the windowed kernel (fewer
-    than two rows fit); sampled rows against the oracle, all terms and the
-    alpha-beta term alone."""
+    sigma in place, and the beta-beta term takes the windowed kernel in both
+    precisions (fewer than four rows fit); sampled rows against the oracle,
+    all terms and the alpha-beta term alone."""
     torch = need_gpu()
     banner(f"sigma long beta rows precision={precision}")
     p = I.small_problem(18, 3, 9, 6, 16500, 31)
