@@ -337,13 +337,15 @@ int launch_same_spin(sqd_ctx* ctx, sqd_space* sp, const T* X, T* Y, int64_t nrow
                      int accumulate, const int* skip, const char* timer_name, int colmajor = 0) {
     const size_t es = sizeof(T);
     if (use_window(ctx, nrows, ncols, norb, es)) {
-        // the windowed kernel writes its targets in scattered order, so the
-        // diagonal (scattered reads of diag and X there) goes in a coalesced
-        // pass after it (2.56e8 workload: beta-beta with the fused diagonal
-        // 35.5 ms, without 28.1 ms)
+        // the windowed kernel ends in slot order, so the diagonal (scattered
+        // reads of diag and X there) goes in the coalesced pass that places
+        // its output, or in one of its own (2.56e8 workload: beta-beta with
+        // the diagonal fused in the kernel 35.5 ms, without 28.1 ms)
+        int diag_done = 0;
         int rc = sqd_same_spin_windowed(ctx, sp, owner(sp, col), owner(sp, row), X, Y, nrows, ncols, colmajor,
-                                        accumulate, sizeof(T) == 4, skip, timer_name);
-        if (rc || !diag) return rc;
+                                        accumulate, sizeof(T) == 4, sizeof(T) == 8 ? diag : nullptr, &diag_done,
+                                        skip, timer_name);
+        if (rc || !diag || diag_done) return rc;
         if constexpr (sizeof(T) == 8) {
             prof_scope pd(ctx, "k_diag_apply");
             const int64_t n = nrows * ncols;

@@ -139,6 +139,7 @@ struct spin_tables {
     int* win_d_off = nullptr;
     uint32_t* win_s_pk = nullptr; // local source | pair << 17 | negative << 31
     uint16_t* win_d_nbr = nullptr; // local source (below the window width)
+    int* win_islot = nullptr;     // n: slot of each target in the perm_ss order
     int* win_s_csr = nullptr;     // CSR index of each slot (-1: padding)
     int* win_d_csr = nullptr;
     double* win_s_v64 = nullptr; float* win_s_v32 = nullptr;
@@ -239,11 +240,14 @@ int sqd_sigma_ab_kh(sqd_ctx* ctx, sqd_space* sp, const void* c, void* sigma, voi
 
 // ---- window.hip ----
 // Same-spin term for rows too long to stage whole: X (nrows x ncols) times the
-// column spin's tables, by windows of source strings; Y written (no
-// accumulation).  col / row: the owning spin_tables of the column and row spins.
+// column spin's tables, by windows of source strings; Y written, or added to
+// with accumulate.  col / row: the owning spin_tables of the column and row
+// spins.  diag (FP64, row-major, or null): where the output is placed by the
+// coalesced pass after the kernel, that pass adds diag * X too and sets
+// *diag_done; otherwise the caller adds the diagonal.
 int sqd_same_spin_windowed(sqd_ctx* ctx, sqd_space* sp, spin_tables& col, spin_tables& row, const void* X, void* Y,
-                           int64_t nrows, int64_t ncols, int colmajor, int accumulate, int fp32, const int* skip,
-                           const char* timer);
+                           int64_t nrows, int64_t ncols, int colmajor, int accumulate, int fp32, const double* diag,
+                           int* diag_done, const int* skip, const char* timer);
 void sqd_free_window_tables(spin_tables* t);
 bool sqd_space_built_for(sqd_ctx* ctx, const sqd_space* sp, int precision, unsigned mask);
 int sqd_window_count(sqd_ctx* ctx, int64_t ncols);    // 0: a window does not fit

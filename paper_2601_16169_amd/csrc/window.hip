@@ -81,6 +81,7 @@ struct win_args {
     int norb;
     int colmajor;               // X, Y hold the transposes: (row, col) at col * nrows + row
     int accumulate;             // Y += (else Y =)
+    int slot_out;               // the last window also writes P (slot order); Y is left alone
 };
 
 // One workgroup per block of R rows; windows in turn.  LDS: xs[(width + 1) * R]
@@ -223,20 +224,46 @@ __global__ void __launch_bounds__(1024) k_same_spin_win(win_args<T> a, const int
             // non-temporal, so that the scratch of all row blocks in flight,
             // larger than the caches, does not evict the table: 2.56e8
             // workload, same box, 28.0 -> 26.6-27.1 ms per same-spin term);
-            // the last window writes the target
+            // the last window writes the target, or with slot_out its slot
+            // of P as well, for a coalesced pass that places the targets
             const int t = a.perm[slot];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int64_t row = row0 + r;
                 if (row >= a.nrows) continue;
                 const T val = acc[r] + prev[r];
-                if (!last) {
+                if (!last || a.slot_out) {
                     __builtin_nontemporal_store(val, a.P + row * ldp + slot);
                 } else if (t < a.ncols) {
                     const int64_t o = a.colmajor ? (int64_t)t * a.nrows + row : row * a.ncols + t;
                     a.Y[o] = a.accumulate ? a.Y[o] + val : val;
                 }
             }
+        }
+    }
+}
+
+// Row-major output of the windowed kernel from the slot-ordered sums in P:
+// Y[row][t] (=|+=) P[row][islot[t]] (+ diag * X, the FP64 diagonal term).
+// One workgroup per row: the reads of P stay within one row (in the L2 after
+// their first touch), everything else is coalesced.  Scattered stores of the
+// targets straight from the last window cost more (2.56e8-determinant
+// workload, beta-beta: FP64 23.9 ms against 20.5 ms with the stores in slot
+// order, FP32 12.9 against 9.9 ms).
+template <typename T>
+__global__ void __launch_bounds__(256) k_win_unperm(const T* __restrict__ P, int64_t ldp, const int* __restrict__ islot,
+                                                    const T* __restrict__ X, const double* __restrict__ diag,
+                                                    T* __restrict__ Y, int64_t nrows, int64_t ncols, int accumulate,
+                                                    const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    for (int64_t row = blockIdx.x; row < nrows; row += gridDim.x) {
+        const T* prow = P + row * ldp;
+        for (int64_t t = threadIdx.x; t < ncols; t += blockDim.x) {
+            const int64_t o = row * ncols + t;
+            T v = prow[islot[t]];
+            if (diag) v += (T)(diag[o] * (double)X[o]);
+            if (accumulate) v += Y[o];
+            Y[o] = v;
         }
     }
 }
@@ -257,6 +284,15 @@ int build_window_tables(sqd_ctx* ctx, sqd_space* sp, spin_tables& t, int W) {
     SQD_HIP(ctx, hipMemcpy(perm.data(), t.perm_ss, sizeof(int) * perm.size(), hipMemcpyDeviceToHost));
     if (t.nnz_s > 0) SQD_HIP(ctx, hipMemcpy(spk.data(), t.s_pk, sizeof(uint32_t) * t.nnz_s, hipMemcpyDeviceToHost));
     if (t.nnz_d > 0) SQD_HIP(ctx, hipMemcpy(dnbr.data(), t.d_nbr, sizeof(int) * t.nnz_d, hipMemcpyDeviceToHost));
+    // slot of every target (perm_ss lists each target once, padding = n)
+    std::vector<int> islot(n > 0 ? n : 1, -1);
+    for (size_t q = 0; q < perm.size(); ++q)
+        if (perm[q] >= 0 && perm[q] < n) {
+            if (islot[perm[q]] >= 0) return sqd_fail(ctx, SQD_E_STATE, "target listed twice in the sliced table");
+            islot[perm[q]] = (int)q;
+        }
+    for (int64_t r = 0; r < n; ++r)
+        if (islot[r] < 0) return sqd_fail(ctx, SQD_E_STATE, "target missing from the sliced table");
     // per (window, target) entry counts, then slice widths per window
     std::vector<int> cs((size_t)W * n, 0), cd((size_t)W * n, 0);
     for (int64_t r = 0; r < n; ++r) {
@@ -330,7 +366,8 @@ int build_window_tables(sqd_ctx* ctx, sqd_space* sp, spin_tables& t, int W) {
         (rc = sqd_alloc(ctx, (void**)&t.win_s_v64, sizeof(double) * S, &bytes)) ||
         (rc = sqd_alloc(ctx, (void**)&t.win_s_v32, sizeof(float) * S, &bytes)) ||
         (rc = sqd_alloc(ctx, (void**)&t.win_d_v64, sizeof(double) * D, &bytes)) ||
-        (rc = sqd_alloc(ctx, (void**)&t.win_d_v32, sizeof(float) * D, &bytes))) {
+        (rc = sqd_alloc(ctx, (void**)&t.win_d_v32, sizeof(float) * D, &bytes)) ||
+        (rc = sqd_alloc(ctx, (void**)&t.win_islot, sizeof(int) * islot.size(), &bytes))) {
         sqd_free_window_tables(&t);
         return rc;
     }
@@ -340,6 +377,7 @@ int build_window_tables(sqd_ctx* ctx, sqd_space* sp, spin_tables& t, int W) {
     SQD_HIP(ctx, hipMemcpy(t.win_s_csr, hs_csr.data(), sizeof(int) * S, hipMemcpyHostToDevice));
     SQD_HIP(ctx, hipMemcpy(t.win_d_nbr, hd_nbr.data(), sizeof(uint16_t) * D, hipMemcpyHostToDevice));
     SQD_HIP(ctx, hipMemcpy(t.win_d_csr, hd_csr.data(), sizeof(int) * D, hipMemcpyHostToDevice));
+    SQD_HIP(ctx, hipMemcpy(t.win_islot, islot.data(), sizeof(int) * islot.size(), hipMemcpyHostToDevice));
     t.win_W = W;
     t.win_width = width;
     t.win_values_version = -1;
@@ -402,17 +440,33 @@ void set_lds_attr(F f, int bytes) {
 
 template <typename T, int R>
 int launch_win(sqd_ctx* ctx, sqd_space* sp, spin_tables& col, spin_tables& row, const T* X, T* Y, int64_t nrows,
-               int64_t ncols, int colmajor, int accumulate, const int* skip) {
+               int64_t ncols, int colmajor, int accumulate, const double* diag, const int* skip, const char* timer,
+               int* diag_done) {
     const T* sv;
     const T* dv;
     const T* wg;
     if constexpr (sizeof(T) == 8) { sv = (const T*)col.win_s_v64; dv = (const T*)col.win_d_v64; wg = (const T*)row.wg64; }
     else { sv = (const T*)col.win_s_v32; dv = (const T*)col.win_d_v32; wg = (const T*)row.wg32; }
+    // row-major output goes through P in slot order (P exists when W > 1);
+    // column-major output stores 64 contiguous bytes per lane directly
+    const int slot_out = (!colmajor && col.win_W > 1) ? 1 : 0;
     win_args<T> a{X, Y, (T*)sp->win_P, nrows, ncols, col.win_W, col.win_width, col.nslices, col.perm_ss,
-                  col.win_s_off, col.win_d_off, col.win_s_pk, sv, col.win_d_nbr, dv, wg, sqd_wtable_ld(row.n), sp->norb, colmajor, accumulate};
+                  col.win_s_off, col.win_d_off, col.win_s_pk, sv, col.win_d_nbr, dv, wg, sqd_wtable_ld(row.n),
+                  sp->norb, colmajor, accumulate, slot_out};
     const size_t lds = (size_t)(col.win_width + 1) * R * sizeof(T);
     set_lds_attr(k_same_spin_win<T, R>, (int)lds);
-    hipLaunchKernelGGL((k_same_spin_win<T, R>), dim3(nblk(nrows, R)), dim3(1024), lds, ctx->stream, a, skip);
+    {
+        prof_scope ps(ctx, timer);
+        hipLaunchKernelGGL((k_same_spin_win<T, R>), dim3(nblk(nrows, R)), dim3(1024), lds, ctx->stream, a, skip);
+    }
+    if (slot_out) {
+        const double* dg = sizeof(T) == 8 ? diag : nullptr;
+        prof_scope pu(ctx, "k_win_unperm");
+        const unsigned g = (unsigned)std::min<int64_t>(nrows, 1 << 20);
+        hipLaunchKernelGGL((k_win_unperm<T>), dim3(g), dim3(256), 0, ctx->stream, (const T*)sp->win_P,
+                           (int64_t)col.nslices * 64, col.win_islot, X, dg, Y, nrows, ncols, accumulate, skip);
+        if (dg && diag_done) *diag_done = 1;
+    }
     SQD_HIP(ctx, hipGetLastError());
     return SQD_OK;
 }
@@ -427,12 +481,13 @@ constexpr int kWinRows = 8;
 constexpr int kWinRows32 = 16;
 
 void sqd_free_window_tables(spin_tables* t) {
-    void* ptrs[] = {t->win_s_off, t->win_d_off, t->win_s_pk, t->win_d_nbr, t->win_s_csr,
-                    t->win_d_csr, t->win_s_v64, t->win_s_v32, t->win_d_v64, t->win_d_v32, t->wg64, t->wg32};
+    void* ptrs[] = {t->win_s_off, t->win_d_off, t->win_s_pk, t->win_d_nbr, t->win_s_csr, t->win_d_csr,
+                    t->win_s_v64, t->win_s_v32, t->win_d_v64, t->win_d_v32, t->wg64, t->wg32, t->win_islot};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     t->win_s_off = t->win_d_off = t->win_s_csr = t->win_d_csr = nullptr;
     t->win_d_nbr = nullptr;
+    t->win_islot = nullptr;
     t->win_s_pk = nullptr;
     t->win_s_v64 = t->win_d_v64 = t->wg64 = nullptr;
     t->win_s_v32 = t->win_d_v32 = t->wg32 = nullptr;
@@ -462,8 +517,8 @@ size_t sqd_window_scratch_bytes(const sqd_space* sp) {
 }
 
 int sqd_same_spin_windowed(sqd_ctx* ctx, sqd_space* sp, spin_tables& col, spin_tables& row, const void* X, void* Y,
-                           int64_t nrows, int64_t ncols, int colmajor, int accumulate, int fp32, const int* skip,
-                           const char* timer) {
+                           int64_t nrows, int64_t ncols, int colmajor, int accumulate, int fp32, const double* diag,
+                           int* diag_done, const int* skip, const char* timer) {
     const int W = sqd_window_count(ctx, ncols);
     if (W == 0) return sqd_fail(ctx, SQD_E_LIMIT, "same-spin window does not fit in LDS");
     const bool cap = sqd_capturing(ctx);
@@ -490,10 +545,9 @@ int sqd_same_spin_windowed(sqd_ctx* ctx, sqd_space* sp, spin_tables& col, spin_t
         if ((rc = sqd_alloc(ctx, &sp->win_P, pb, &sp->bytes))) return rc;
         sp->win_P_bytes = pb;
     }
-    prof_scope ps(ctx, timer);
     if (fp32)
         return launch_win<float, kWinRows32>(ctx, sp, col, row, (const float*)X, (float*)Y, nrows, ncols, colmajor,
-                                             accumulate, skip);
+                                             accumulate, nullptr, skip, timer, diag_done);
     return launch_win<double, kWinRows>(ctx, sp, col, row, (const double*)X, (double*)Y, nrows, ncols, colmajor,
-                                          accumulate, skip);
+                                          accumulate, diag, skip, timer, diag_done);
 }
