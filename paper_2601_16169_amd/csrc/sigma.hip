@@ -755,8 +755,9 @@ int sqd_sigma_impl(sqd_ctx* ctx, sqd_space* sp, const double* c, double* sigma, 
         double* Yab = Yt + dim + 64;
         // beta-beta (with the diagonal) writes sigma first, so that its
         // scattered stores need no read of sigma; the alpha-alpha term reads
-        // the columns of C and adds into sigma (row-staged kernel), or comes
-        // back through a coalesced transpose that adds (windowed kernel)
+        // the columns of C and adds into sigma (row-staged kernel with eight
+        // rows, and the windowed kernel through its placing pass), or comes
+        // back through a coalesced transpose that adds
         bool written = false;
         if (mask & SQD_TERM_BB) {
             if ((rc = launch_same_spin<double>(ctx, sp, c, sigma, na, nb, B, A, ctx->jk64, norb, diag, 0, skip,

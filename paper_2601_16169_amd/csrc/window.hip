@@ -13,9 +13,9 @@
 // in every window; interleaving spreads each target's sources evenly over the
 // windows, which keeps the 64-lane slices of every part nearly as tight as
 // the whole table's.  A lane's partial sums go to a scratch row in slot order
-// (coalesced, read back by the same lane in the next window) and the last
-// window writes the target (the caller adds the diagonal in a coalesced
-// pass).  The cross-spin part of the
+// (coalesced, read back by the same lane in the next window); the last
+// window leaves them there too, and a coalesced pass places the targets
+// (adding the diagonal for row-major output).  The cross-spin part of the
 // singles comes from a per-string table wg[pq][s] = sum_{k in s} (pq|kk) of
 // the row spin (global memory) instead of an LDS copy per row, held with the
 // strings fastest so that a lane reads the values of its row block for one
@@ -224,8 +224,8 @@ __global__ void __launch_bounds__(1024) k_same_spin_win(win_args<T> a, const int
             // non-temporal, so that the scratch of all row blocks in flight,
             // larger than the caches, does not evict the table: 2.56e8
             // workload, same box, 28.0 -> 26.6-27.1 ms per same-spin term);
-            // the last window writes the target, or with slot_out its slot
-            // of P as well, for a coalesced pass that places the targets
+            // with slot_out the last window writes P as well, for the
+            // coalesced pass that places the targets; else it writes them
             const int t = a.perm[slot];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -264,6 +264,79 @@ __global__ void __launch_bounds__(256) k_win_unperm(const T* __restrict__ P, int
             if (diag) v += (T)(diag[o] * (double)X[o]);
             if (accumulate) v += Y[o];
             Y[o] = v;
+        }
+    }
+}
+
+// The same with the scratch row staged in LDS first (coalesced reads, each
+// line of P fetched once), for rows of ldp * sizeof(T) bytes up to the LDS
+// size: the gathers straight from P re-fetch lines evicted by the other rows
+// in flight (2.56e8-determinant workload, beta-beta placing pass: FP64 1.76
+// -> 0.74 ms, FP32 1.26 -> 0.35 ms).
+template <typename T>
+__global__ void __launch_bounds__(1024) k_win_unperm_lds(const T* __restrict__ P, int64_t ldp,
+                                                         const int* __restrict__ islot, const T* __restrict__ X,
+                                                         const double* __restrict__ diag, T* __restrict__ Y,
+                                                         int64_t nrows, int64_t ncols, int accumulate,
+                                                         const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    T* ps = reinterpret_cast<T*>(lds_raw);
+    constexpr int kB = 8;
+    const int64_t step = (int64_t)blockDim.x * kB;
+    for (int64_t row = blockIdx.x; row < nrows; row += gridDim.x) {
+        const T* prow = P + row * ldp;
+        __syncthreads();   // the previous row's reads of ps are done
+        for (int64_t q0 = threadIdx.x; q0 < ldp; q0 += step) {
+            T v[kB];
+#pragma unroll
+            for (int u = 0; u < kB; ++u) {
+                const int64_t q = q0 + (int64_t)u * blockDim.x;
+                v[u] = q < ldp ? __builtin_nontemporal_load(prow + q) : (T)0;
+            }
+#pragma unroll
+            for (int u = 0; u < kB; ++u) {
+                const int64_t q = q0 + (int64_t)u * blockDim.x;
+                if (q < ldp) ps[q] = v[u];
+            }
+        }
+        __syncthreads();
+        for (int64_t t = threadIdx.x; t < ncols; t += blockDim.x) {
+            const int64_t o = row * ncols + t;
+            T v = ps[islot[t]];
+            if (diag) v += (T)(diag[o] * (double)X[o]);
+            if (accumulate) v += Y[o];
+            Y[o] = v;
+        }
+    }
+}
+
+// Column-major output (Y[t * nrows + row]) from the slot-ordered sums in P:
+// 64 x 64 tiles of (rows, slots) through LDS, each target's 64 rows read
+// and written as 64 contiguous values.  The last window's adds into 64-byte
+// pieces of scattered targets cost more (2.56e8-determinant workload,
+// alpha-alpha term adding into sigma: FP64 24.1 ms against 19.2 + 1.9 ms,
+// FP32 14.4 against 10.2 + 0.9 ms).
+template <typename T>
+__global__ void __launch_bounds__(256) k_win_unperm_t(const T* __restrict__ P, int64_t ldp, const int* __restrict__ perm,
+                                                      T* __restrict__ Y, int64_t nrows, int64_t ncols, int accumulate,
+                                                      const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    __shared__ T tile[64][65];
+    const int64_t s0 = (int64_t)blockIdx.x * 64, r0 = (int64_t)blockIdx.y * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int i = ty; i < 64; i += 4) {
+        const int64_t r = r0 + i;
+        tile[i][tx] = r < nrows ? P[r * ldp + s0 + tx] : (T)0;
+    }
+    __syncthreads();
+    const int64_t r = r0 + tx;
+    for (int j = ty; j < 64; j += 4) {
+        const int t = perm[s0 + j];
+        if (t < ncols && r < nrows) {
+            const int64_t o = (int64_t)t * nrows + r;
+            const T v = tile[tx][j];
+            Y[o] = accumulate ? Y[o] + v : v;
         }
     }
 }
@@ -447,9 +520,9 @@ int launch_win(sqd_ctx* ctx, sqd_space* sp, spin_tables& col, spin_tables& row, 
     const T* wg;
     if constexpr (sizeof(T) == 8) { sv = (const T*)col.win_s_v64; dv = (const T*)col.win_d_v64; wg = (const T*)row.wg64; }
     else { sv = (const T*)col.win_s_v32; dv = (const T*)col.win_d_v32; wg = (const T*)row.wg32; }
-    // row-major output goes through P in slot order (P exists when W > 1);
-    // column-major output stores 64 contiguous bytes per lane directly
-    const int slot_out = (!colmajor && col.win_W > 1) ? 1 : 0;
+    // the output goes through P in slot order (P exists when W > 1) and a
+    // coalesced pass places it
+    const int slot_out = col.win_W > 1 ? 1 : 0;
     win_args<T> a{X, Y, (T*)sp->win_P, nrows, ncols, col.win_W, col.win_width, col.nslices, col.perm_ss,
                   col.win_s_off, col.win_d_off, col.win_s_pk, sv, col.win_d_nbr, dv, wg, sqd_wtable_ld(row.n),
                   sp->norb, colmajor, accumulate, slot_out};
@@ -459,12 +532,27 @@ int launch_win(sqd_ctx* ctx, sqd_space* sp, spin_tables& col, spin_tables& row, 
         prof_scope ps(ctx, timer);
         hipLaunchKernelGGL((k_same_spin_win<T, R>), dim3(nblk(nrows, R)), dim3(1024), lds, ctx->stream, a, skip);
     }
-    if (slot_out) {
+    if (slot_out && colmajor) {
+        prof_scope pu(ctx, "k_win_unperm");
+        const dim3 tg((unsigned)col.nslices, nblk(nrows, 64));
+        hipLaunchKernelGGL((k_win_unperm_t<T>), tg, dim3(256), 0, ctx->stream, (const T*)sp->win_P,
+                           (int64_t)col.nslices * 64, col.perm_ss, Y, nrows, ncols, accumulate, skip);
+    } else if (slot_out) {
         const double* dg = sizeof(T) == 8 ? diag : nullptr;
         prof_scope pu(ctx, "k_win_unperm");
-        const unsigned g = (unsigned)std::min<int64_t>(nrows, 1 << 20);
-        hipLaunchKernelGGL((k_win_unperm<T>), dim3(g), dim3(256), 0, ctx->stream, (const T*)sp->win_P,
-                           (int64_t)col.nslices * 64, col.win_islot, X, dg, Y, nrows, ncols, accumulate, skip);
+        const int64_t ldp = (int64_t)col.nslices * 64;
+        const size_t rb = (size_t)ldp * sizeof(T);
+        if (rb <= (size_t)ctx->max_lds) {
+            set_lds_attr(k_win_unperm_lds<T>, (int)rb);
+            const int per_cu = std::max<int>(1, (int)((size_t)ctx->max_lds / rb));
+            const unsigned g = (unsigned)std::min<int64_t>(nrows, (int64_t)ctx->num_cu * per_cu);
+            hipLaunchKernelGGL((k_win_unperm_lds<T>), dim3(g), dim3(1024), rb, ctx->stream, (const T*)sp->win_P, ldp,
+                               col.win_islot, X, dg, Y, nrows, ncols, accumulate, skip);
+        } else {
+            const unsigned g = (unsigned)std::min<int64_t>(nrows, 1 << 20);
+            hipLaunchKernelGGL((k_win_unperm<T>), dim3(g), dim3(256), 0, ctx->stream, (const T*)sp->win_P, ldp,
+                               col.win_islot, X, dg, Y, nrows, ncols, accumulate, skip);
+        }
         if (dg && diag_done) *diag_done = 1;
     }
     SQD_HIP(ctx, hipGetLastError());
