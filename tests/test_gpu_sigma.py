@@ -173,6 +173,50 @@ def test_sigma_graph_capture_replays(precision, ab_variant):
         gctx.close()
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_sigma_graph_capture_windowed(precision):
+    """The windowed same-spin kernel (forced, 64-string windows: 2 windows
+    of beta sources, 4 of alpha sources) with its slot-order scratch and the
+    placing passes (row-major with the diagonal, column-major adding into
+    sigma) captured in a HIP graph: every replay equals the eager product,
+    with eager products of another vector between the replays, and the eager
+    product matches the oracle."""
+    torch = need_gpu()
+    from paper_2601_16169_amd import sqd
+    banner(f"sigma graph capture windowed precision {precision}")
+    stream = torch.cuda.Stream()
+    gctx = sqd.Context(0, stream)
+    gctx.set_tuning(sqd.TUNE_SS_WINDOW, 64)
+    try:
+        p = I.small_problem(10, 4, 3, 210, 120, 4)
+        sp = _space(gctx, p)
+        with torch.cuda.stream(stream):
+            c = torch.tensor(I.random_vector(sp.dim, 25), device="cuda:0")
+            c2 = torch.tensor(I.random_vector(sp.dim, 26), device="cuda:0")
+            out = torch.empty_like(c)
+            other = torch.empty_like(c)
+            eager = sp.sigma(c, precision=precision).clone()
+            sp.sigma(c, out, precision=precision)
+        stream.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=stream):
+            sp.sigma(c, out, precision=precision)
+        for rep in range(4):
+            out.fill_(float("nan"))
+            graph.replay()
+            stream.synchronize()
+            assert torch.equal(out, eager), f"replay {rep} differs"
+            with torch.cuda.stream(stream):
+                sp.sigma(c2, other, precision=precision)
+                sp.sigma(c2, other, precision=0)
+            stream.synchronize()
+        o = core.Space.from_problem(p).sigma(I.random_vector(sp.dim, 25))
+        assert max(rel_err(eager.cpu().numpy(), o)) <= (1e-12 if precision == 0 else 2e-6)
+        sp.close()
+    finally:
+        gctx.close()
+
+
 def test_sigma_capture_without_warmup_is_refused():
     """Under stream capture sqd_sigma allocates nothing: on a space whose
     product has never run eagerly it returns SQD_E_STATE."""
