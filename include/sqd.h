@@ -295,7 +295,7 @@ int sqd_sigma(sqd_ctx* ctx, const sqd_space* space, const double* c_dev,
  * source row of C plus one norb^2 integral row must fit in one workgroup's LDS
  * (as for SQD_TUNE_AB_VARIANT 2); beyond either SQD_E_LIMIT, before anything
  * is enqueued.  Where a same-spin term takes the windowed kernel (rows too
- * long to stage two whole in LDS), its tables are built by the space's first
+ * long to stage four whole in LDS), its tables are built by the space's first
  * sqd_sigma call with that term and precision; until then SQD_E_STATE, before
  * anything is enqueued.  After a Hamiltonian change the first call refreshes the
  * space's values in place (kernels and a synchronisation; under capture it

@@ -689,7 +689,7 @@ bool sqd_sigma_prepared(sqd_ctx* ctx, const sqd_space* sp, int precision, unsign
 
 // True when the arrays that a space's first product builds exist for a
 // product with these arguments: the diagonal, and for same-spin rows too long
-// to stage two whole the windowed tables of the column spin, the cross-spin
+// to stage four whole the windowed tables of the column spin, the cross-spin
 // table of the row spin and the partial-sum scratch.  (Their values may still
 // be stale: those are refreshed in place.)
 bool sqd_space_built_for(sqd_ctx* ctx, const sqd_space* sp, int precision, unsigned mask) {
